@@ -1,0 +1,190 @@
+/*
+ * ahom -- generalized Basic Scheme of FFT-based homogenization on lattice
+ * patterns P(M), native to AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Every call returns an int status
+ * (AHOM_OK = 0, a positive warning, or a negative error); no exception or
+ * abort crosses this boundary.  ahom_last_error() gives a thread-local text
+ * for the last failure.  Handles are created and destroyed explicitly by
+ * the caller; one handle must not be used from two threads at once,
+ * separate handles may.
+ *
+ * Conventions shared by all calls
+ *  - d is 2 or 3.  Matrices are row-major.
+ *  - Pattern points and frequencies are always in the library's canonical
+ *    Smith-normal-form order (lexicographic in lambda, resp. kappa, slowest
+ *    axis first, over the axes with e_j > 1).  ahom_pattern_points /
+ *    ahom_pattern_freqs give the exact coordinates of that order.
+ *  - Strain/stress tensors: plain tensor components (no sqrt(2), no
+ *    engineering shear).  A full 3x3 symmetric tensor is passed as 9 doubles
+ *    row-major; in 2-D its upper-left 2x2 block is used.
+ *  - Field components: 3-D (11,22,33,23,13,12), 2-D (11,22,12).
+ *  - mem_flags = AHOM_MEM_HOST (default): host arrays, copied before the call
+ *    returns.  AHOM_MEM_DEVICE: the *field* arrays (phase ids, per-point
+ *    stiffness, init, strain_out, dft in/out) are device pointers used on the
+ *    solver's stream; the caller keeps them alive until that stream has been
+ *    synchronized.  Small arrays (eps_bar, iters, resid, mean_stress, Ceff,
+ *    lame table) are always host memory.
+ */
+#ifndef AHOM_H
+#define AHOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define AHOM_OK                  0
+#define AHOM_W_NOT_CONVERGED     1   /* max_iter reached; outputs hold iterate max_iter */
+#define AHOM_E_ARG              -1   /* invalid argument (null pointer, bad d, bad size) */
+#define AHOM_E_SINGULAR         -2   /* det M = 0 */
+#define AHOM_E_OVERFLOW         -3   /* |det M| > 2^31 or int64 overflow in the Smith form */
+#define AHOM_E_UNSUPPORTED_SIZE -4   /* an elementary divisor has a prime factor > 7 */
+#define AHOM_E_MATERIAL         -5   /* mu <= 0 or 3 lambda + 2 mu <= 0, or no material set */
+#define AHOM_E_DIVERGED         -6   /* residual NaN/Inf or grew beyond 1e3 times its start */
+#define AHOM_E_DEVICE           -7   /* HIP runtime error, or no GPU */
+#define AHOM_E_NOMEM            -8   /* device allocation failed */
+
+/* precision modes */
+#define AHOM_FP64               0    /* every stage in double precision */
+#define AHOM_FP32_MIXED         1    /* FFT, Gamma0 and local law in float; residual,
+                                        averages and twiddle generation in double */
+
+/* memory flags */
+#define AHOM_MEM_HOST           0
+#define AHOM_MEM_DEVICE         1
+
+/* treatment of unpaired boundary frequencies */
+#define AHOM_NYQUIST_HERMITIAN  0
+
+typedef struct ahom_pattern ahom_pattern;
+typedef struct ahom_solver ahom_solver;
+
+typedef struct ahom_config {
+    int precision;      /* AHOM_FP64 or AHOM_FP32_MIXED */
+    double tol;         /* stop when the equilibrium residual r(n) <= tol */
+    int max_iter;       /* upper bound on the number of updates */
+    int check_period;   /* iterations enqueued between host-side status reads (>= 1) */
+    int nyquist;        /* AHOM_NYQUIST_HERMITIAN */
+    void* stream;       /* hipStream_t to run on; NULL = the null stream */
+} ahom_config;
+
+/* Library version, (major << 16) | (minor << 8) | patch. */
+int ahom_version(void);
+
+/* Text of the last failure on this thread ("" if none).  Owned by the library. */
+const char* ahom_last_error(void);
+
+/*
+ * Pattern P(M) of a regular integer matrix M (Sec. 2.1) and its Smith normal
+ * form M = Q E R, Q and R unimodular, E = diag(e_1..e_d), e_j | e_{j+1}
+ * (Sec. 2.2).  M: d*d int64, row-major, host memory, copied.
+ * Errors: AHOM_E_ARG (d not 2 or 3, null), AHOM_E_SINGULAR, AHOM_E_OVERFLOW,
+ * AHOM_E_UNSUPPORTED_SIZE.  Host-only: needs no GPU.
+ */
+int ahom_pattern_create(int d, const int64_t* M, ahom_pattern** out);
+void ahom_pattern_destroy(ahom_pattern* p);
+
+/*
+ * m = |det M|, dM = #{j : e_j > 1} (pattern dimension, Sec. 2.2), e[0..d-1],
+ * Q and R (d*d row-major).  E is unique; Q and R are the library's
+ * deterministic choice.  Any output pointer may be NULL.
+ */
+int ahom_pattern_info(const ahom_pattern* p, int64_t* m, int* dM, int64_t* e, int64_t* Q, int64_t* R);
+
+/*
+ * Canonical point order: num[i*d + j] = m * y_j of point i, exact, with
+ * y in [-1/2, 1/2)^d (Sec. 2.1).  num: m*d int64, host memory.
+ */
+int ahom_pattern_points(const ahom_pattern* p, int64_t* num);
+
+/*
+ * Canonical frequency order: h[i*d + j], h in G(M^T) = M^T [-1/2,1/2)^d
+ * intersected with Z^d (Sec. 2.1), exact.  h: m*d int64, host memory.
+ */
+int ahom_pattern_freqs(const ahom_pattern* p, int64_t* h);
+
+/*
+ * Bare pattern DFT (eq. Fouriermatrix, Sec. 2.2) on the GPU, computed as the
+ * d_M-dimensional FFT over the Smith-form axes.  sign = -1: forward,
+ * out_h = (1/m) sum_y in_y exp(-2 pi i h^T y); sign = +1: inverse,
+ * out_y = sum_h in_h exp(+2 pi i h^T y).  in/out: m interleaved complex
+ * values (re, im) in canonical point (forward input) / frequency order,
+ * double when prec = AHOM_FP64, float when AHOM_FP32_MIXED.  in and out may
+ * not alias.  stream: hipStream_t or NULL.
+ */
+int ahom_dft(const ahom_pattern* p, int sign, int prec, const void* in, void* out, int mem_flags, void* stream);
+
+/*
+ * Solver for Algorithm 1 (Sec. 3.2) on the pattern p (which must outlive
+ * the solver).  Allocates device buffers.  Errors: AHOM_E_ARG, AHOM_E_DEVICE,
+ * AHOM_E_NOMEM.
+ */
+int ahom_solver_create(const ahom_pattern* p, const ahom_config* cfg, ahom_solver** out);
+void ahom_solver_destroy(ahom_solver* s);
+
+/*
+ * Piecewise-constant isotropic stiffness (Sec. 3.1): lame[2*k], lame[2*k+1]
+ * = (lambda, mu) of phase k (host memory); phase[i] in [0, n_phase) is the
+ * phase of canonical point i (m bytes).  n_phase <= 256.
+ * Errors: AHOM_E_MATERIAL (mu <= 0 or 3 lambda + 2 mu <= 0), AHOM_E_ARG.
+ */
+int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags);
+
+/*
+ * Per-point isotropic stiffness: lame_pts[2*i], lame_pts[2*i+1] = (lambda,
+ * mu) at canonical point i (m*2 doubles).  Replaces any phase table.
+ */
+int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int mem_flags);
+
+/*
+ * Reference medium C0 (isotropic Lame pair).  If never called, the mean of
+ * the extreme values over the material (phase table or field) is used.
+ * Errors: AHOM_E_MATERIAL for mu0 <= 0 or lambda0 + 2 mu0 <= 0.
+ */
+int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0);
+
+/*
+ * Algorithm 1 for n_load macroscopic strains at once (one batched launch per
+ * pass).  eps_bar: n_load*9 (host).  init: NULL, or n_load*c*m doubles, the
+ * fluctuation added to eps_bar in eps(0) (c = 6 in 3-D, 3 in 2-D,
+ * component-major per load, canonical point order).  strain_out: NULL, or
+ * n_load*c*m doubles receiving eps(n_k) per load.  iters[k]: n_k = number of
+ * updates performed for load k; resid[k] = r(n_k), the equilibrium
+ * residual sqrt(sum_{h active, h != 0} |sigma_hat_h xi_h|^2) / |<sigma>|_F;
+ * mean_stress: n_load*9, <sigma(n_k)> (Def. 3.1: C_eff : eps_bar).
+ * Any of iters, resid, mean_stress may be NULL.
+ * Returns AHOM_OK if every load converged, AHOM_W_NOT_CONVERGED if some load
+ * reached max_iter (outputs hold that iterate), AHOM_E_DIVERGED if some
+ * load diverged, or an error.
+ */
+int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* init, void* strain_out,
+               int* iters, double* resid, double* mean_stress, int mem_flags);
+
+/*
+ * Effective stiffness in Mandel form (c x c row-major, c = 6 or 3): runs the
+ * c Mandel unit loads as one batched solve; column k is Mandel(<sigma>) of
+ * load k.  iters: NULL or c ints.  Same return codes as ahom_solve.
+ */
+int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters);
+
+/*
+ * Device timing of the last ahom_solve on this solver: total milliseconds
+ * between the first kernel and convergence detection (HIP events on the
+ * solver's stream), and the number of iterations enqueued.
+ */
+int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* iterations_enqueued);
+
+/*
+ * Per-iteration residual history r(0..n) of load k of the last solve:
+ * writes up to cap doubles, *count = number written.
+ */
+int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AHOM_H */

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of libahom (argument marshalling only).
+
+Every step of the computation runs in the HIP library; this module only
+converts Python/numpy/torch arguments to pointers and sizes.  Importing it
+fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libahom.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"libahom.so not built at {_LIB_PATH}; run __graft_entry__.build()")
+_lib = ct.CDLL(_LIB_PATH)
+
+AHOM_OK = 0
+AHOM_W_NOT_CONVERGED = 1
+AHOM_E_ARG = -1
+AHOM_E_SINGULAR = -2
+AHOM_E_OVERFLOW = -3
+AHOM_E_UNSUPPORTED_SIZE = -4
+AHOM_E_MATERIAL = -5
+AHOM_E_DIVERGED = -6
+AHOM_E_DEVICE = -7
+AHOM_E_NOMEM = -8
+FP64 = 0
+FP32_MIXED = 1
+MEM_HOST = 0
+MEM_DEVICE = 1
+NYQUIST_HERMITIAN = 0
+
+EXPORTS = [
+    "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_destroy", "ahom_pattern_info",
+    "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
+    "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
+    "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_history",
+]
+
+
+class Config(ct.Structure):
+    _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
+                ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p)]
+
+
+_P = ct.c_void_p
+_i64p = ct.POINTER(ct.c_int64)
+_dp = ct.POINTER(ct.c_double)
+_ip = ct.POINTER(ct.c_int)
+
+_lib.ahom_version.restype = ct.c_int
+_lib.ahom_last_error.restype = ct.c_char_p
+_lib.ahom_pattern_create.argtypes = [ct.c_int, _i64p, ct.POINTER(_P)]
+_lib.ahom_pattern_destroy.argtypes = [_P]
+_lib.ahom_pattern_destroy.restype = None
+_lib.ahom_pattern_info.argtypes = [_P, _i64p, _ip, _i64p, _i64p, _i64p]
+_lib.ahom_pattern_points.argtypes = [_P, _i64p]
+_lib.ahom_pattern_freqs.argtypes = [_P, _i64p]
+_lib.ahom_dft.argtypes = [_P, ct.c_int, ct.c_int, _P, _P, ct.c_int, _P]
+_lib.ahom_solver_create.argtypes = [_P, ct.POINTER(Config), ct.POINTER(_P)]
+_lib.ahom_solver_destroy.argtypes = [_P]
+_lib.ahom_solver_destroy.restype = None
+_lib.ahom_solver_set_material.argtypes = [_P, ct.c_int, _dp, _P, ct.c_int]
+_lib.ahom_solver_set_stiffness_field.argtypes = [_P, _P, ct.c_int]
+_lib.ahom_solver_set_reference.argtypes = [_P, ct.c_double, ct.c_double]
+_lib.ahom_solve.argtypes = [_P, ct.c_int, _dp, _P, _P, _ip, _dp, _dp, ct.c_int]
+_lib.ahom_effective_stiffness.argtypes = [_P, _dp, _ip]
+_lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
+_lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
+
+
+class AhomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ahom error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc, allow=(AHOM_OK,)):
+    if rc not in allow:
+        raise AhomError(rc, _lib.ahom_last_error().decode())
+    return rc
+
+
+def version():
+    return _lib.ahom_version()
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+class Pattern:
+    """P(M) with the library's Smith-normal-form addressing (host only)."""
+
+    def __init__(self, M):
+        M = np.ascontiguousarray(np.asarray(M, dtype=np.int64))
+        if M.ndim != 2 or M.shape[0] != M.shape[1]:
+            raise ValueError("M must be square")
+        self.d = M.shape[0]
+        self.M = M
+        h = _P()
+        _check(_lib.ahom_pattern_create(self.d, _ptr(M, ct.c_int64), ct.byref(h)))
+        self._h = h
+        m = ct.c_int64()
+        dM = ct.c_int()
+        e = np.zeros(self.d, np.int64)
+        Q = np.zeros(self.d * self.d, np.int64)
+        R = np.zeros(self.d * self.d, np.int64)
+        _check(_lib.ahom_pattern_info(h, ct.byref(m), ct.byref(dM), _ptr(e, ct.c_int64), _ptr(Q, ct.c_int64), _ptr(R, ct.c_int64)))
+        self.m, self.dM, self.e = int(m.value), int(dM.value), e
+        self.Q, self.R = Q.reshape(self.d, self.d), R.reshape(self.d, self.d)
+
+    def points(self):
+        out = np.zeros((self.m, self.d), np.int64)
+        _check(_lib.ahom_pattern_points(self._h, _ptr(out, ct.c_int64)))
+        return out
+
+    def freqs(self):
+        out = np.zeros((self.m, self.d), np.int64)
+        _check(_lib.ahom_pattern_freqs(self._h, _ptr(out, ct.c_int64)))
+        return out
+
+    def dft(self, a, sign=-1, precision=FP64, stream=None):
+        """Pattern DFT of m complex values (numpy: host path; torch cuda: device path)."""
+        if _is_torch(a):
+            import torch
+            out = torch.empty_like(a)
+            s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+            _check(_lib.ahom_dft(self._h, sign, precision, a.data_ptr(), out.data_ptr(), MEM_DEVICE, s))
+            return out
+        dt = np.complex128 if precision == FP64 else np.complex64
+        a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+        if a.size != self.m:
+            raise ValueError("need m values")
+        out = np.empty_like(a)
+        _check(_lib.ahom_dft(self._h, sign, precision, a.ctypes.data, out.ctypes.data, MEM_HOST, None))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.ahom_pattern_destroy(self._h)
+            self._h = None
+
+
+class Solver:
+    """Algorithm 1 on a pattern (device buffers owned by the library)."""
+
+    def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None):
+        self.pattern = pattern
+        self.ncomp = 6 if pattern.d == 3 else 3
+        self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream)
+        h = _P()
+        _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
+        self._h = h
+
+    def set_material(self, lame, phase):
+        lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        if _is_torch(phase):
+            _check(_lib.ahom_solver_set_material(self._h, lame.shape[0], _ptr(lame, ct.c_double), phase.data_ptr(), MEM_DEVICE))
+        else:
+            ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
+            _check(_lib.ahom_solver_set_material(self._h, lame.shape[0], _ptr(lame, ct.c_double), ph.ctypes.data, MEM_HOST))
+
+    def set_stiffness_field(self, lame_pts):
+        lp = np.ascontiguousarray(np.asarray(lame_pts, dtype=np.float64).reshape(-1, 2))
+        _check(_lib.ahom_solver_set_stiffness_field(self._h, lp.ctypes.data, MEM_HOST))
+
+    def set_reference(self, lam0, mu0):
+        _check(_lib.ahom_solver_set_reference(self._h, float(lam0), float(mu0)))
+
+    def solve(self, eps_bar, init=None, want_strain=False, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        """eps_bar: (n_load, 3, 3).  Returns dict(status, iters, resid, mean_stress, strain)."""
+        eb = np.ascontiguousarray(np.asarray(eps_bar, dtype=np.float64).reshape(-1, 9))
+        n = eb.shape[0]
+        iters = np.zeros(n, np.int32)
+        resid = np.zeros(n, np.float64)
+        mean = np.zeros((n, 9), np.float64)
+        strain = np.empty((n, self.ncomp, self.pattern.m), np.float64) if want_strain else None
+        init_arr = None
+        if init is not None:
+            init_arr = np.ascontiguousarray(np.asarray(init, dtype=np.float64).reshape(n, self.ncomp, self.pattern.m))
+        rc = _lib.ahom_solve(self._h, n, _ptr(eb, ct.c_double),
+                             init_arr.ctypes.data if init_arr is not None else None,
+                             strain.ctypes.data if strain is not None else None,
+                             _ptr(iters, ct.c_int), _ptr(resid, ct.c_double), _ptr(mean, ct.c_double), MEM_HOST)
+        _check(rc, allow)
+        return dict(status=rc, iters=iters, resid=resid, mean_stress=mean.reshape(n, 3, 3), strain=strain)
+
+    def solve_device(self, eps_bar, strain_out=None, init=None, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        """Like solve() with device-resident field arrays (torch cuda tensors, float64)."""
+        eb = np.ascontiguousarray(np.asarray(eps_bar, dtype=np.float64).reshape(-1, 9))
+        n = eb.shape[0]
+        iters = np.zeros(n, np.int32)
+        resid = np.zeros(n, np.float64)
+        mean = np.zeros((n, 9), np.float64)
+        rc = _lib.ahom_solve(self._h, n, _ptr(eb, ct.c_double),
+                             init.data_ptr() if init is not None else None,
+                             strain_out.data_ptr() if strain_out is not None else None,
+                             _ptr(iters, ct.c_int), _ptr(resid, ct.c_double), _ptr(mean, ct.c_double), MEM_DEVICE)
+        _check(rc, allow)
+        return dict(status=rc, iters=iters, resid=resid, mean_stress=mean.reshape(n, 3, 3))
+
+    def effective_stiffness(self, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        k = self.ncomp
+        C = np.zeros(k * k, np.float64)
+        iters = np.zeros(k, np.int32)
+        rc = _lib.ahom_effective_stiffness(self._h, _ptr(C, ct.c_double), _ptr(iters, ct.c_int))
+        _check(rc, allow)
+        return C.reshape(k, k), iters
+
+    def last_timing(self):
+        ms = ct.c_double()
+        enq = ct.c_int()
+        _check(_lib.ahom_solver_last_timing(self._h, ct.byref(ms), ct.byref(enq)))
+        return ms.value, enq.value
+
+    def history(self, load=0, cap=100000):
+        out = np.zeros(cap, np.float64)
+        cnt = ct.c_int()
+        _check(_lib.ahom_solver_history(self._h, load, _ptr(out, ct.c_double), cap, ct.byref(cnt)))
+        return out[:cnt.value]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.ahom_solver_destroy(self._h)
+            self._h = None

@@ -1,0 +1,627 @@
+// C ABI of libahom: patterns (host-only), the bare pattern DFT and the
+// Algorithm 1 solver (device).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ahom.h"
+#include "ahom_internal.h"
+#include "ahom_kernels.h"
+
+namespace {
+thread_local std::string g_err;
+
+constexpr int kLmax = 256;          // longest transform held by one pass
+constexpr size_t kLdsCap = 150 * 1024;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(AHOM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// field index (11,22,33,23,13,12) / (11,22,12) -> position in a 3x3 row-major tensor
+const int kComp3[6] = {0, 4, 8, 5, 2, 1};
+const int kComp2[3] = {0, 4, 1};
+}  // namespace
+
+void ahom_set_error(const std::string& msg) { g_err = msg; }
+
+struct DeviceTables {
+    int device = -1;
+    Plan* plan = nullptr;
+    double2* tw64 = nullptr;
+    float2* tw32 = nullptr;
+};
+
+struct ahom_pattern {
+    SmithForm sf;
+    Plan plan;
+    std::vector<double> tw;
+    DeviceTables dev;
+
+    int ensure_device() {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (dev.plan && dev.device == cur) return AHOM_OK;
+        if (dev.plan) return fail(AHOM_E_DEVICE, "pattern used on a second device");
+        HIPCHK(hipMalloc((void**)&dev.plan, sizeof(Plan)));
+        HIPCHK(hipMemcpy(dev.plan, &plan, sizeof(Plan), hipMemcpyHostToDevice));
+        const size_t n = tw.size() / 2;
+        HIPCHK(hipMalloc((void**)&dev.tw64, std::max<size_t>(n, 1) * sizeof(double2)));
+        HIPCHK(hipMalloc((void**)&dev.tw32, std::max<size_t>(n, 1) * sizeof(float2)));
+        std::vector<float> t32(tw.size());
+        for (size_t i = 0; i < tw.size(); ++i) t32[i] = (float)tw[i];
+        if (n) {
+            HIPCHK(hipMemcpy(dev.tw64, tw.data(), n * sizeof(double2), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dev.tw32, t32.data(), n * sizeof(float2), hipMemcpyHostToDevice));
+        }
+        dev.device = cur;
+        return AHOM_OK;
+    }
+
+    ~ahom_pattern() {
+        dfree(dev.plan);
+        dfree(dev.tw64);
+        dfree(dev.tw32);
+    }
+};
+
+namespace {
+
+struct PassGeom {
+    int NC = 1, CS = 1, nwg = 1;
+    size_t lds = 0;
+};
+
+// Choose columns per workgroup for a pass over columns of length L.
+int choose_geom(int L, int64_t ncols, int nbuf, size_t extra, size_t es, int prec, PassGeom* g) {
+    const int target = prec == AHOM_FP64 ? 1024 : 2048;
+    int NC = std::max(1, target / L);
+    if (ncols < NC) NC = (int)std::max<int64_t>(1, ncols);
+    const int CS = L + 1;
+    while (NC > 1 && (size_t)nbuf * NC * CS * es + extra > kLdsCap) NC /= 2;
+    size_t lds = (size_t)nbuf * NC * CS * es + extra;
+    if (lds > 160 * 1024) return fail(AHOM_E_UNSUPPORTED_SIZE, "transform length too long for one LDS tile");
+    g->NC = NC;
+    g->CS = CS;
+    g->lds = lds;
+    g->nwg = (int)((ncols + NC - 1) / NC);
+    return AHOM_OK;
+}
+
+}  // namespace
+
+struct ahom_solver {
+    ahom_pattern* pat = nullptr;
+    ahom_config cfg{};
+    int prec = 0, dim = 3, ncomp = 6, npack = 3, nt = 3;
+    hipStream_t stream = nullptr;
+    // material
+    bool has_material = false, ref_set = false;
+    int n_phase = 0;
+    double lam0 = 0, mu0 = 0;
+    double lam_lo = 0, lam_hi = 0, mu_lo = 0, mu_hi = 0;
+    uint8_t* d_phase = nullptr;
+    double* d_lame_tab = nullptr;
+    double* d_lame_pts = nullptr;
+    // buffers
+    int cap = 0;
+    void* d_buf0 = nullptr;
+    void* d_buf1 = nullptr;
+    void* d_tbuf = nullptr;
+    LoadState* d_st = nullptr;
+    LoadState* h_st = nullptr;
+    double* d_sig = nullptr;
+    double* d_res = nullptr;
+    double* d_hist = nullptr;
+    double* d_epsbar = nullptr;
+    double* d_real = nullptr;
+    int hist_cap = 0;
+    // geometry
+    PassGeom g_real, g_spec, g_axis[AHOM_MAX_AXES];
+    // timing
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0;
+    int last_enqueued = 0;
+    int last_nload = 0;
+
+    size_t es() const { return prec == AHOM_FP64 ? 16 : 8; }
+
+    int release_buffers() {
+        dfree(d_buf0); dfree(d_buf1); dfree(d_tbuf); dfree(d_st); dfree(d_sig);
+        dfree(d_res); dfree(d_hist); dfree(d_epsbar); dfree(d_real);
+        if (h_st) (void)hipHostFree(h_st);
+        h_st = nullptr;
+        cap = 0;
+        return AHOM_OK;
+    }
+
+    int ensure_capacity(int nload) {
+        if (nload <= cap) return AHOM_OK;
+        release_buffers();
+        const Plan& P = pat->plan;
+        const size_t fb = (size_t)nload * ncomp * P.S * es();
+        HIPCHK(hipMalloc(&d_buf0, fb));
+        HIPCHK(hipMalloc(&d_buf1, fb));
+        HIPCHK(hipMalloc(&d_tbuf, (size_t)nload * nt * P.S * es()));
+        HIPCHK(hipMalloc((void**)&d_st, nload * sizeof(LoadState)));
+        HIPCHK(hipHostMalloc((void**)&h_st, nload * sizeof(LoadState), hipHostMallocDefault));
+        HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * g_real.nwg * ncomp * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * g_spec.nwg * sizeof(double)));
+        hist_cap = cfg.max_iter + 1;
+        HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_real, (size_t)nload * ncomp * P.m * sizeof(double)));
+        cap = nload;
+        return AHOM_OK;
+    }
+
+    ~ahom_solver() {
+        release_buffers();
+        dfree(d_phase); dfree(d_lame_tab); dfree(d_lame_pts);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+
+    RealArgs real_args(int mode) const {
+        RealArgs a{};
+        a.plan = pat->dev.plan;
+        a.buf0 = d_buf0;
+        a.buf1 = d_buf1;
+        a.tw = prec == AHOM_FP64 ? (const void*)pat->dev.tw64 : (const void*)pat->dev.tw32;
+        a.tw64 = pat->dev.tw64;
+        a.st = d_st;
+        a.phase = d_phase;
+        a.lame_tab = d_lame_tab;
+        a.lame_pts = d_lame_pts;
+        a.lam0 = lam0;
+        a.mu0 = mu0;
+        a.sig_part = d_sig;
+        a.real_io = d_real;
+        a.eps_bar = d_epsbar;
+        a.NC = g_real.NC;
+        a.CS = g_real.CS;
+        (void)mode;
+        return a;
+    }
+
+    AxisArgs axis_args(int axis) const {
+        AxisArgs a{};
+        a.plan = pat->dev.plan;
+        a.buf0 = d_buf0;
+        a.buf1 = d_buf1;
+        a.tw = prec == AHOM_FP64 ? (const void*)pat->dev.tw64 : (const void*)pat->dev.tw32;
+        a.tw64 = pat->dev.tw64;
+        a.st = d_st;
+        a.load_stride = (int64_t)ncomp * pat->plan.S;
+        a.field_stride = pat->plan.S;
+        a.axis = axis;
+        a.slen0_full = 0;
+        a.NC = g_axis[axis].NC;
+        a.CS = g_axis[axis].CS;
+        return a;
+    }
+
+    SpecArgs spec_args() const {
+        SpecArgs a{};
+        a.plan = pat->dev.plan;
+        a.buf0 = d_buf0;
+        a.buf1 = d_buf1;
+        a.tbuf = d_tbuf;
+        a.tw = prec == AHOM_FP64 ? (const void*)pat->dev.tw64 : (const void*)pat->dev.tw32;
+        a.st = d_st;
+        a.eps_bar = d_epsbar;
+        a.mu0 = mu0;
+        a.beta = (lam0 + mu0) / (lam0 + 2.0 * mu0);
+        a.res_part = d_res;
+        a.NC = g_spec.NC;
+        a.CS = g_spec.CS;
+        return a;
+    }
+
+    int enqueue_iteration(int nload) {
+        const Plan& P = pat->plan;
+        hipStream_t s = stream;
+        if (ahom_launch_real(prec, dim, REAL_TURN, real_args(REAL_TURN), g_real.nwg, nload, g_real.lds, s))
+            return fail(AHOM_E_DEVICE, "launch k_real failed");
+        for (int a = 1; a <= P.D - 2; ++a)
+            if (ahom_launch_axis(prec, -1, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s))
+                return fail(AHOM_E_DEVICE, "launch k_axis failed");
+        if (ahom_launch_spec(prec, dim, spec_args(), g_spec.nwg, nload, g_spec.lds, s))
+            return fail(AHOM_E_DEVICE, "launch k_spec failed");
+        for (int a = P.D - 2; a >= 1; --a)
+            if (ahom_launch_axis(prec, +1, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s))
+                return fail(AHOM_E_DEVICE, "launch k_axis failed");
+        ReduceArgs r{};
+        r.st = d_st;
+        r.sig_part = d_sig;
+        r.res_part = d_res;
+        r.hist = d_hist;
+        r.n_real = g_real.nwg;
+        r.n_spec = g_spec.nwg;
+        r.hist_cap = hist_cap;
+        r.m = P.m;
+        r.tol = cfg.tol;
+        r.max_iter = cfg.max_iter;
+        if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
+        return AHOM_OK;
+    }
+};
+
+// ============================================================================ API
+extern "C" {
+
+int ahom_version(void) { return (0 << 16) | (1 << 8) | 0; }
+
+const char* ahom_last_error(void) { return g_err.c_str(); }
+
+int ahom_pattern_create(int d, const int64_t* M, ahom_pattern** out) {
+    if (!M || !out) return fail(AHOM_E_ARG, "null argument");
+    *out = nullptr;
+    ahom_pattern* p = new (std::nothrow) ahom_pattern();
+    if (!p) return fail(AHOM_E_NOMEM, "host allocation failed");
+    std::string err;
+    int rc = ahom_smith_form(d, M, &p->sf, &err);
+    if (rc != AHOM_OK) { delete p; return fail(rc, err); }
+    if (p->sf.m > 1) {
+        rc = ahom_build_plan(p->sf, kLmax, &p->plan, &err);
+        if (rc != AHOM_OK) { delete p; return fail(rc, err); }
+        ahom_build_twiddles(&p->plan, &p->tw);
+    } else {
+        p->plan = Plan{};
+        p->plan.d = d;
+        p->plan.m = 1;
+    }
+    *out = p;
+    return AHOM_OK;
+}
+
+void ahom_pattern_destroy(ahom_pattern* p) { delete p; }
+
+int ahom_pattern_info(const ahom_pattern* p, int64_t* m, int* dM, int64_t* e, int64_t* Q, int64_t* R) {
+    if (!p) return fail(AHOM_E_ARG, "null pattern");
+    const int d = p->sf.d;
+    if (m) *m = p->sf.m;
+    if (dM) *dM = p->sf.dM;
+    for (int i = 0; i < d; ++i) {
+        if (e) e[i] = p->sf.e[i];
+        for (int j = 0; j < d; ++j) {
+            if (Q) Q[i * d + j] = p->sf.Q[i][j];
+            if (R) R[i * d + j] = p->sf.R[i][j];
+        }
+    }
+    return AHOM_OK;
+}
+
+int ahom_pattern_points(const ahom_pattern* p, int64_t* num) {
+    if (!p || !num) return fail(AHOM_E_ARG, "null argument");
+    ahom_canonical_points(p->sf, num);
+    return AHOM_OK;
+}
+
+int ahom_pattern_freqs(const ahom_pattern* p, int64_t* h) {
+    if (!p || !h) return fail(AHOM_E_ARG, "null argument");
+    if (p->sf.m == 1) {
+        for (int i = 0; i < p->sf.d; ++i) h[i] = 0;
+        return AHOM_OK;
+    }
+    ahom_canonical_freqs(p->sf, p->plan.fm, h);
+    return AHOM_OK;
+}
+
+int ahom_dft(const ahom_pattern* pc, int sign, int prec, const void* in, void* out, int mem_flags, void* stream) {
+    if (!pc || !in || !out || (sign != -1 && sign != 1)) return fail(AHOM_E_ARG, "bad argument");
+    if (prec != AHOM_FP64 && prec != AHOM_FP32_MIXED) return fail(AHOM_E_ARG, "bad precision");
+    ahom_pattern* p = const_cast<ahom_pattern*>(pc);
+    const int64_t m = p->sf.m;
+    const size_t es = prec == AHOM_FP64 ? 16 : 8;
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 1) {
+        if (mem_flags == AHOM_MEM_DEVICE) HIPCHK(hipMemcpyAsync(out, in, es, hipMemcpyDeviceToDevice, s));
+        else std::memcpy(out, in, es);
+        return AHOM_OK;
+    }
+    int rc = p->ensure_device();
+    if (rc) return rc;
+    const Plan& P = p->plan;
+    void* X = nullptr;
+    void* Y = nullptr;
+    HIPCHK(hipMalloc(&X, m * es));
+    HIPCHK(hipMalloc(&Y, m * es));
+    auto cleanup = [&]() { (void)hipFree(X); (void)hipFree(Y); };
+    const hipMemcpyKind kin = mem_flags == AHOM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind kout = mem_flags == AHOM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (hipMemcpyAsync(sign < 0 ? X : Y, in, m * es, kin, s) != hipSuccess) { cleanup(); return fail(AHOM_E_DEVICE, "copy in"); }
+    ReorderArgs ro{};
+    ro.plan = p->dev.plan;
+    if (sign > 0) {  // canonical frequency order -> kernel positions
+        ro.in = Y; ro.out = X; ro.dir = 1; ro.scale = 1.0;
+        if (ahom_launch_reorder(prec, ro, m, s)) { cleanup(); return fail(AHOM_E_DEVICE, "reorder"); }
+    }
+    for (int t = 0; t < P.D; ++t) {
+        const int a = sign < 0 ? t : P.D - 1 - t;
+        int64_t O = 1, I = 1;
+        for (int b = 0; b < a; ++b) O *= P.ax[b].len;
+        for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].len;
+        PassGeom g;
+        if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, prec, &g))) { cleanup(); return rc; }
+        AxisArgs aa{};
+        aa.plan = p->dev.plan;
+        aa.buf0 = X;
+        aa.buf1 = X;
+        aa.tw = prec == AHOM_FP64 ? (const void*)p->dev.tw64 : (const void*)p->dev.tw32;
+        aa.tw64 = p->dev.tw64;
+        aa.st = nullptr;
+        aa.axis = a;
+        aa.slen0_full = 1;
+        aa.NC = g.NC;
+        aa.CS = g.CS;
+        if (ahom_launch_axis(prec, sign, aa, g.nwg, 1, 1, g.lds, s)) { cleanup(); return fail(AHOM_E_DEVICE, "axis launch"); }
+    }
+    if (sign < 0) {
+        ro.in = X; ro.out = Y; ro.dir = 0; ro.scale = 1.0 / (double)m;
+        if (ahom_launch_reorder(prec, ro, m, s)) { cleanup(); return fail(AHOM_E_DEVICE, "reorder"); }
+    }
+    if (hipMemcpyAsync(out, sign < 0 ? Y : X, m * es, kout, s) != hipSuccess) { cleanup(); return fail(AHOM_E_DEVICE, "copy out"); }
+    if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return fail(AHOM_E_DEVICE, "sync"); }
+    cleanup();
+    return AHOM_OK;
+}
+
+int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solver** out) {
+    if (!pc || !cfg || !out) return fail(AHOM_E_ARG, "null argument");
+    *out = nullptr;
+    if (cfg->precision != AHOM_FP64 && cfg->precision != AHOM_FP32_MIXED) return fail(AHOM_E_ARG, "bad precision");
+    if (cfg->max_iter < 0 || !(cfg->tol >= 0.0)) return fail(AHOM_E_ARG, "bad tol/max_iter");
+    if (cfg->nyquist != AHOM_NYQUIST_HERMITIAN) return fail(AHOM_E_ARG, "unsupported Nyquist rule");
+    ahom_pattern* p = const_cast<ahom_pattern*>(pc);
+    if (p->sf.m < 2) return fail(AHOM_E_ARG, "trivial pattern (m = 1): the strain is eps_bar");
+    int rc = p->ensure_device();
+    if (rc) return rc;
+    ahom_solver* s = new (std::nothrow) ahom_solver();
+    if (!s) return fail(AHOM_E_NOMEM, "host allocation failed");
+    s->pat = p;
+    s->cfg = *cfg;
+    if (s->cfg.check_period < 1) s->cfg.check_period = 1;
+    s->prec = cfg->precision;
+    s->dim = p->sf.d;
+    s->ncomp = s->dim == 3 ? 6 : 3;
+    s->npack = s->dim == 3 ? 3 : 2;
+    s->nt = s->dim == 3 ? 3 : 2;
+    s->stream = (hipStream_t)cfg->stream;
+    const Plan& P = p->plan;
+    const size_t es = s->es();
+    auto bad = [&](int code) { delete s; return code; };
+    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)s->ncomp * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
+    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
+    for (int a = 1; a <= P.D - 2; ++a) {
+        int64_t O = 1, I = 1;
+        for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
+        for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
+        if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, s->prec, &s->g_axis[a]))) return bad(rc);
+    }
+    if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
+        return bad(fail(AHOM_E_DEVICE, "event create"));
+    *out = s;
+    return AHOM_OK;
+}
+
+void ahom_solver_destroy(ahom_solver* s) { delete s; }
+
+int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags) {
+    if (!s || !lame || !phase || n_phase < 1 || n_phase > 256) return fail(AHOM_E_ARG, "bad material arguments");
+    double llo = 1e300, lhi = -1e300, mlo = 1e300, mhi = -1e300;
+    for (int k = 0; k < n_phase; ++k) {
+        const double l = lame[2 * k], mu = lame[2 * k + 1];
+        if (!(mu > 0.0) || !(3.0 * l + 2.0 * mu > 0.0)) return fail(AHOM_E_MATERIAL, "phase " + std::to_string(k) + ": need mu > 0 and 3 lambda + 2 mu > 0");
+        llo = std::min(llo, l); lhi = std::max(lhi, l); mlo = std::min(mlo, mu); mhi = std::max(mhi, mu);
+    }
+    const int64_t m = s->pat->sf.m;
+    dfree(s->d_lame_pts);
+    if (!s->d_phase) HIPCHK(hipMalloc((void**)&s->d_phase, m));
+    dfree(s->d_lame_tab);
+    HIPCHK(hipMalloc((void**)&s->d_lame_tab, 2 * n_phase * sizeof(double)));
+    HIPCHK(hipMemcpy(s->d_lame_tab, lame, 2 * n_phase * sizeof(double), hipMemcpyHostToDevice));
+    if (mem_flags == AHOM_MEM_DEVICE) {
+        HIPCHK(hipMemcpyAsync(s->d_phase, phase, m, hipMemcpyDeviceToDevice, s->stream));
+    } else {
+        std::vector<uint8_t> chk(phase, phase + m);
+        for (int64_t i = 0; i < m; ++i)
+            if (chk[i] >= n_phase) return fail(AHOM_E_ARG, "phase id out of range");
+        HIPCHK(hipMemcpy(s->d_phase, phase, m, hipMemcpyHostToDevice));
+    }
+    s->n_phase = n_phase;
+    s->lam_lo = llo; s->lam_hi = lhi; s->mu_lo = mlo; s->mu_hi = mhi;
+    s->has_material = true;
+    if (!s->ref_set) { s->lam0 = 0.5 * (llo + lhi); s->mu0 = 0.5 * (mlo + mhi); }
+    return AHOM_OK;
+}
+
+int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int mem_flags) {
+    if (!s || !lame_pts) return fail(AHOM_E_ARG, "null argument");
+    const int64_t m = s->pat->sf.m;
+    std::vector<double> h;
+    const double* hp = lame_pts;
+    if (mem_flags == AHOM_MEM_DEVICE) {
+        h.resize(2 * m);
+        HIPCHK(hipMemcpy(h.data(), lame_pts, 2 * m * sizeof(double), hipMemcpyDeviceToHost));
+        hp = h.data();
+    }
+    double llo = 1e300, lhi = -1e300, mlo = 1e300, mhi = -1e300;
+    for (int64_t i = 0; i < m; ++i) {
+        const double l = hp[2 * i], mu = hp[2 * i + 1];
+        if (!(mu > 0.0) || !(3.0 * l + 2.0 * mu > 0.0)) return fail(AHOM_E_MATERIAL, "point " + std::to_string(i) + ": need mu > 0 and 3 lambda + 2 mu > 0");
+        llo = std::min(llo, l); lhi = std::max(lhi, l); mlo = std::min(mlo, mu); mhi = std::max(mhi, mu);
+    }
+    dfree(s->d_lame_pts);
+    HIPCHK(hipMalloc((void**)&s->d_lame_pts, 2 * m * sizeof(double)));
+    HIPCHK(hipMemcpy(s->d_lame_pts, hp, 2 * m * sizeof(double), hipMemcpyHostToDevice));
+    s->lam_lo = llo; s->lam_hi = lhi; s->mu_lo = mlo; s->mu_hi = mhi;
+    s->has_material = true;
+    if (!s->ref_set) { s->lam0 = 0.5 * (llo + lhi); s->mu0 = 0.5 * (mlo + mhi); }
+    return AHOM_OK;
+}
+
+int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0) {
+    if (!s) return fail(AHOM_E_ARG, "null solver");
+    if (!(mu0 > 0.0) || !(lambda0 + 2.0 * mu0 > 0.0)) return fail(AHOM_E_MATERIAL, "reference needs mu0 > 0 and lambda0 + 2 mu0 > 0");
+    s->lam0 = lambda0;
+    s->mu0 = mu0;
+    s->ref_set = true;
+    return AHOM_OK;
+}
+
+int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* init, void* strain_out,
+               int* iters, double* resid, double* mean_stress, int mem_flags) {
+    if (!s || !eps_bar || n_load < 1) return fail(AHOM_E_ARG, "bad solve arguments");
+    if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
+    int rc = s->ensure_capacity(n_load);
+    if (rc) return rc;
+    const Plan& P = s->pat->plan;
+    const int nc = s->ncomp;
+    const int* comp = s->dim == 3 ? kComp3 : kComp2;
+    hipStream_t st = s->stream;
+    std::vector<double> eb((size_t)n_load * nc);
+    for (int l = 0; l < n_load; ++l)
+        for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
+    HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+    if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    if (!init) {
+        FillArgs f{};
+        f.buf = s->d_buf0;
+        f.eps_bar = s->d_epsbar;
+        f.S = P.S;
+        f.row = P.S / P.ax[0].slen;
+        f.nfield = nc;
+        if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    } else {
+        const size_t bytes = (size_t)n_load * nc * P.m * sizeof(double);
+        HIPCHK(hipMemcpyAsync(s->d_real, init, bytes, mem_flags == AHOM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+        if (ahom_launch_real(s->prec, s->dim, REAL_FROM_REAL, s->real_args(REAL_FROM_REAL), s->g_real.nwg, n_load, s->g_real.lds, st))
+            return fail(AHOM_E_DEVICE, "launch from_real");
+        // traction of eps(0): t(0) = -(C0 : eps_hat(0)) xi, so that the first
+        // residual is sigma_hat(0) xi = t(1) - t(0) as on later iterations
+        HIPCHK(hipMemcpyAsync(s->d_buf1, s->d_buf0, (size_t)n_load * nc * P.S * s->es(), hipMemcpyDeviceToDevice, st));
+        for (int a = 1; a <= P.D - 2; ++a) {
+            AxisArgs aa = s->axis_args(a);
+            aa.st = nullptr;
+            aa.buf0 = s->d_buf1;
+            if (ahom_launch_axis(s->prec, -1, aa, s->g_axis[a].nwg, nc, n_load, s->g_axis[a].lds, st))
+                return fail(AHOM_E_DEVICE, "launch init axis");
+        }
+        SpecArgs sa = s->spec_args();
+        sa.buf0 = s->d_buf1;
+        sa.buf1 = nullptr;
+        sa.lam0_init = s->lam0;
+        if (ahom_launch_spec_init(s->prec, s->dim, sa, s->g_spec.nwg, n_load, s->g_spec.lds, st))
+            return fail(AHOM_E_DEVICE, "launch init traction");
+    }
+    HIPCHK(hipEventRecord(s->ev0, st));
+    int enq = 0;
+    const int limit = s->cfg.max_iter + 1;
+    bool all_done = false;
+    while (!all_done) {
+        const int k = std::min(s->cfg.check_period, std::max(1, limit - enq));
+        for (int i = 0; i < k; ++i) {
+            if ((rc = s->enqueue_iteration(n_load))) return rc;
+            ++enq;
+        }
+        HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(s->ev1, st));
+        HIPCHK(hipStreamSynchronize(st));
+        all_done = true;
+        for (int l = 0; l < n_load; ++l) all_done = all_done && s->h_st[l].done;
+        if (enq > limit + 2 * s->cfg.check_period) return fail(AHOM_E_DEVICE, "loop control did not terminate");
+    }
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->last_ms = ms;
+    s->last_enqueued = enq;
+    s->last_nload = n_load;
+    if (strain_out) {
+        RealArgs ra = s->real_args(REAL_TO_REAL);
+        if (mem_flags == AHOM_MEM_DEVICE) ra.real_io = (double*)strain_out;
+        if (ahom_launch_real(s->prec, s->dim, REAL_TO_REAL, ra, s->g_real.nwg, n_load, s->g_real.lds, st))
+            return fail(AHOM_E_DEVICE, "launch to_real");
+        if (mem_flags != AHOM_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(strain_out, s->d_real, (size_t)n_load * nc * P.m * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    int ret = AHOM_OK;
+    for (int l = 0; l < n_load; ++l) {
+        const LoadState& ls = s->h_st[l];
+        if (iters) iters[l] = ls.iter;
+        if (resid) resid[l] = ls.resid;
+        if (mean_stress) {
+            double* ms9 = mean_stress + (size_t)l * 9;
+            for (int q = 0; q < 9; ++q) ms9[q] = 0.0;
+            for (int c = 0; c < nc; ++c) {
+                const int pos = comp[c];
+                ms9[pos] = ls.mean[c];
+                ms9[(pos % 3) * 3 + pos / 3] = ls.mean[c];
+            }
+        }
+        if (ls.status == 2) ret = AHOM_E_DIVERGED;
+        else if (ls.status == 1 && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
+    }
+    if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
+    return ret;
+}
+
+int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters) {
+    if (!s || !Ceff) return fail(AHOM_E_ARG, "null argument");
+    const int d = s->dim;
+    const int k = d == 3 ? 6 : 3;
+    const int pr3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    const int pr2[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+    std::vector<double> eb((size_t)k * 9, 0.0), ms((size_t)k * 9);
+    const double r2 = std::sqrt(2.0);
+    for (int l = 0; l < k; ++l) {
+        const int i = d == 3 ? pr3[l][0] : pr2[l][0], j = d == 3 ? pr3[l][1] : pr2[l][1];
+        const double v = i == j ? 1.0 : 1.0 / r2;
+        eb[(size_t)l * 9 + i * 3 + j] = v;
+        eb[(size_t)l * 9 + j * 3 + i] = v;
+    }
+    int rc = ahom_solve(s, k, eb.data(), nullptr, nullptr, iters, nullptr, ms.data(), AHOM_MEM_HOST);
+    if (rc < 0) return rc;
+    for (int col = 0; col < k; ++col)
+        for (int row = 0; row < k; ++row) {
+            const int i = d == 3 ? pr3[row][0] : pr2[row][0], j = d == 3 ? pr3[row][1] : pr2[row][1];
+            Ceff[row * k + col] = ms[(size_t)col * 9 + i * 3 + j] * (i == j ? 1.0 : r2);
+        }
+    return rc;
+}
+
+int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* enq) {
+    if (!s) return fail(AHOM_E_ARG, "null solver");
+    if (ms) *ms = s->last_ms;
+    if (enq) *enq = s->last_enqueued;
+    return AHOM_OK;
+}
+
+int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count) {
+    if (!s || !hist || !count || load < 0 || load >= s->last_nload) return fail(AHOM_E_ARG, "bad history arguments");
+    const int n = std::min(cap, std::min(s->hist_cap, s->h_st[load].iter + 1));
+    HIPCHK(hipMemcpy(hist, s->d_hist + (size_t)load * s->hist_cap, n * sizeof(double), hipMemcpyDeviceToHost));
+    *count = n;
+    return AHOM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Kernel argument blocks and launchers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ahom_internal.h"
+
+enum { REAL_TURN = 0, REAL_TO_REAL = 1, REAL_FROM_REAL = 2 };
+enum { SPEC_TURN = 0, SPEC_INIT = 1 };
+
+// Device-side state of one load case.  iter = n of the iterate being
+// processed; done/status/final_buf are set by k_reduce.
+struct LoadState {
+    int iter;
+    int done;
+    int status;      // 0 converged, 1 max_iter, 2 diverged
+    int final_buf;   // state buffer that holds eps(n) at stop
+    double r0;
+    double resid;
+    double mean[6];
+};
+
+struct RealArgs {
+    const Plan* plan;
+    void* buf0;
+    void* buf1;
+    const void* tw;           // Stockham roots in the working precision
+    const double2* tw64;      // FP64 roots (four-step twiddles)
+    LoadState* st;
+    const uint8_t* phase;
+    const double* lame_tab;   // (lambda, mu) per phase
+    const double* lame_pts;   // or per point (nullptr if unused)
+    double lam0, mu0;
+    double* sig_part;         // [load][wg][ncomp]
+    double* real_io;          // [load][ncomp][m] for TO_REAL / FROM_REAL
+    const double* eps_bar;    // [load][ncomp]
+    int NC, CS;
+};
+
+struct AxisArgs {
+    const Plan* plan;
+    void* buf0;
+    void* buf1;
+    const void* tw;
+    const double2* tw64;
+    LoadState* st;            // nullptr: always use buf0
+    int64_t load_stride, field_stride;
+    int axis;
+    int slen0_full;           // 1: axis 0 stored at full length (bare DFT)
+    int NC, CS;
+};
+
+struct SpecArgs {
+    const Plan* plan;
+    void* buf0;
+    void* buf1;
+    void* tbuf;               // traction tau_hat xi of the previous iteration
+    const void* tw;
+    LoadState* st;
+    const double* eps_bar;
+    double mu0, beta;
+    double lam0_init;          // lambda0 (used by SPEC_INIT)
+    double* res_part;         // [load][wg]
+    int NC, CS;
+};
+
+struct ReduceArgs {
+    LoadState* st;
+    const double* sig_part;
+    const double* res_part;
+    double* hist;
+    int n_real, n_spec, hist_cap;
+    int64_t m;
+    double tol;
+    int max_iter;
+};
+
+struct FillArgs {
+    void* buf;
+    const double* eps_bar;
+    int64_t S, row;
+    int nfield;
+};
+
+struct ReorderArgs {
+    const Plan* plan;
+    const void* in;
+    void* out;
+    double scale;
+    int dir;
+};
+
+int ahom_launch_real(int prec, int dim, int mode, const RealArgs& a, int nwg, int nload, size_t lds, hipStream_t s);
+int ahom_launch_axis(int prec, int dir, const AxisArgs& a, int nwg, int nfield, int nload, size_t lds, hipStream_t s);
+int ahom_launch_spec(int prec, int dim, const SpecArgs& a, int nwg, int nload, size_t lds, hipStream_t s);
+int ahom_launch_spec_init(int prec, int dim, const SpecArgs& a, int nwg, int nload, size_t lds, hipStream_t s);
+int ahom_launch_reduce(int dim, const ReduceArgs& a, int nload, hipStream_t s);
+int ahom_launch_fill(int prec, const FillArgs& a, int nload, hipStream_t s);
+int ahom_launch_reset(LoadState* st, int n, hipStream_t s);
+int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s);
+int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s);

@@ -1,0 +1,770 @@
+// HIP kernels (gfx950) for one iteration of the generalized Basic Scheme.
+//
+// Field storage (per load case, per strain component): the half spectrum
+// along kernel axis 0 (stored length L0/2 + 1), full length along the other
+// kernel axes, row-major, interleaved complex.  One iteration (Algorithm 1,
+// Sec. 3.2) is a chain of passes over HBM:
+//   k_real   axis 0 : inverse C2R, local law tau = (C - C0) : eps, forward R2C
+//   k_axis   axes 1..D-2 forward, then later inverse (plain complex FFTs)
+//   k_spec   axis D-1 : forward FFT, Gamma0 at h(kappa) + residual terms,
+//                       inverse FFT
+//   k_reduce          : FP64 residual and mean stress, loop control
+// Each 1-D transform is a mixed-radix Stockham FFT held in LDS.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "ahom_internal.h"
+#include "ahom_kernels.h"
+
+namespace {
+
+template <typename T> struct CT;
+template <> struct CT<double> { using t = double2; };
+template <> struct CT<float> { using t = float2; };
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) { return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+// multiply by -i (forward, DIR = -1) or +i (inverse, DIR = +1)
+template <int DIR, typename C> __device__ __forceinline__ C mul_i(C a) {
+    return DIR < 0 ? C{a.y, -a.x} : C{-a.y, a.x};
+}
+
+// ---------------------------------------------------------------- butterflies
+// y_k = sum_r v_r W_R^{r k}, W_R = exp(DIR 2 pi i / R)
+template <int DIR, typename C> __device__ __forceinline__ void bfly2(C* v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void bfly4(C* v) {
+    C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    C c = cadd(v[1], v[3]), d = mul_i<DIR>(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+}
+
+template <int DIR, typename C> __device__ __forceinline__ void bfly8(C* v) {
+    using T = decltype(v[0].x);
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    bfly4<DIR>(e);
+    bfly4<DIR>(o);
+    const T r = (T)0.70710678118654752440;
+    // W8^1 o1, W8^2 o2, W8^3 o3
+    C o1 = DIR < 0 ? C{r * (o[1].x + o[1].y), r * (o[1].y - o[1].x)} : C{r * (o[1].x - o[1].y), r * (o[1].y + o[1].x)};
+    C o2 = mul_i<DIR>(o[2]);
+    C o3 = DIR < 0 ? C{r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y)} : C{-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y)};
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+}
+
+// small odd radices: direct sum with cos/sin of 2 pi j / R
+template <int R, int DIR, typename C> __device__ __forceinline__ void bfly_odd(C* v) {
+    using T = decltype(v[0].x);
+    constexpr double c3[3] = {1.0, -0.5, -0.5};
+    constexpr double s3[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+    constexpr double c5[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410, -0.80901699437494742410, 0.30901699437494742410};
+    constexpr double s5[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917, -0.58778525229247312917, -0.95105651629515357212};
+    constexpr double c7[7] = {1.0, 0.62348980185873353053, -0.22252093395631440429, -0.90096886790241912624,
+                              -0.90096886790241912624, -0.22252093395631440429, 0.62348980185873353053};
+    constexpr double s7[7] = {0.0, 0.78183148246802980871, 0.97492791218182360702, 0.43388373911755812048,
+                              -0.43388373911755812048, -0.97492791218182360702, -0.78183148246802980871};
+    const double* cs = R == 3 ? c3 : (R == 5 ? c5 : c7);
+    const double* sn = R == 3 ? s3 : (R == 5 ? s5 : s7);
+    C out[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        C acc = v[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const int j = (r * k) % R;
+            const T c = (T)cs[j], s = (T)(DIR < 0 ? -sn[j] : sn[j]);
+            acc.x += v[r].x * c - v[r].y * s;
+            acc.y += v[r].x * s + v[r].y * c;
+        }
+        out[k] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
+// One radix-R Stockham stage over `total` butterflies of all columns.
+template <int R, int DIR, typename C>
+__device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__ dst, int ncol, int L, int CS, int Ns,
+                                      const C* __restrict__ tw) {
+    const int nb = L / R;
+    const int total = ncol * nb;
+    const int tstep = L / (Ns * R);
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int j = t / nb;
+        const int b = t - j * nb;
+        const int k = b % Ns;
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = src[j * CS + b + r * nb];
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const C w = tw[k * r * tstep];
+                v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+            }
+        }
+        if constexpr (R == 2) bfly2<DIR>(v);
+        else if constexpr (R == 4) bfly4<DIR>(v);
+        else if constexpr (R == 8) bfly8<DIR>(v);
+        else bfly_odd<R, DIR>(v);
+        const int o = (b / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[j * CS + o + r * Ns] = v[r];
+    }
+}
+
+// In-LDS FFT of `ncol` columns of length L (column stride CS); result in buf.
+template <int DIR, typename C>
+__device__ void lds_fft(C* buf, C* tmp, int ncol, int CS, const AxisDesc& ax, const C* __restrict__ tw) {
+    const int L = ax.len;
+    C* src = buf;
+    C* dst = tmp;
+    int Ns = 1;
+    for (int s = 0; s < ax.nstage; ++s) {
+        const int R = ax.radix[s];
+        switch (R) {
+            case 8: stage<8, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+            case 4: stage<4, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+            case 2: stage<2, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+            case 3: stage<3, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+            case 5: stage<5, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+            default: stage<7, DIR>(src, dst, ncol, L, CS, Ns, tw); break;
+        }
+        __syncthreads();
+        C* t = src; src = dst; dst = t;
+        Ns *= R;
+    }
+    if (src != buf) {
+        for (int e = threadIdx.x; e < ncol * L; e += blockDim.x) {
+            const int j = e / L, l = e - j * L;
+            buf[j * CS + l] = src[j * CS + l];
+        }
+        __syncthreads();
+    }
+}
+
+// Four-step twiddle W_N^{j} from the two-level FP64 table, rounded to C.
+template <typename C>
+__device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
+    const double2 a = tw64[ax.sp_off1 + (j % ax.spB)];
+    const double2 b = tw64[ax.sp_off2 + (j / ax.spB)];
+    const double2 w = cmul(a, b);
+    using T = decltype(C{}.x);
+    return C{(T)w.x, (T)w.y};
+}
+
+template <typename T> __device__ __forceinline__ T* lds_base() {
+    extern __shared__ __align__(16) unsigned char ahom_smem[];
+    return reinterpret_cast<T*>(ahom_smem);
+}
+
+// block-wide sum of NV doubles per thread (fixed order); result valid in thread 0
+template <int NV>
+__device__ void block_sum(double* vals, double* scratch) {
+    const int tid = threadIdx.x;
+    for (int c = 0; c < NV; ++c) scratch[c * AHOM_WG + tid] = vals[c];
+    __syncthreads();
+    for (int off = AHOM_WG / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int c = 0; c < NV; ++c) scratch[c * AHOM_WG + tid] += scratch[c * AHOM_WG + tid + off];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int c = 0; c < NV; ++c) vals[c] = scratch[c * AHOM_WG];
+}
+
+template <int DIM> struct Comp;
+template <> struct Comp<3> { static constexpr int N = 6, NP = 3, NT = 3; };
+template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
+
+}  // namespace
+
+// =============================================================================
+// axis 0: real-space turnaround
+// =============================================================================
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.y;
+    const LoadState& st = a.st[load];
+    if (MODE == REAL_TURN && st.done) return;
+    const AxisDesc& ax = P.ax[0];
+    const int L = ax.len, H = ax.slen;
+    const int64_t I = P.S / H;
+    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int ncol = (int)((I - c0) < a.NC ? (I - c0) : a.NC);
+    const int CS = a.CS;
+    const int tid = threadIdx.x;
+
+    C* Z = lds_base<C>();
+    C* tmp = Z + NP * a.NC * CS;
+    double* red = reinterpret_cast<double*>(tmp + a.NC * CS);
+
+    int src_buf = 0;
+    if (MODE == REAL_TURN) src_buf = st.iter & 1;
+    if (MODE == REAL_TO_REAL) src_buf = st.final_buf;
+    const C* src = reinterpret_cast<const C*>(src_buf ? a.buf1 : a.buf0) + (int64_t)load * NC_ * P.S;
+    C* dst = reinterpret_cast<C*>((MODE == REAL_TURN ? (src_buf ^ 1) : 0) ? a.buf1 : a.buf0) + (int64_t)load * NC_ * P.S;
+    const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
+
+    if (MODE != REAL_FROM_REAL) {
+        // ---- gather the half spectra and form packed full spectra Z_p = A + i B
+        for (int e = tid; e < H * a.NC; e += blockDim.x) {
+            const int k = e / a.NC, j = e - k * a.NC;
+            if (j >= ncol) continue;
+            const int64_t col = c0 + j;
+            C w = C{(T)1, (T)0};
+            if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int fa = 2 * p, fb = 2 * p + 1;
+                C A = src[(int64_t)fa * P.S + (int64_t)k * I + col];
+                C B = fb < NC_ ? src[(int64_t)fb * P.S + (int64_t)k * I + col] : C{(T)0, (T)0};
+                if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
+                if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
+                C* Zp = Z + p * a.NC * CS + j * CS;
+                Zp[k] = C{A.x - B.y, A.y + B.x};
+                if (k > 0 && 2 * k != L) Zp[L - k] = C{A.x + B.y, B.x - A.y};
+            }
+        }
+        __syncthreads();
+        for (int p = 0; p < NP; ++p) lds_fft<+1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, tw);
+    }
+
+    if (MODE == REAL_TO_REAL) {
+        double* out = a.real_io + (int64_t)load * NC_ * P.m;
+        for (int e = tid; e < L * a.NC; e += blockDim.x) {
+            const int n = e / a.NC, j = e - n * a.NC;
+            if (j >= ncol) continue;
+            const int64_t pt = (int64_t)n * I + c0 + j;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const C z = Z[p * a.NC * CS + j * CS + n];
+                out[(int64_t)(2 * p) * P.m + pt] = (double)z.x;
+                if (2 * p + 1 < NC_) out[(int64_t)(2 * p + 1) * P.m + pt] = (double)z.y;
+            }
+        }
+        return;
+    }
+
+    double sig[NC_];
+#pragma unroll
+    for (int c = 0; c < NC_; ++c) sig[c] = 0.0;
+
+    if (MODE == REAL_TURN) {
+        const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
+        for (int e = tid; e < L * a.NC; e += blockDim.x) {
+            const int n = e / a.NC, j = e - n * a.NC;
+            if (j >= ncol) continue;
+            const int64_t pt = (int64_t)n * I + c0 + j;
+            T lam, mu;
+            if (a.lame_pts) {
+                lam = (T)a.lame_pts[2 * pt];
+                mu = (T)a.lame_pts[2 * pt + 1];
+            } else {
+                const int ph = a.phase[pt];
+                lam = (T)a.lame_tab[2 * ph];
+                mu = (T)a.lame_tab[2 * ph + 1];
+            }
+            T eps[NC_];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const C z = Z[p * a.NC * CS + j * CS + n];
+                eps[2 * p] = z.x;
+                if (2 * p + 1 < NC_) eps[2 * p + 1] = z.y;
+            }
+            const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+            const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+            T tau[NC_];
+#pragma unroll
+            for (int c = 0; c < NC_; ++c) {
+                const bool diag = DIM == 3 ? c < 3 : c < 2;
+                const T s = (T)2 * mu * eps[c] + (diag ? lam * tr : (T)0);
+                sig[c] += (double)s;
+                tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                Z[p * a.NC * CS + j * CS + n] = C{tau[2 * p], 2 * p + 1 < NC_ ? tau[2 * p + 1] : (T)0};
+        }
+    } else {  // REAL_FROM_REAL: eps = eps_bar + init
+        const double* in = a.real_io + (int64_t)load * NC_ * P.m;
+        const double* eb = a.eps_bar + (int64_t)load * NC_;
+        for (int e = tid; e < L * a.NC; e += blockDim.x) {
+            const int n = e / a.NC, j = e - n * a.NC;
+            if (j >= ncol) continue;
+            const int64_t pt = (int64_t)n * I + c0 + j;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int fa = 2 * p, fb = 2 * p + 1;
+                const T va = (T)(eb[fa] + in[(int64_t)fa * P.m + pt]);
+                const T vb = fb < NC_ ? (T)(eb[fb] + in[(int64_t)fb * P.m + pt]) : (T)0;
+                Z[p * a.NC * CS + j * CS + n] = C{va, vb};
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = 0; p < NP; ++p) lds_fft<-1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, tw);
+
+    // ---- split the packed spectra and store the half spectra
+    const T scale = MODE == REAL_FROM_REAL ? (T)(1.0 / L) : (T)1;
+    for (int e = tid; e < H * a.NC; e += blockDim.x) {
+        const int k = e / a.NC, j = e - k * a.NC;
+        if (j >= ncol) continue;
+        const int64_t col = c0 + j;
+        C w = C{(T)1, (T)0};
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+        const int km = k == 0 ? 0 : L - k;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const C* Zp = Z + p * a.NC * CS + j * CS;
+            const C zk = Zp[k], zm = Zp[km];
+            // A = (Z_k + conj Z_{-k})/2,  B = (Z_k - conj Z_{-k})/(2i)
+            C A = C{(T)0.5 * (zk.x + zm.x) * scale, (T)0.5 * (zk.y - zm.y) * scale};
+            C B = C{(T)0.5 * (zk.y + zm.y) * scale, (T)0.5 * (zm.x - zk.x) * scale};
+            if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
+            dst[(int64_t)(2 * p) * P.S + (int64_t)k * I + col] = A;
+            if (2 * p + 1 < NC_) dst[(int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col] = B;
+        }
+    }
+
+    if (MODE == REAL_TURN) {
+        __syncthreads();
+        block_sum<NC_>(sig, red);
+        if (tid == 0)
+            for (int c = 0; c < NC_; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NC_ + c] = sig[c];
+    }
+}
+
+// =============================================================================
+// middle axes: plain complex FFT passes (also the bare pattern DFT)
+// =============================================================================
+template <typename T, int DIR>
+__global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
+    using C = typename CT<T>::t;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.z;
+    int par = 0;
+    if (a.st) {
+        const LoadState& st = a.st[load];
+        if (st.done) return;
+        par = (st.iter + 1) & 1;
+    }
+    const AxisDesc& ax = P.ax[a.axis];
+    const int L = ax.len;
+    int64_t O = 1, I = 1;
+    for (int b = 0; b < a.axis; ++b) O *= a.slen0_full && b == 0 ? P.ax[0].len : P.ax[b].slen;
+    for (int b = a.axis + 1; b < P.D; ++b) I *= P.ax[b].slen;
+    const int64_t ncols = O * I;
+    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int ncol = (int)((ncols - c0) < a.NC ? (ncols - c0) : a.NC);
+    const int CS = a.CS;
+    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)blockIdx.y * a.field_stride;
+    const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
+    C* X = lds_base<C>();
+    C* tmp = X + a.NC * CS;
+    const bool rowmajor = I >= a.NC;
+    const int tid = threadIdx.x;
+
+    for (int e = tid; e < L * a.NC; e += blockDim.x) {
+        int j, l;
+        if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
+        if (j >= ncol) continue;
+        const int64_t col = c0 + j;
+        const int64_t addr = (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+        C v = base[addr];
+        if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, ((col % I) / ax.qdiv) * (int64_t)l));
+        X[j * CS + l] = v;
+    }
+    __syncthreads();
+    lds_fft<DIR>(X, tmp, ncol, CS, ax, tw);
+    for (int e = tid; e < L * a.NC; e += blockDim.x) {
+        int j, l;
+        if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
+        if (j >= ncol) continue;
+        const int64_t col = c0 + j;
+        const int64_t addr = (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+        C v = X[j * CS + l];
+        if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, ((col % I) / ax.qdiv) * (int64_t)l));
+        base[addr] = v;
+    }
+}
+
+// =============================================================================
+// last axis: spectral turnaround with Gamma0 and the residual terms
+// =============================================================================
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.y;
+    const LoadState& st = a.st[load];
+    if (st.done) return;
+    const int par = MODE == SPEC_INIT ? 0 : (st.iter + 1) & 1;
+    const int D = P.D;
+    const AxisDesc& ax = P.ax[D - 1];
+    const int L = ax.len;
+    const int64_t ncols = P.S / L;
+    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int ncol = (int)((ncols - c0) < a.NC ? (ncols - c0) : a.NC);
+    const int CS = a.CS;
+    const int tid = threadIdx.x;
+    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * NC_ * P.S;
+    C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
+    const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
+    C* F = lds_base<C>();
+    C* tmp = F + NC_ * a.NC * CS;
+    double* red = reinterpret_cast<double*>(tmp + a.NC * CS);
+
+    for (int e = tid; e < L * a.NC; e += blockDim.x) {
+        const int j = e / L, l = e - j * L;
+        if (j >= ncol) continue;
+        const int64_t addr = (c0 + j) * L + l;
+#pragma unroll
+        for (int f = 0; f < NC_; ++f) F[f * a.NC * CS + j * CS + l] = base[(int64_t)f * P.S + addr];
+    }
+    __syncthreads();
+    for (int f = 0; f < NC_; ++f) lds_fft<-1>(F + f * a.NC * CS, tmp, ncol, CS, ax, tw);
+
+    const double* eb = a.eps_bar + (int64_t)load * NC_;
+    const T inv_m = (T)(1.0 / (double)P.m);
+    const T mu0 = (T)a.mu0, beta = (T)a.beta;
+    const int L0 = P.ax[0].len;
+    double res = 0.0;
+    for (int e = tid; e < L * a.NC; e += blockDim.x) {
+        const int j = e / L, l = e - j * L;
+        if (j >= ncol) continue;
+        // position -> kappa
+        int64_t kpos[AHOM_MAX_AXES];
+        int64_t o = c0 + j;
+        for (int b = D - 2; b >= 0; --b) {
+            const int64_t sl = P.ax[b].slen;
+            kpos[b] = o % sl;
+            o /= sl;
+        }
+        kpos[D - 1] = l;
+        int64_t kap[3] = {0, 0, 0};
+        for (int b = 0; b < D; ++b) kap[P.ax[b].snf] += P.ax[b].mult * kpos[b];
+        const bool is_zero = kap[0] == 0 && kap[1] == 0 && kap[2] == 0;
+        int64_t N[3];
+        const int half = ahom_centred_numerators(P.fm, kap, N);
+        const bool active = !half || ahom_self_conjugate(P.fm, kap);
+        const int64_t spos = (c0 + j) * L + l;
+        C* fp[NC_];
+#pragma unroll
+        for (int f = 0; f < NC_; ++f) fp[f] = F + f * a.NC * CS + j * CS + l;
+        if (is_zero) {
+#pragma unroll
+            for (int f = 0; f < NC_; ++f) *fp[f] = C{(T)eb[f], (T)0};
+            continue;
+        }
+        if (!active) {
+#pragma unroll
+            for (int f = 0; f < NC_; ++f) *fp[f] = C{(T)0, (T)0};
+            continue;
+        }
+        double hd[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < DIM; ++i)
+            for (int q = 0; q < DIM; ++q) hd[i] += (double)P.fm.MT[i][q] * (double)N[q];
+        double hn = 0.0;
+        for (int i = 0; i < DIM; ++i) hn += hd[i] * hd[i];
+        hn = 1.0 / sqrt(hn);
+        T xi[3];
+        for (int i = 0; i < DIM; ++i) xi[i] = (T)(hd[i] * hn);
+        if (MODE == SPEC_INIT) {
+            // eps_hat(0) = value * L0 / m; t(0) = -(C0 : eps_hat(0)) xi
+            const T sc = (T)((double)L0 / (double)P.m);
+            C ev[NC_];
+#pragma unroll
+            for (int f = 0; f < NC_; ++f) { C v = *fp[f]; ev[f] = C{v.x * sc, v.y * sc}; }
+            const T lam0 = (T)a.lam0_init, two_mu0 = (T)2 * (T)a.mu0;
+            C trc = DIM == 3 ? cadd(cadd(ev[0], ev[1]), ev[2]) : cadd(ev[0], ev[1]);
+            C E[3][3];
+            if constexpr (DIM == 3) {
+                E[0][0] = ev[0]; E[1][1] = ev[1]; E[2][2] = ev[2];
+                E[1][2] = E[2][1] = ev[3]; E[0][2] = E[2][0] = ev[4]; E[0][1] = E[1][0] = ev[5];
+            } else {
+                E[0][0] = ev[0]; E[1][1] = ev[1]; E[0][1] = E[1][0] = ev[2];
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                C acc = C{lam0 * trc.x * xi[i], lam0 * trc.y * xi[i]};
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) { acc.x += two_mu0 * E[i][q].x * xi[q]; acc.y += two_mu0 * E[i][q].y * xi[q]; }
+                tb[(int64_t)i * P.S + spos] = C{-acc.x, -acc.y};
+            }
+            continue;
+        }
+        // tau_hat tensor entries (normalized by 1/m)
+        C tv[NC_];
+#pragma unroll
+        for (int f = 0; f < NC_; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
+        C t[NT];
+        if constexpr (DIM == 3) {
+            // components (11,22,33,23,13,12)
+            const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
+            t[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
+            t[1] = C{T01.x * xi[0] + T11.x * xi[1] + T12.x * xi[2], T01.y * xi[0] + T11.y * xi[1] + T12.y * xi[2]};
+            t[NT - 1] = C{T02.x * xi[0] + T12.x * xi[1] + T22.x * xi[2], T02.y * xi[0] + T12.y * xi[1] + T22.y * xi[2]};
+        } else {
+            // components (11,22,12)
+            const C T00 = tv[0], T11 = tv[1], T01 = tv[2];
+            t[0] = C{T00.x * xi[0] + T01.x * xi[1], T00.y * xi[0] + T01.y * xi[1]};
+            t[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
+        }
+        // residual: sigma_hat(n) xi = t(n+1) - t(n) on active frequencies
+        const double wgt = (kpos[0] == 0 || 2 * kpos[0] == L0) ? 1.0 : 2.0;
+        double r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const C old = tb[(int64_t)c * P.S + spos];
+            const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
+            r2 += dx * dx + dy * dy;
+            tb[(int64_t)c * P.S + spos] = t[c];
+        }
+        res += wgt * r2;
+        // v = (t - beta (xi . t) xi) / mu0 ; eps_hat = -sym(xi (x) v)
+        C xt = C{(T)0, (T)0};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * t[i].x; xt.y += xi[i] * t[i].y; }
+        C v[3];
+        const T im0 = (T)1 / mu0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) v[i] = C{(t[i].x - beta * xt.x * xi[i]) * im0, (t[i].y - beta * xt.y * xi[i]) * im0};
+        if constexpr (DIM == 3) {
+            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+            *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
+            *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
+            *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
+            *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+        } else {
+            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+            *fp[NC_ - 1] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+        }
+    }
+    if (MODE == SPEC_INIT) return;
+    __syncthreads();
+    for (int f = 0; f < NC_; ++f) lds_fft<+1>(F + f * a.NC * CS, tmp, ncol, CS, ax, tw);
+    for (int e = tid; e < L * a.NC; e += blockDim.x) {
+        const int j = e / L, l = e - j * L;
+        if (j >= ncol) continue;
+        const int64_t addr = (c0 + j) * L + l;
+#pragma unroll
+        for (int f = 0; f < NC_; ++f) base[(int64_t)f * P.S + addr] = F[f * a.NC * CS + j * CS + l];
+    }
+    double rv[1] = {res};
+    block_sum<1>(rv, red);
+    if (tid == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
+}
+
+// =============================================================================
+// residual / mean stress reduction and loop control (one block per load)
+// =============================================================================
+template <int DIM>
+__global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
+    constexpr int NC_ = Comp<DIM>::N;
+    __shared__ double scratch[(NC_ + 1) * AHOM_WG];
+    const int load = blockIdx.x;
+    LoadState& st = a.st[load];
+    if (st.done) return;
+    const int tid = threadIdx.x;
+    double v[NC_ + 1];
+    for (int c = 0; c <= NC_; ++c) v[c] = 0.0;
+    for (int w = tid; w < a.n_real; w += AHOM_WG)
+        for (int c = 0; c < NC_; ++c) v[c] += a.sig_part[((int64_t)load * a.n_real + w) * NC_ + c];
+    for (int w = tid; w < a.n_spec; w += AHOM_WG) v[NC_] += a.res_part[(int64_t)load * a.n_spec + w];
+    block_sum<NC_ + 1>(v, scratch);
+    if (tid != 0) return;
+    const double inv_m = 1.0 / (double)a.m;
+    double mean[NC_];
+    double fro = 0.0;
+    for (int c = 0; c < NC_; ++c) {
+        mean[c] = v[c] * inv_m;
+        const bool diag = DIM == 3 ? c < 3 : c < 2;
+        fro += (diag ? 1.0 : 2.0) * mean[c] * mean[c];
+    }
+    const double r = sqrt(v[NC_]) / sqrt(fro);
+    const int n = st.iter;
+    if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = r;
+    if (n == 0) st.r0 = r;
+    st.resid = r;
+    for (int c = 0; c < NC_; ++c) st.mean[c] = mean[c];
+    const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
+    if (bad) { st.done = 1; st.status = 2; st.final_buf = n & 1; return; }
+    if (r <= a.tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; return; }
+    if (n >= a.max_iter) { st.done = 1; st.status = 1; st.final_buf = n & 1; return; }
+    st.iter = n + 1;
+}
+
+// =============================================================================
+// helpers: state initialisation and DFT reordering
+// =============================================================================
+template <typename T>
+__global__ void k_fill_state(FillArgs a) {
+    using C = typename CT<T>::t;
+    const int load = blockIdx.y;
+    const int f = blockIdx.z;
+    C* buf = reinterpret_cast<C*>(a.buf) + ((int64_t)load * a.nfield + f) * a.S;
+    const double v = a.eps_bar[(int64_t)load * a.nfield + f];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.S; i += (int64_t)gridDim.x * blockDim.x)
+        buf[i] = i < a.row ? C{(T)v, (T)0} : C{(T)0, (T)0};
+}
+
+__global__ void k_reset_states(LoadState* st, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        LoadState s{};
+        st[i] = s;
+    }
+}
+
+template <typename T>
+__global__ void k_zero(T* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = (T)0;
+}
+
+// kernel order position <-> canonical kappa order; dir = 0 gather to canonical
+// (out[canon] = in[pos] * scale), dir = 1 scatter from canonical.
+template <typename T>
+__global__ void k_reorder(ReorderArgs a) {
+    using C = typename CT<T>::t;
+    const Plan& P = *a.plan;
+    const C* in = reinterpret_cast<const C*>(a.in);
+    C* out = reinterpret_cast<C*>(a.out);
+    for (int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < P.m; pos += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = pos, kap[3] = {0, 0, 0};
+        for (int b = P.D - 1; b >= 0; --b) {
+            const int64_t k = r % P.ax[b].len;
+            r /= P.ax[b].len;
+            kap[P.ax[b].snf] += P.ax[b].mult * k;
+        }
+        int64_t canon = 0;
+        for (int s = 0; s < P.d; ++s) canon += kap[s] * P.canon_stride[s];
+        if (a.dir == 0) {
+            C v = in[pos];
+            out[canon] = C{v.x * (decltype(v.x))a.scale, v.y * (decltype(v.x))a.scale};
+        } else {
+            out[pos] = in[canon];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- launchers
+#define AHOM_CHECK_LAUNCH() (hipGetLastError() == hipSuccess ? 0 : -1)
+
+template <typename T>
+static int set_lds(const void* fn, size_t bytes) {
+    if (bytes > 64 * 1024)
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) return -1;
+    return 0;
+}
+
+int ahom_launch_real(int prec, int dim, int mode, const RealArgs& a, int nwg, int nload, size_t lds, hipStream_t s) {
+    dim3 grid(nwg, nload), block(AHOM_WG);
+#define AHOM_REAL(T, D, M)                                                             \
+    do {                                                                               \
+        auto fn = k_real<T, D, M>;                                                     \
+        if (set_lds<T>((const void*)fn, lds)) return -1;                               \
+        hipLaunchKernelGGL(fn, grid, block, lds, s, a);                                \
+    } while (0)
+#define AHOM_REAL_M(T, D)                                                              \
+    do {                                                                               \
+        if (mode == REAL_TURN) AHOM_REAL(T, D, REAL_TURN);                             \
+        else if (mode == REAL_TO_REAL) AHOM_REAL(T, D, REAL_TO_REAL);                  \
+        else AHOM_REAL(T, D, REAL_FROM_REAL);                                          \
+    } while (0)
+    if (prec == 0) { if (dim == 3) AHOM_REAL_M(double, 3); else AHOM_REAL_M(double, 2); }
+    else { if (dim == 3) AHOM_REAL_M(float, 3); else AHOM_REAL_M(float, 2); }
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_axis(int prec, int dir, const AxisArgs& a, int nwg, int nfield, int nload, size_t lds, hipStream_t s) {
+    dim3 grid(nwg, nfield, nload), block(AHOM_WG);
+#define AHOM_AXIS(T, DIR)                                                              \
+    do {                                                                               \
+        auto fn = k_axis<T, DIR>;                                                      \
+        if (set_lds<T>((const void*)fn, lds)) return -1;                               \
+        hipLaunchKernelGGL(fn, grid, block, lds, s, a);                                \
+    } while (0)
+    if (prec == 0) { if (dir < 0) AHOM_AXIS(double, -1); else AHOM_AXIS(double, 1); }
+    else { if (dir < 0) AHOM_AXIS(float, -1); else AHOM_AXIS(float, 1); }
+    return AHOM_CHECK_LAUNCH();
+}
+
+#define AHOM_SPEC(T, D, M)                                                             \
+    do {                                                                               \
+        auto fn = k_spec<T, D, M>;                                                     \
+        if (set_lds<T>((const void*)fn, lds)) return -1;                               \
+        hipLaunchKernelGGL(fn, grid, block, lds, s, a);                                \
+    } while (0)
+int ahom_launch_spec(int prec, int dim, const SpecArgs& a, int nwg, int nload, size_t lds, hipStream_t s) {
+    dim3 grid(nwg, nload), block(AHOM_WG);
+    if (prec == 0) { if (dim == 3) AHOM_SPEC(double, 3, SPEC_TURN); else AHOM_SPEC(double, 2, SPEC_TURN); }
+    else { if (dim == 3) AHOM_SPEC(float, 3, SPEC_TURN); else AHOM_SPEC(float, 2, SPEC_TURN); }
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_spec_init(int prec, int dim, const SpecArgs& a, int nwg, int nload, size_t lds, hipStream_t s) {
+    dim3 grid(nwg, nload), block(AHOM_WG);
+    if (prec == 0) { if (dim == 3) AHOM_SPEC(double, 3, SPEC_INIT); else AHOM_SPEC(double, 2, SPEC_INIT); }
+    else { if (dim == 3) AHOM_SPEC(float, 3, SPEC_INIT); else AHOM_SPEC(float, 2, SPEC_INIT); }
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_reduce(int dim, const ReduceArgs& a, int nload, hipStream_t s) {
+    if (dim == 3) hipLaunchKernelGGL(k_reduce<3>, dim3(nload), dim3(AHOM_WG), 0, s, a);
+    else hipLaunchKernelGGL(k_reduce<2>, dim3(nload), dim3(AHOM_WG), 0, s, a);
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_fill(int prec, const FillArgs& a, int nload, hipStream_t s) {
+    int64_t blocks = (a.S + AHOM_WG - 1) / AHOM_WG;
+    if (blocks > 4096) blocks = 4096;
+    dim3 grid((unsigned)blocks, nload, a.nfield);
+    if (prec == 0) hipLaunchKernelGGL(k_fill_state<double>, grid, dim3(AHOM_WG), 0, s, a);
+    else hipLaunchKernelGGL(k_fill_state<float>, grid, dim3(AHOM_WG), 0, s, a);
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_reset(LoadState* st, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_states, dim3((n + 63) / 64), dim3(64), 0, s, st, n);
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s) {
+    int64_t n = 2 * n_complex;
+    int64_t blocks = (n + AHOM_WG - 1) / AHOM_WG;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    if (prec == 0) hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (double*)p, n);
+    else hipLaunchKernelGGL(k_zero<float>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (float*)p, n);
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s) {
+    int64_t blocks = (m + AHOM_WG - 1) / AHOM_WG;
+    if (blocks > 4096) blocks = 4096;
+    if (prec == 0) hipLaunchKernelGGL(k_reorder<double>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, a);
+    else hipLaunchKernelGGL(k_reorder<float>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, a);
+    return AHOM_CHECK_LAUNCH();
+}

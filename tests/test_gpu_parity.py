@@ -1,0 +1,230 @@
+"""GPU parity: libahom (HIP, gfx950) against the CPU FP64 oracle.
+
+Every case prints its name, shape and seed before the GPU call.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import closed_forms as CF
+from oracle import elasticity as E
+from oracle.dft import NaiveDFT, SnfFFT, make_transform
+from tests.gpu_util import perm_between, fields_to_tensors, tensors_to_fields, rel_err
+
+pytestmark = pytest.mark.gpu
+
+ahom = pytest.importorskip("paper_1605_05712_amd.ahom")
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+DFT_MATS = [
+    [[8, 0], [0, 8]],
+    [[8, -4], [2, 7]],              # rank-1 (1, 64)
+    [[4, 4], [-4, 4]],              # quincunx (4, 8)
+    [[6, 2], [1, 5]],               # m = 28
+    [[-6, 1], [2, 3]],              # negative determinant
+    [[105, 0], [0, 3]],             # odd radices 3, 5, 7
+    [[2, 0], [0, 1]],               # m = 2
+    [[24, 0], [0, 360]],            # (24, 360) ragged tiles
+    [[4096, 8192], [0, 1]],         # rank-1, split axis
+    [[3, 1, 0], [0, 2, 1], [1, 0, 4]],
+    [[12, 0, 0], [0, 6, 0], [3, 0, 4]],
+    [[8, 0, 0], [0, 8, 0], [0, 0, 8]],
+    [[128, 0, 0], [16, 64, 0], [0, 0, 1]],
+]
+
+
+@pytest.mark.parametrize("prec", [ahom.FP64, ahom.FP32_MIXED])
+@pytest.mark.parametrize("M", DFT_MATS)
+def test_dft_parity(M, prec):
+    P = ahom.Pattern(M)
+    say("dft", M, "m", P.m, "prec", prec)
+    T = NaiveDFT(M) if P.m <= 1024 else SnfFFT(M)
+    rng = np.random.default_rng(P.m)
+    a = rng.standard_normal(P.m) + 1j * rng.standard_normal(P.m)
+    ip = perm_between(P.points(), T.points)        # library order -> oracle order
+    ref = T.forward(a[ip])
+    ifr = perm_between(T.freqs, P.freqs())          # oracle freq order -> library order
+    out = P.dft(a, -1, prec)
+    tol = 1e-12 if prec == ahom.FP64 else 2e-6
+    assert rel_err(out, ref[ifr]) < tol
+    back = P.dft(out, +1, prec)
+    assert rel_err(back, a) < tol
+
+
+def solver_case(M, lame, phase_fn, eps_bar, prec=ahom.FP64, tol=0.0, max_iter=5, init=None):
+    P = ahom.Pattern(M)
+    d = len(M)
+    pts = P.points()
+    ph = phase_fn(pts, P.m)
+    S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=4)
+    S.set_material(lame, ph)
+    return P, S, pts, ph
+
+
+def oracle_case(M, lame, phase_fn, eps_bar, **kw):
+    T = make_transform(M)
+    ph = phase_fn(T.points, T.m)
+    lame = np.asarray(lame, np.float64)
+    r = E.basic_scheme(M, ph, lame, E.default_reference(lame), eps_bar, transform=T, **kw)
+    return T, r
+
+
+LAM2 = np.array(synth.LAMINATE_LAME)
+LAM3 = np.array([[1.0, 0.5], [4.0, 2.0], [2.0, 3.0]])
+
+
+def lam_phase(pts, m):
+    return synth.laminate_phase(pts, m)
+
+
+def rnd_phase(seed, n):
+    def f(pts, m):
+        # phase depends on exact coordinates only, so both orders agree
+        key = (pts.astype(np.int64) * np.array([7919, 104729, 1299709][: pts.shape[1]])).sum(axis=1)
+        return (np.random.default_rng(seed).permutation(97)[np.abs(key) % 97] % n).astype(np.uint8)
+    return f
+
+
+FIELD_CASES = [
+    ("laminate 16x16", [[16, 0], [0, 16]], LAM2, lam_phase, 2),
+    ("laminate 24x40", [[24, 0], [0, 40]], LAM2, lam_phase, 2),
+    ("rank-1 2-D", [[8, -4], [2, 7]], LAM3, rnd_phase(1, 3), 2),
+    ("quincunx", [[16, 16], [-16, 16]], LAM3, rnd_phase(2, 3), 2),
+    ("odd 15x21", [[15, 0], [0, 21]], LAM3, rnd_phase(3, 3), 2),
+    ("3-D 8^3", [[8, 0, 0], [0, 8, 0], [0, 0, 8]], LAM3, rnd_phase(4, 3), 3),
+    ("3-D sheared", [[12, 0, 0], [0, 6, 0], [3, 0, 4]], LAM3, rnd_phase(5, 3), 3),
+    ("3-D rank-1 4096", synth.rank1_matrix(4096, [1, 77, (77 * 77) % 4096]).tolist(), LAM3, rnd_phase(6, 3), 3),
+    ("3-D 16x16x2", [[16, 0, 0], [0, 16, 0], [0, 0, 2]], LAM3, rnd_phase(7, 3), 3),
+]
+
+
+@pytest.mark.parametrize("name,M,lame,pf,d", FIELD_CASES, ids=[c[0] for c in FIELD_CASES])
+def test_fields_after_fixed_iterations(name, M, lame, pf, d):
+    """FP64 strain after N updates, residual history and mean stress: <= 1e-10 relative."""
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((d, d))
+    eps_bar = 0.5 * (A + A.T)
+    N = 6
+    say("fields", name, M, "N", N)
+    P, S, pts, ph = solver_case(M, lame, pf, eps_bar, tol=0.0, max_iter=N)
+    out = S.solve(eps_bar[None] if d == 3 else np.pad(eps_bar, ((0, 1), (0, 1)))[None], want_strain=True)
+    assert out["status"] == ahom.AHOM_W_NOT_CONVERGED and out["iters"][0] == N
+    T, r = oracle_case(M, lame, pf, eps_bar, fixed_iters=N)
+    ip = perm_between(T.points, pts)  # oracle order -> library order
+    ref = tensors_to_fields(r.eps[:, :, ip])
+    assert rel_err(out["strain"][0], ref) < 1e-10
+    hist = S.history(0)
+    assert len(hist) == N + 1
+    assert np.allclose(hist, r.history, rtol=1e-10, atol=0)
+    ms = out["mean_stress"][0][:d, :d]
+    assert np.allclose(ms, r.mean_stress, rtol=1e-10, atol=1e-12 * np.abs(r.mean_stress).max())
+
+
+def test_converged_ceff_laminate_and_symmetry():
+    M = [[32, 0], [0, 32]]
+    say("ceff laminate", M)
+    P = ahom.Pattern(M)
+    S = ahom.Solver(P, tol=1e-10, max_iter=2000)
+    S.set_material(LAM2, synth.laminate_phase(P.points(), P.m))
+    C, it = S.effective_stiffness()
+    T = make_transform(M)
+    Cref, runs = E.effective_stiffness(M, synth.laminate_phase(T.points, T.m), LAM2, E.default_reference(LAM2), tol=1e-10, transform=T)
+    assert list(it) == [r.iters for r in runs]
+    assert rel_err(C, Cref) < 1e-10
+    assert np.allclose(C, C.T, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec", [ahom.FP64, ahom.FP32_MIXED])
+def test_exact_laminate_pin(prec):
+    """M = [[4096, 8192], [0, 1]]: all frequencies along the normal; closed form."""
+    M = [[4096, 8192], [0, 1]]
+    say("exact laminate", M, prec)
+    P = ahom.Pattern(M)
+    S = ahom.Solver(P, precision=prec, tol=1e-12 if prec == ahom.FP64 else 1e-6, max_iter=50)
+    S.set_material(LAM2, synth.laminate_phase(P.points(), P.m))
+    C, it = S.effective_stiffness()
+    ex = CF.laminate_milton(*LAM2, 0.5, [1, 2])
+    assert rel_err(C, ex) < (1e-10 if prec == ahom.FP64 else 1e-5)
+
+
+def test_homogeneous_zero_iterations():
+    M = [[6, 2, 0], [1, 5, 0], [0, 0, 4]]
+    say("homogeneous", M)
+    P = ahom.Pattern(M)
+    S = ahom.Solver(P, tol=1e-12, max_iter=10)
+    S.set_material([[1.2, 0.7]], np.zeros(P.m, np.uint8))
+    C, it = S.effective_stiffness()
+    assert list(it) == [0] * 6
+    assert np.allclose(C, E.tensor4_to_mandel(E.iso_tensor(1.2, 0.7, 3)), atol=1e-13)
+
+
+def test_init_matches_oracle():
+    """A given initial fluctuation: fields and residual history match the oracle."""
+    M = [[12, 0], [4, 10]]
+    d = 2
+    say("init", M)
+    P = ahom.Pattern(M)
+    pf = rnd_phase(9, 3)
+    rng = np.random.default_rng(3)
+    eps_bar = np.array([[0.2, 0.1], [0.1, -0.3]])
+    T = make_transform(M)
+    init_o = rng.standard_normal((2, 2, T.m))
+    init_o = 0.5 * (init_o + init_o.transpose(1, 0, 2)) * 0.1
+    r = E.basic_scheme(M, pf(T.points, T.m), LAM3, E.default_reference(LAM3), eps_bar, init=init_o, transform=T, fixed_iters=4)
+    ip = perm_between(T.points, P.points())
+    S = ahom.Solver(P, tol=0.0, max_iter=4)
+    S.set_material(LAM3, pf(P.points(), P.m))
+    init_l = tensors_to_fields(init_o[:, :, ip])[None]
+    out = S.solve(np.pad(eps_bar, ((0, 1), (0, 1)))[None], init=init_l, want_strain=True)
+    assert rel_err(out["strain"][0], tensors_to_fields(r.eps[:, :, ip])) < 1e-10
+    assert np.allclose(S.history(0), r.history, rtol=1e-9)
+
+
+def test_stiffness_field_equals_phase_table():
+    M = [[8, 0, 0], [0, 8, 0], [0, 0, 4]]
+    say("stiffness field", M)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(10, 3)(P.points(), P.m)
+    S1 = ahom.Solver(P, tol=0.0, max_iter=5)
+    S1.set_material(LAM3, ph)
+    S2 = ahom.Solver(P, tol=0.0, max_iter=5)
+    S2.set_stiffness_field(LAM3[ph])
+    eb = np.eye(3)[None] * 0.01
+    a = S1.solve(eb, want_strain=True)["strain"]
+    b = S2.solve(eb, want_strain=True)["strain"]
+    assert np.array_equal(a, b)
+
+
+def test_divergence_and_material_errors():
+    M = [[16, 0], [0, 16]]
+    P = ahom.Pattern(M)
+    say("divergence", M)
+    S = ahom.Solver(P, tol=1e-8, max_iter=400)
+    S.set_material(LAM2, synth.laminate_phase(P.points(), P.m))
+    S.set_reference(0.2, 0.1)
+    out = S.solve(np.eye(3)[None], allow=(ahom.AHOM_E_DIVERGED,))
+    assert out["status"] == ahom.AHOM_E_DIVERGED
+    with pytest.raises(ahom.AhomError) as ex:
+        S.set_material([[1.0, -1.0]], np.zeros(P.m, np.uint8))
+    assert ex.value.code == ahom.AHOM_E_MATERIAL
+
+
+def test_repeat_solve_is_bitwise_deterministic():
+    M = [[16, 0, 0], [0, 16, 0], [0, 0, 16]]
+    say("determinism", M)
+    P = ahom.Pattern(M)
+    S = ahom.Solver(P, tol=0.0, max_iter=3)
+    S.set_material(LAM3, rnd_phase(12, 3)(P.points(), P.m))
+    eb = np.tile(np.eye(3), (2, 1, 1)) * 0.01
+    a = S.solve(eb, want_strain=True)
+    b = S.solve(eb, want_strain=True)
+    assert np.array_equal(a["strain"], b["strain"])
+    assert np.array_equal(a["mean_stress"], b["mean_stress"])
