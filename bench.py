@@ -1,0 +1,206 @@
+"""Benchmark: lattice-point updates/s of the generalized Basic Scheme on one MI355X.
+
+Workload (3-D generalized Hashin structure, Sec. 4.2 shape): coated confocal
+ellipsoid, semi-axes (0.15, 0.2, 0.3), coating 0.1 of the cell, rotated by
+seeded Euler angles; core E = 10, coating E = 0.5, neutral matrix, nu = 0.3;
+pattern M = diag(128, 128, 128) (m = 2^21 points); the 6 Mandel unit loads
+solved together.  A step is one iteration of Algorithm 1 for all 6 loads
+(every pass of the path), inputs resident in HBM.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "lattice-point updates/s per iteration; time-to-1e-6 residual vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def mandel_loads():
+    import numpy as np
+    r = 1.0 / math.sqrt(2.0)
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    out = np.zeros((6, 3, 3))
+    for k, (i, j) in enumerate(pairs):
+        v = 1.0 if i == j else r
+        out[k, i, j] = v
+        out[k, j, i] = v
+    return out
+
+
+def workload(n=128):
+    import numpy as np
+    import synth
+    from paper_1605_05712_amd import ahom
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "hashin_c2.json")))
+    M = np.diag([n, n, n]).astype(np.int64)
+    P = ahom.Pattern(M)
+    geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
+    ph = synth.hashin_phase(P.points(), P.m, geom)
+    lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+    return P, ph, lame, g
+
+
+def e_eff_from_ceff(C, g):
+    """e_eff of Sec. 5.1 for the special load eps0 (by linearity of the 6 columns)."""
+    import numpy as np
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    eps0 = np.array(g["eps0"])
+    v = np.array([eps0[i, j] * (1.0 if i == j else math.sqrt(2.0)) for i, j in pairs])
+    s = C @ v
+    ref = np.array(g["ceff_eps0"])
+    refv = np.array([ref[i, j] * (1.0 if i == j else math.sqrt(2.0)) for i, j in pairs])
+    return float(np.linalg.norm(s - refv) / np.linalg.norm(refv))
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
+    src = open(os.path.join(ROOT, "paper_1605_05712_amd", "csrc", "ahom_kernels.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or rec.get("kernel_source_sha") != sha:
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(n=128, n_iter=1):
+    """Oracle (CPU FP64) on a bounded sample of the same workload: one load, n_iter updates."""
+    code = f"""
+import json, os, sys, time
+import numpy as np
+sys.path.insert(0, {ROOT!r})
+import synth
+from oracle import elasticity as E
+from oracle.dft import make_transform
+g = json.load(open(os.path.join({ROOT!r}, 'tests', 'golden', 'hashin_c2.json')))
+M = [[{n},0,0],[0,{n},0],[0,0,{n}]]
+T = make_transform(M)
+geom = dict(c=np.array(g['c']), rho_c=g['rho_c'], rho_e=g['rho_e'], R=np.array(g['R']))
+ph = synth.hashin_phase(T.points, T.m, geom)
+lame = np.array([g['lame_core'], g['lame_coating'], g['lame_matrix']])
+t0 = time.perf_counter()
+E.basic_scheme(M, ph, lame, E.default_reference(lame), E.unit_loads(3)[0], transform=T, fixed_iters={n_iter})
+dt = time.perf_counter() - t0
+print(json.dumps(dict(seconds=dt, m=T.m)))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        return None
+    rec = json.loads(out.stdout.strip().splitlines()[-1])
+    return dict(value=rec["m"] * n_iter / rec["seconds"], unit="lattice-point updates/s", cores=1, kind="oracle",
+                sample=f"1 load (Mandel e11) x {n_iter} update(s) on diag({n},{n},{n}) in FP64, single thread; "
+                       f"{rec['seconds']:.1f} s incl. the residual evaluations")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(load cases shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    torch.cuda.set_device(0)
+    from paper_1605_05712_amd import ahom
+
+    print(f"[bench] building workload diag({args.size},{args.size},{args.size})", file=sys.stderr, flush=True)
+    P, ph, lame, g = workload(args.size)
+    loads = mandel_loads()
+    nload = loads.shape[0]
+
+    def make(prec, tol, max_iter, check):
+        S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=check)
+        S.set_material(lame, ph)
+        return S
+
+    # ---- throughput: fixed number of iterations, FP64 (plain scheme)
+    results = {}
+    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
+        Sw = make(prec, 0.0, max(args.warmup, 1) - 1, max(args.warmup, 1))
+        Sw.solve(loads)
+        del Sw
+        S = make(prec, 0.0, args.steps - 1, args.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.solve(loads)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dev_ms, enq = S.last_timing()
+        assert enq == args.steps
+        ms_step = (t1 - t0) * 1e3 / args.steps
+        ms, by = S.pass_times(5)
+        results[name] = dict(ms_per_step=ms_step, device_ms_per_step=dev_ms / args.steps,
+                             value=P.m * nload / (ms_step * 1e-3), pass_ms=ms.tolist(), pass_bytes=by.tolist())
+        print(f"[bench] {name}: {ms_step:.3f} ms/step, passes {np.round(ms, 4).tolist()} ms", file=sys.stderr, flush=True)
+        del S
+
+    main_res = results["fp64"]
+    ms, by = np.array(main_res["pass_ms"]), np.array(main_res["pass_bytes"])
+    names = ["k_real"] + ["k_axis_fwd"] * ((len(ms) - 3) // 2) + ["k_spec"] + ["k_axis_inv"] * ((len(ms) - 3) // 2) + ["k_reduce"]
+    dom = int(np.argmax(ms))
+    achieved = by[dom] / (ms[dom] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic_record(names[dom]),
+                    kernel=names[dom], kernel_ms=round(float(ms[dom]), 4), algorithmic_bytes=float(by[dom]),
+                    all_passes={f"{i}:{n}": dict(ms=round(float(t), 4), GBs=round(float(b / (t * 1e-3) / 1e9), 1))
+                                for i, (n, t, b) in enumerate(zip(names, ms, by))})
+
+    # ---- time to the 1e-6 residual: plain FP64 vs FP32 mixed (all 6 loads)
+    ttt = None
+    if not args.no_ttt:
+        ttt = {}
+        for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
+            S = make(prec, 1e-6, 3000, 16)
+            C, it = S.effective_stiffness()
+            dev_ms, enq = S.last_timing()
+            ttt[name] = dict(ms=round(dev_ms, 2), iters=[int(v) for v in it], e_eff=round(e_eff_from_ceff(C, g), 6),
+                             ceff_asym=float(np.max(np.abs(C - C.T))))
+            print(f"[bench] time-to-1e-6 {name}: {dev_ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
+            del S
+        ttt["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["fp32"]["ms"], 3)
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.size)
+
+    line = dict(
+        metric=METRIC, value=round(main_res["value"], 1), unit="lattice-point updates/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(main_res["ms_per_step"], 4), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=f"3-D generalized Hashin coated ellipsoid on M=diag({args.size},{args.size},{args.size}), "
+                             f"6 Mandel unit loads per step, plain Basic Scheme FP64", m=P.m, loads=nload,
+                    pattern=f"diag({args.size},{args.size},{args.size})"),
+        roofline=roofline, cpu_baseline=cpu,
+        fp32_mixed=dict(value=round(results["fp32"]["value"], 1), ms_per_step=round(results["fp32"]["ms_per_step"], 4)),
+        device_ms_per_step=round(main_res["device_ms_per_step"], 4),
+        time_to_1e6=ttt,
+    )
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -178,6 +178,19 @@ int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters);
 int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* iterations_enqueued);
 
 /*
+ * Per-pass device timing (profiling mode): runs n_iter iterations of the
+ * last solve's load set from eps(0) = eps_bar (no stopping), with a HIP event
+ * pair around every pass kernel on the solver's stream.  ms[p] receives the
+ * mean duration of pass p over the iterations, in launch order within an
+ * iteration: real-space turnaround, forward middle axes, spectral
+ * turnaround, inverse middle axes, reduction.  bytes[p] receives the
+ * algorithmic bytes that pass must move per launch (each state field read
+ * and written once, plus phase ids or traction terms).  *n_pass = number of
+ * passes (<= cap).
+ */
+int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes, int cap, int* n_pass);
+
+/*
  * Per-iteration residual history r(0..n) of load k of the last solve:
  * writes up to cap doubles, *count = number written.
  */

@@ -36,7 +36,7 @@ EXPORTS = [
     "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_destroy", "ahom_pattern_info",
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
-    "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_history",
+    "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_history", "ahom_solver_pass_times",
 ]
 
 
@@ -69,6 +69,7 @@ _lib.ahom_solve.argtypes = [_P, ct.c_int, _dp, _P, _P, _ip, _dp, _dp, ct.c_int]
 _lib.ahom_effective_stiffness.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
+_lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
 
 
 class AhomError(RuntimeError):
@@ -219,6 +220,14 @@ class Solver:
         enq = ct.c_int()
         _check(_lib.ahom_solver_last_timing(self._h, ct.byref(ms), ct.byref(enq)))
         return ms.value, enq.value
+
+    def pass_times(self, n_iter=10):
+        """Mean ms per pass and algorithmic bytes per launch (profiling mode)."""
+        ms = np.zeros(32, np.float64)
+        by = np.zeros(32, np.float64)
+        n = ct.c_int()
+        _check(_lib.ahom_solver_pass_times(self._h, n_iter, _ptr(ms, ct.c_double), _ptr(by, ct.c_double), 32, ct.byref(n)))
+        return ms[: n.value], by[: n.value]
 
     def history(self, load=0, cap=100000):
         out = np.zeros(cap, np.float64)

@@ -609,6 +609,66 @@ int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters) {
     return rc;
 }
 
+int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes, int cap, int* n_pass) {
+    if (!s || !ms || !n_pass || n_iter < 1 || s->last_nload < 1) return fail(AHOM_E_ARG, "bad pass-timing arguments (solve first)");
+    const Plan& P = s->pat->plan;
+    const int nload = s->last_nload;
+    const int np = 2 * (P.D - 2) + 3;
+    if (cap < np) return fail(AHOM_E_ARG, "cap too small");
+    hipStream_t st = s->stream;
+    std::vector<hipEvent_t> ev(np + 1);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    std::vector<double> acc(np, 0.0);
+    if (ahom_launch_reset(s->d_st, nload, st)) return fail(AHOM_E_DEVICE, "reset");
+    if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)nload * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    FillArgs f{};
+    f.buf = s->d_buf0; f.eps_bar = s->d_epsbar; f.S = P.S; f.row = P.S / P.ax[0].slen; f.nfield = s->ncomp;
+    if (ahom_launch_fill(s->prec, f, nload, st)) return fail(AHOM_E_DEVICE, "fill");
+    ReduceArgs r{};
+    r.st = s->d_st; r.sig_part = s->d_sig; r.res_part = s->d_res; r.hist = s->d_hist;
+    r.n_real = s->g_real.nwg; r.n_spec = s->g_spec.nwg; r.hist_cap = s->hist_cap; r.m = P.m;
+    r.tol = -1.0; r.max_iter = 1 << 30;
+    for (int it = 0; it < n_iter; ++it) {
+        int p = 0;
+        HIPCHK(hipEventRecord(ev[p], st));
+        if (ahom_launch_real(s->prec, s->dim, REAL_TURN, s->real_args(REAL_TURN), s->g_real.nwg, nload, s->g_real.lds, st)) return fail(AHOM_E_DEVICE, "real");
+        HIPCHK(hipEventRecord(ev[++p], st));
+        for (int a = 1; a <= P.D - 2; ++a) {
+            if (ahom_launch_axis(s->prec, -1, s->axis_args(a), s->g_axis[a].nwg, s->ncomp, nload, s->g_axis[a].lds, st)) return fail(AHOM_E_DEVICE, "axis");
+            HIPCHK(hipEventRecord(ev[++p], st));
+        }
+        if (ahom_launch_spec(s->prec, s->dim, s->spec_args(), s->g_spec.nwg, nload, s->g_spec.lds, st)) return fail(AHOM_E_DEVICE, "spec");
+        HIPCHK(hipEventRecord(ev[++p], st));
+        for (int a = P.D - 2; a >= 1; --a) {
+            if (ahom_launch_axis(s->prec, +1, s->axis_args(a), s->g_axis[a].nwg, s->ncomp, nload, s->g_axis[a].lds, st)) return fail(AHOM_E_DEVICE, "axis");
+            HIPCHK(hipEventRecord(ev[++p], st));
+        }
+        if (ahom_launch_reduce(s->dim, r, nload, st)) return fail(AHOM_E_DEVICE, "reduce");
+        HIPCHK(hipEventRecord(ev[++p], st));
+        HIPCHK(hipEventSynchronize(ev[p]));
+        for (int q = 0; q < np; ++q) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+            acc[q] += t;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    const double es = (double)s->es();
+    const double field = (double)P.S * es;      // one stored field
+    for (int q = 0; q < np; ++q) {
+        ms[q] = acc[q] / n_iter;
+        if (!bytes) continue;
+        double b = 0.0;
+        if (q == 0) b = 2.0 * s->ncomp * field + (double)P.m * (s->d_lame_pts ? 16.0 : 1.0);
+        else if (q == np - 1) b = 0.0;
+        else if (q == P.D - 1) b = 2.0 * s->ncomp * field + 2.0 * s->nt * field;
+        else b = 2.0 * s->ncomp * field;
+        bytes[q] = b * nload;
+    }
+    *n_pass = np;
+    return AHOM_OK;
+}
+
 int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* enq) {
     if (!s) return fail(AHOM_E_ARG, "null solver");
     if (ms) *ms = s->last_ms;
