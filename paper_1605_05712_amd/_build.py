@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libahom.so")
 
-SOURCES = ["ahom_plan.cpp", "ahom_kernels.hip", "ahom_api.hip"]
+SOURCES = ["ahom_plan.cpp", "ahom_kernels.hip", "ahom_fast.hip", "ahom_api.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -133,8 +134,13 @@ struct ahom_solver {
     double* d_epsbar = nullptr;
     double* d_real = nullptr;
     int hist_cap = 0;
-    // geometry
+    // geometry: generic kernels (always available) and the power-of-two fast path
     PassGeom g_real, g_spec, g_axis[AHOM_MAX_AXES];
+    bool f_real = false, f_spec = false, f_axis[AHOM_MAX_AXES] = {};
+    int fn_real = 0, fn_spec = 0, fn_axis[AHOM_MAX_AXES] = {};
+    bool use_fast = true;
+    int n_real_wg() const { return f_real ? fn_real : g_real.nwg; }
+    int n_spec_wg() const { return f_spec ? fn_spec : g_spec.nwg; }
     // timing
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double last_ms = 0;
@@ -162,8 +168,8 @@ struct ahom_solver {
         HIPCHK(hipMalloc(&d_tbuf, (size_t)nload * nt * P.S * es()));
         HIPCHK(hipMalloc((void**)&d_st, nload * sizeof(LoadState)));
         HIPCHK(hipHostMalloc((void**)&h_st, nload * sizeof(LoadState), hipHostMallocDefault));
-        HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * g_real.nwg * ncomp * sizeof(double)));
-        HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * g_spec.nwg * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * std::max(g_real.nwg, fn_real) * ncomp * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * std::max(g_spec.nwg, fn_spec) * sizeof(double)));
         hist_cap = cfg.max_iter + 1;
         HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
@@ -235,26 +241,35 @@ struct ahom_solver {
         return a;
     }
 
+    int launch_real_turn(int nload, hipStream_t s) {
+        if (f_real) return ahom_launch_fast_real(prec, dim, pat->plan.ax[0].len, real_args(REAL_TURN), fn_real, nload, s);
+        return ahom_launch_real(prec, dim, REAL_TURN, real_args(REAL_TURN), g_real.nwg, nload, g_real.lds, s);
+    }
+    int launch_axis(int a, int dir, int nload, hipStream_t s) {
+        if (f_axis[a]) return ahom_launch_fast_axis(prec, dir, pat->plan.ax[a].len, axis_args(a), fn_axis[a], ncomp, nload, s);
+        return ahom_launch_axis(prec, dir, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s);
+    }
+    int launch_spec(int nload, hipStream_t s) {
+        if (f_spec) return ahom_launch_fast_spec(prec, dim, pat->plan.ax[pat->plan.D - 1].len, spec_args(), fn_spec, nload, s);
+        return ahom_launch_spec(prec, dim, spec_args(), g_spec.nwg, nload, g_spec.lds, s);
+    }
+
     int enqueue_iteration(int nload) {
         const Plan& P = pat->plan;
         hipStream_t s = stream;
-        if (ahom_launch_real(prec, dim, REAL_TURN, real_args(REAL_TURN), g_real.nwg, nload, g_real.lds, s))
-            return fail(AHOM_E_DEVICE, "launch k_real failed");
+        if (launch_real_turn(nload, s)) return fail(AHOM_E_DEVICE, "launch real-space pass failed");
         for (int a = 1; a <= P.D - 2; ++a)
-            if (ahom_launch_axis(prec, -1, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s))
-                return fail(AHOM_E_DEVICE, "launch k_axis failed");
-        if (ahom_launch_spec(prec, dim, spec_args(), g_spec.nwg, nload, g_spec.lds, s))
-            return fail(AHOM_E_DEVICE, "launch k_spec failed");
+            if (launch_axis(a, -1, nload, s)) return fail(AHOM_E_DEVICE, "launch axis pass failed");
+        if (launch_spec(nload, s)) return fail(AHOM_E_DEVICE, "launch spectral pass failed");
         for (int a = P.D - 2; a >= 1; --a)
-            if (ahom_launch_axis(prec, +1, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s))
-                return fail(AHOM_E_DEVICE, "launch k_axis failed");
+            if (launch_axis(a, +1, nload, s)) return fail(AHOM_E_DEVICE, "launch axis pass failed");
         ReduceArgs r{};
         r.st = d_st;
         r.sig_part = d_sig;
         r.res_part = d_res;
         r.hist = d_hist;
-        r.n_real = g_real.nwg;
-        r.n_spec = g_spec.nwg;
+        r.n_real = n_real_wg();
+        r.n_spec = n_spec_wg();
         r.hist_cap = hist_cap;
         r.m = P.m;
         r.tol = cfg.tol;
@@ -415,6 +430,31 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
         for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
         for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
         if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, s->prec, &s->g_axis[a]))) return bad(rc);
+    }
+    {
+        const char* env = getenv("AHOM_GENERIC_ONLY");
+        s->use_fast = !(env && env[0] == '1');
+    }
+    if (s->use_fast) {
+        FastGeom fg;
+        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, &fg)) {
+            const int64_t I = P.S / P.ax[0].slen;
+            s->f_real = true;
+            s->fn_real = (int)((I + fg.NC - 1) / fg.NC);
+        }
+        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, &fg)) {
+            const int64_t nc = P.S / P.ax[P.D - 1].len;
+            s->f_spec = true;
+            s->fn_spec = (int)((nc + fg.NC - 1) / fg.NC);
+        }
+        for (int a = 1; a <= P.D - 2; ++a)
+            if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, &fg)) {
+                int64_t O = 1, I = 1;
+                for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
+                for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
+                s->f_axis[a] = true;
+                s->fn_axis[a] = (int)((O * I + fg.NC - 1) / fg.NC);
+            }
     }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
         return bad(fail(AHOM_E_DEVICE, "event create"));
@@ -626,21 +666,21 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
     if (ahom_launch_fill(s->prec, f, nload, st)) return fail(AHOM_E_DEVICE, "fill");
     ReduceArgs r{};
     r.st = s->d_st; r.sig_part = s->d_sig; r.res_part = s->d_res; r.hist = s->d_hist;
-    r.n_real = s->g_real.nwg; r.n_spec = s->g_spec.nwg; r.hist_cap = s->hist_cap; r.m = P.m;
+    r.n_real = s->n_real_wg(); r.n_spec = s->n_spec_wg(); r.hist_cap = s->hist_cap; r.m = P.m;
     r.tol = -1.0; r.max_iter = 1 << 30;
     for (int it = 0; it < n_iter; ++it) {
         int p = 0;
         HIPCHK(hipEventRecord(ev[p], st));
-        if (ahom_launch_real(s->prec, s->dim, REAL_TURN, s->real_args(REAL_TURN), s->g_real.nwg, nload, s->g_real.lds, st)) return fail(AHOM_E_DEVICE, "real");
+        if (s->launch_real_turn(nload, st)) return fail(AHOM_E_DEVICE, "real");
         HIPCHK(hipEventRecord(ev[++p], st));
         for (int a = 1; a <= P.D - 2; ++a) {
-            if (ahom_launch_axis(s->prec, -1, s->axis_args(a), s->g_axis[a].nwg, s->ncomp, nload, s->g_axis[a].lds, st)) return fail(AHOM_E_DEVICE, "axis");
+            if (s->launch_axis(a, -1, nload, st)) return fail(AHOM_E_DEVICE, "axis");
             HIPCHK(hipEventRecord(ev[++p], st));
         }
-        if (ahom_launch_spec(s->prec, s->dim, s->spec_args(), s->g_spec.nwg, nload, s->g_spec.lds, st)) return fail(AHOM_E_DEVICE, "spec");
+        if (s->launch_spec(nload, st)) return fail(AHOM_E_DEVICE, "spec");
         HIPCHK(hipEventRecord(ev[++p], st));
         for (int a = P.D - 2; a >= 1; --a) {
-            if (ahom_launch_axis(s->prec, +1, s->axis_args(a), s->g_axis[a].nwg, s->ncomp, nload, s->g_axis[a].lds, st)) return fail(AHOM_E_DEVICE, "axis");
+            if (s->launch_axis(a, +1, nload, st)) return fail(AHOM_E_DEVICE, "axis");
             HIPCHK(hipEventRecord(ev[++p], st));
         }
         if (ahom_launch_reduce(s->dim, r, nload, st)) return fail(AHOM_E_DEVICE, "reduce");

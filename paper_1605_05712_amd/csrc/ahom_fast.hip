@@ -1,0 +1,676 @@
+// Pass kernels specialised on a power-of-two transform length L <= 256.
+//
+// Same passes and data layout as the generic kernels (ahom_kernels.hip); the
+// 1-D FFT of each column is a two-level factorisation L = N1 * N2 held in
+// registers: thread tau < N1 of a column takes the N2 samples
+// x[tau + N1 q], does a radix-N2 DFT, multiplies by W_L^{tau k_a}, exchanges
+// through LDS once and finishes with N2/N1 radix-N1 DFTs, giving
+// X[k_a + N2 k_b].  All index arithmetic is compile-time.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "ahom_internal.h"
+#include "ahom_kernels.h"
+
+namespace {
+
+template <typename T> struct CT;
+template <> struct CT<double> { using t = double2; };
+template <> struct CT<float> { using t = float2; };
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) { return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }
+
+// cos / sin of 2 pi j / 16
+constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                             -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                             0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                             1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                             -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// v * W_16^j with W_16 = exp(DIR 2 pi i / 16)
+template <int DIR, int J, typename C> __device__ __forceinline__ C tw16(C v) {
+    using T = decltype(C{}.x);
+    constexpr int j = J % 16;
+    if constexpr (j == 0) return v;
+    else if constexpr (j == 4) return DIR < 0 ? C{v.y, -v.x} : C{-v.y, v.x};
+    else if constexpr (j == 8) return C{-v.x, -v.y};
+    else if constexpr (j == 12) return DIR < 0 ? C{-v.y, v.x} : C{v.y, -v.x};
+    else {
+        const T c = (T)kC16[j], s = (T)(DIR < 0 ? -kS16[j] : kS16[j]);
+        return C{v.x * c - v.y * s, v.x * s + v.y * c};
+    }
+}
+
+// in-place DFT of N = 1, 2, 4, 8, 16 points, natural order in and out
+template <int N, int DIR, typename C> __device__ __forceinline__ void dft(C* v) {
+    if constexpr (N == 2) {
+        C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (N == 4) {
+        C a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        C c = cadd(v[1], v[3]), d = tw16<DIR, 4>(csub(v[1], v[3]));
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, d);
+        v[3] = csub(b, d);
+    } else if constexpr (N == 8) {
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
+        dft<4, DIR>(e);
+        dft<4, DIR>(o);
+        o[1] = tw16<DIR, 2>(o[1]);
+        o[2] = tw16<DIR, 4>(o[2]);
+        o[3] = tw16<DIR, 6>(o[3]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    } else if constexpr (N == 16) {
+        // n = n1 + 4 n2, k = k2 + 4 k1
+        C a[4][4];
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+#pragma unroll
+            for (int n2 = 0; n2 < 4; ++n2) a[n1][n2] = v[n1 + 4 * n2];
+            dft<4, DIR>(a[n1]);
+        }
+        a[1][1] = tw16<DIR, 1>(a[1][1]); a[1][2] = tw16<DIR, 2>(a[1][2]); a[1][3] = tw16<DIR, 3>(a[1][3]);
+        a[2][1] = tw16<DIR, 2>(a[2][1]); a[2][2] = tw16<DIR, 4>(a[2][2]); a[2][3] = tw16<DIR, 6>(a[2][3]);
+        a[3][1] = tw16<DIR, 3>(a[3][1]); a[3][2] = tw16<DIR, 6>(a[3][2]); a[3][3] = tw16<DIR, 9>(a[3][3]);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            C t[4] = {a[0][k2], a[1][k2], a[2][k2], a[3][k2]};
+            dft<4, DIR>(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) v[k2 + 4 * k1] = t[k1];
+        }
+    }
+}
+
+template <int L> struct Split {
+    static constexpr int N2 = L >= 128 ? 16 : (L >= 32 ? 8 : L);
+    static constexpr int N1 = L / N2;
+    static_assert(N1 * N2 == L && (N1 == 1 || N2 % N1 == 0), "unsupported length");
+};
+
+constexpr int pow2floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+// columns per workgroup: NF fields x NC columns x N1 threads <= 512 threads,
+// NF x NC x (L + 1) elements <= 50 KB of LDS
+template <typename T, int L, int NF> struct Geo {
+    static constexpr int es = 2 * (int)sizeof(T);
+    static constexpr int N1 = Split<L>::N1;
+    static constexpr int CS = L + 1;
+    static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
+    static constexpr int by_thr = 512 / (NF * N1);
+    static constexpr int NC = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
+    static constexpr int THREADS = ((NF * NC * N1 + 63) / 64) * 64;
+    static constexpr int TILE = NF * NC * CS;  // complex elements of LDS tile
+};
+
+// FFT of `ncols` columns (stride CS) of an LDS tile in place; twl = W_L^j in LDS.
+template <int L, int DIR, int CS, typename C>
+__device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
+    constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2;
+    const int s = threadIdx.x;
+    const int col = s / N1, tau = s % N1;
+    const bool act = col < ncols;
+    C* base = lds + col * CS;
+    C v[N2];
+    if constexpr (N1 == 1) {
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) v[q] = base[q];
+            dft<N2, DIR>(v);
+#pragma unroll
+            for (int q = 0; q < N2; ++q) base[q] = v[q];
+        }
+        __syncthreads();
+        return;
+    } else {
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < N2; ++q) v[q] = base[tau + N1 * q];
+        }
+        __syncthreads();
+        if (act) {
+            dft<N2, DIR>(v);
+#pragma unroll
+            for (int ka = 1; ka < N2; ++ka) {
+                const C w = twl[tau * ka];
+                v[ka] = DIR < 0 ? cmul(v[ka], w) : cmulc(v[ka], w);
+            }
+#pragma unroll
+            for (int ka = 0; ka < N2; ++ka) base[ka * N1 + tau] = v[ka];
+        }
+        __syncthreads();
+        constexpr int B = N2 / N1;
+        if (act) {
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * N1 + t];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                dft<N1, DIR>(v + b * N1);
+#pragma unroll
+                for (int kb = 0; kb < N1; ++kb) base[tau + N1 * b + N2 * kb] = v[b * N1 + kb];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ void load_twiddles(C* twl, const C* tw, int L) {
+    for (int j = threadIdx.x; j < L; j += blockDim.x) twl[j] = tw[j];
+}
+
+template <typename C>
+__device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
+    const double2 a = tw64[ax.sp_off1 + (j % ax.spB)];
+    const double2 b = tw64[ax.sp_off2 + (j / ax.spB)];
+    const double2 w = cmul(a, b);
+    using T = decltype(C{}.x);
+    return C{(T)w.x, (T)w.y};
+}
+
+template <int DIM> struct Comp;
+template <> struct Comp<3> { static constexpr int N = 6, NP = 3, NT = 3; };
+template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
+
+template <typename T> __device__ __forceinline__ T* smem() {
+    extern __shared__ __align__(16) unsigned char ahom_fast_smem[];
+    return reinterpret_cast<T*>(ahom_fast_smem);
+}
+
+// fixed-order block sum of NV doubles (result in thread 0); scratch: NV * blockDim doubles
+template <int NV>
+__device__ void block_sum(double* vals, double* scratch) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int c = 0; c < NV; ++c) scratch[c * nt + tid] = vals[c];
+    __syncthreads();
+    int n = nt;
+    while (n > 1) {
+        const int h = (n + 1) / 2;
+        if (tid < n - h)
+            for (int c = 0; c < NV; ++c) scratch[c * nt + tid] += scratch[c * nt + tid + h];
+        __syncthreads();
+        n = h;
+    }
+    if (tid == 0)
+        for (int c = 0; c < NV; ++c) vals[c] = scratch[c * nt];
+}
+
+// exact (A kappa) mod emax, centred; double path while products stay below 2^53
+__device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_t* kap, int64_t* N, int dim) {
+    int half = 0;
+    const double inv = 1.0 / (double)f.emax;
+    const double e = (double)f.emax;
+    for (int i = 0; i < dim; ++i) {
+        int64_t r;
+        if (f.emax <= (int64_t(1) << 24)) {
+            double x = 0.0;
+            for (int s = 0; s < dim; ++s) x += (double)f.A[i][s] * (double)kap[s];
+            double q = floor(x * inv);
+            double rr = x - q * e;
+            if (rr < 0) rr += e;
+            if (rr >= e) rr -= e;
+            r = (int64_t)rr;
+        } else {
+            r = 0;
+            for (int s = 0; s < dim; ++s) r = (r + (f.A[i][s] % f.emax) * kap[s]) % f.emax;
+        }
+        if (2 * r >= f.emax) r -= f.emax;
+        if (2 * r == -f.emax) half = 1;
+        N[i] = r;
+    }
+    return half;
+}
+
+}  // namespace
+
+// =============================================================================
+// real-space turnaround along axis 0
+// =============================================================================
+template <typename T, int DIM, int L>
+__global__ void __launch_bounds__(512) kf_real(RealArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    using G = Geo<T, L, NP>;
+    constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.y;
+    const LoadState& st = a.st[load];
+    if (st.done) return;
+    const AxisDesc& ax = P.ax[0];
+    const int64_t I = P.S / H;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int ncol = (int)((I - c0) < NC ? (I - c0) : NC);
+    const int tid = threadIdx.x;
+    C* Z = smem<C>();
+    C* twl = Z + G::TILE;
+    const int src_buf = st.iter & 1;
+    const C* src = reinterpret_cast<const C*>(src_buf ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+    C* dst = reinterpret_cast<C*>(src_buf ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
+    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+
+    for (int e = tid; e < H * NC; e += blockDim.x) {
+        const int k = e / NC, j = e % NC;
+        if (j >= ncol) continue;
+        const int64_t col = c0 + j;
+        C w = C{(T)1, (T)0};
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int fa = 2 * p, fb = 2 * p + 1;
+            C A = src[(int64_t)fa * P.S + (int64_t)k * I + col];
+            C B = fb < NCOMP ? src[(int64_t)fb * P.S + (int64_t)k * I + col] : C{(T)0, (T)0};
+            if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
+            if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
+            C* Zp = Z + (p * NC + j) * CS;
+            Zp[k] = C{A.x - B.y, A.y + B.x};
+            if (k > 0 && 2 * k != L) Zp[L - k] = C{A.x + B.y, B.x - A.y};
+        }
+    }
+    __syncthreads();
+    fft_cols<L, +1, CS>(Z, NP * NC, twl);
+
+    double sig[NCOMP];
+#pragma unroll
+    for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
+    const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        const int n = e / NC, j = e % NC;
+        if (j >= ncol) continue;
+        const int64_t pt = (int64_t)n * I + c0 + j;
+        T lam, mu;
+        if (a.lame_pts) {
+            lam = (T)a.lame_pts[2 * pt];
+            mu = (T)a.lame_pts[2 * pt + 1];
+        } else {
+            const int ph = a.phase[pt];
+            lam = (T)a.lame_tab[2 * ph];
+            mu = (T)a.lame_tab[2 * ph + 1];
+        }
+        T eps[NCOMP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const C z = Z[(p * NC + j) * CS + n];
+            eps[2 * p] = z.x;
+            if (2 * p + 1 < NCOMP) eps[2 * p + 1] = z.y;
+        }
+        const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+        const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+        T tau[NCOMP];
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) {
+            const bool diag = DIM == 3 ? c < 3 : c < 2;
+            sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
+            tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            Z[(p * NC + j) * CS + n] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
+    }
+    __syncthreads();
+    fft_cols<L, -1, CS>(Z, NP * NC, twl);
+
+    for (int e = tid; e < H * NC; e += blockDim.x) {
+        const int k = e / NC, j = e % NC;
+        if (j >= ncol) continue;
+        const int64_t col = c0 + j;
+        C w = C{(T)1, (T)0};
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+        const int km = k == 0 ? 0 : L - k;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const C* Zp = Z + (p * NC + j) * CS;
+            const C zk = Zp[k], zm = Zp[km];
+            C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+            C B = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
+            if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
+            dst[(int64_t)(2 * p) * P.S + (int64_t)k * I + col] = A;
+            if (2 * p + 1 < NCOMP) dst[(int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col] = B;
+        }
+    }
+    __syncthreads();
+    block_sum<NCOMP>(sig, reinterpret_cast<double*>(Z));
+    if (tid == 0)
+        for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NCOMP + c] = sig[c];
+}
+
+// =============================================================================
+// middle axes
+// =============================================================================
+template <typename T, int L, int DIR>
+__global__ void __launch_bounds__(512) kf_axis(AxisArgs a) {
+    using C = typename CT<T>::t;
+    using G = Geo<T, L, 1>;
+    constexpr int NC = G::NC, CS = G::CS;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.z;
+    int par = 0;
+    if (a.st) {
+        const LoadState& st = a.st[load];
+        if (st.done) return;
+        par = (st.iter + 1) & 1;
+    }
+    const AxisDesc& ax = P.ax[a.axis];
+    int64_t O = 1, I = 1;
+    for (int b = 0; b < a.axis; ++b) O *= (a.slen0_full && b == 0) ? P.ax[0].len : P.ax[b].slen;
+    for (int b = a.axis + 1; b < P.D; ++b) I *= P.ax[b].slen;
+    const int64_t ncols = O * I;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+    C* X = smem<C>();
+    C* twl = X + G::TILE;
+    int64_t* cbase = reinterpret_cast<int64_t*>(twl + L);
+    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)blockIdx.y * a.field_stride;
+    const int tid = threadIdx.x;
+    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+    if (tid < NC) {
+        const int64_t col = c0 + tid;
+        cbase[tid] = (col / I) * (int64_t)L * I + (col % I);
+    }
+    __syncthreads();
+    const bool rowmajor = I >= NC;
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        int j, l;
+        if (rowmajor) { l = e / NC; j = e % NC; } else { j = e / L; l = e % L; }
+        if (j >= ncol) continue;
+        C v = base[cbase[j] + (int64_t)l * I];
+        if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+        X[j * CS + l] = v;
+    }
+    __syncthreads();
+    fft_cols<L, DIR, CS>(X, NC, twl);
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        int j, l;
+        if (rowmajor) { l = e / NC; j = e % NC; } else { j = e / L; l = e % L; }
+        if (j >= ncol) continue;
+        C v = X[j * CS + l];
+        if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+        base[cbase[j] + (int64_t)l * I] = v;
+    }
+}
+
+// =============================================================================
+// spectral turnaround along the last axis
+// =============================================================================
+template <typename T, int DIM, int L>
+__global__ void __launch_bounds__(512) kf_spec(SpecArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NCOMP = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    using G = Geo<T, L, NCOMP>;
+    constexpr int NC = G::NC, CS = G::CS;
+    const Plan& P = *a.plan;
+    const int load = blockIdx.y;
+    const LoadState& st = a.st[load];
+    if (st.done) return;
+    const int par = (st.iter + 1) & 1;
+    const int D = P.D;
+    const int64_t ncols = P.S / L;
+    const int64_t c0 = (int64_t)blockIdx.x * NC;
+    const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+    const int tid = threadIdx.x;
+    C* F = smem<C>();
+    C* twl = F + G::TILE;
+    int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
+    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+    C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
+    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, L);
+    if (tid < NC) {
+        int64_t o = c0 + tid;
+        int64_t kap[3] = {0, 0, 0};
+        int64_t k0 = 0;
+        for (int b = D - 2; b >= 0; --b) {
+            const int64_t sl = P.ax[b].slen;
+            const int64_t kk = o % sl;
+            o /= sl;
+            kap[P.ax[b].snf] += P.ax[b].mult * kk;
+            if (b == 0) k0 = kk;
+        }
+        kb[tid * 4 + 0] = kap[0];
+        kb[tid * 4 + 1] = kap[1];
+        kb[tid * 4 + 2] = kap[2];
+        kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
+    }
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        const int j = e / L, l = e % L;
+        if (j >= ncol) continue;
+        const int64_t addr = (c0 + j) * L + l;
+#pragma unroll
+        for (int f = 0; f < NCOMP; ++f) F[(f * NC + j) * CS + l] = base[(int64_t)f * P.S + addr];
+    }
+    __syncthreads();
+    fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
+
+    const double* eb = a.eps_bar + (int64_t)load * NCOMP;
+    const T inv_m = (T)(1.0 / (double)P.m);
+    const T mu0 = (T)a.mu0, beta = (T)a.beta;
+    const int last_snf = P.ax[D - 1].snf;
+    const int64_t last_mult = P.ax[D - 1].mult;
+    double res = 0.0;
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        const int j = e / L, l = e % L;
+        if (j >= ncol) continue;
+        int64_t kap[3] = {kb[j * 4 + 0], kb[j * 4 + 1], kb[j * 4 + 2]};
+        kap[last_snf] += last_mult * l;
+        C* fp[NCOMP];
+#pragma unroll
+        for (int f = 0; f < NCOMP; ++f) fp[f] = F + (f * NC + j) * CS + l;
+        if (kap[0] == 0 && kap[1] == 0 && kap[2] == 0) {
+#pragma unroll
+            for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)eb[f], (T)0};
+            continue;
+        }
+        int64_t N[3];
+        const int half = centred_numerators(P.fm, kap, N, DIM);
+        if (half && !ahom_self_conjugate(P.fm, kap)) {
+#pragma unroll
+            for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)0, (T)0};
+            continue;
+        }
+        double hd[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            hd[i] = 0.0;
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) hd[i] += (double)P.fm.MT[i][q] * (double)N[q];
+        }
+        double hn = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) hn += hd[i] * hd[i];
+        hn = rsqrt(hn);
+        T xi[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) xi[i] = (T)(hd[i] * hn);
+        C tv[NCOMP];
+#pragma unroll
+        for (int f = 0; f < NCOMP; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
+        C t[NT];
+        if constexpr (DIM == 3) {
+            const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
+            t[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
+            t[1] = C{T01.x * xi[0] + T11.x * xi[1] + T12.x * xi[2], T01.y * xi[0] + T11.y * xi[1] + T12.y * xi[2]};
+            t[2] = C{T02.x * xi[0] + T12.x * xi[1] + T22.x * xi[2], T02.y * xi[0] + T12.y * xi[1] + T22.y * xi[2]};
+        } else {
+            const C T00 = tv[0], T11 = tv[1], T01 = tv[2];
+            t[0] = C{T00.x * xi[0] + T01.x * xi[1], T00.y * xi[0] + T01.y * xi[1]};
+            t[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
+        }
+        const int64_t spos = (c0 + j) * L + l;
+        double r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const C old = tb[(int64_t)c * P.S + spos];
+            const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
+            r2 += dx * dx + dy * dy;
+            tb[(int64_t)c * P.S + spos] = t[c];
+        }
+        res += (double)kb[j * 4 + 3] * r2;
+        C xt = C{(T)0, (T)0};
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * t[i].x; xt.y += xi[i] * t[i].y; }
+        const T im0 = (T)1 / mu0;
+        C v[DIM];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) v[i] = C{(t[i].x - beta * xt.x * xi[i]) * im0, (t[i].y - beta * xt.y * xi[i]) * im0};
+        if constexpr (DIM == 3) {
+            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+            *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
+            *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
+            *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
+            *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+        } else {
+            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+            *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+        }
+    }
+    __syncthreads();
+    fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
+    for (int e = tid; e < L * NC; e += blockDim.x) {
+        const int j = e / L, l = e % L;
+        if (j >= ncol) continue;
+        const int64_t addr = (c0 + j) * L + l;
+#pragma unroll
+        for (int f = 0; f < NCOMP; ++f) base[(int64_t)f * P.S + addr] = F[(f * NC + j) * CS + l];
+    }
+    __syncthreads();
+    double rv[1] = {res};
+    block_sum<1>(rv, reinterpret_cast<double*>(F));
+    if (tid == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
+}
+
+// ----------------------------------------------------------------- dispatch
+namespace {
+
+template <typename T, int L, int NF>
+FastGeom geom_of(int kind) {
+    using G = Geo<T, L, NF>;
+    FastGeom g;
+    g.NC = G::NC;
+    g.threads = G::THREADS;
+    // tile + twiddles + per-column integers (axis: base offsets, spec: kappa + weight)
+    size_t extra = kind == FAST_AXIS ? (size_t)G::NC * 8 : (kind == FAST_SPEC ? (size_t)G::NC * 32 : 0);
+    size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
+    // block reduction reuses the tile: NV doubles per thread
+    const size_t red = (size_t)G::THREADS * 8 * (kind == FAST_REAL ? 6 : 1);
+    g.lds = lds > red ? lds : red;
+    return g;
+}
+
+template <typename T>
+bool geom_T(int kind, int dim, int L, FastGeom* g) {
+    const int nf = kind == FAST_REAL ? (dim == 3 ? 3 : 2) : (kind == FAST_SPEC ? (dim == 3 ? 6 : 3) : 1);
+#define AHOM_G(LL)                                                     \
+    case LL:                                                           \
+        if (nf == 1) *g = geom_of<T, LL, 1>(kind);                     \
+        else if (nf == 2) *g = geom_of<T, LL, 2>(kind);                \
+        else if (nf == 3) *g = geom_of<T, LL, 3>(kind);                \
+        else *g = geom_of<T, LL, 6>(kind);                             \
+        return true;
+    switch (L) {
+        AHOM_G(1) AHOM_G(2) AHOM_G(4) AHOM_G(8) AHOM_G(16) AHOM_G(32) AHOM_G(64) AHOM_G(128) AHOM_G(256)
+        default: return false;
+    }
+#undef AHOM_G
+}
+
+template <typename F>
+int launch(F fn, const FastGeom& g) {
+    if (g.lds > 64 * 1024)
+        if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess) return -1;
+    return 0;
+}
+
+}  // namespace
+
+bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g) {
+    return prec == 0 ? geom_T<double>(kind, dim, L, g) : geom_T<float>(kind, dim, L, g);
+}
+
+#define AHOM_FAST_SWITCH(MACRO) \
+    switch (L) {                \
+        MACRO(1) MACRO(2) MACRO(4) MACRO(8) MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) \
+        default: return -1;     \
+    }
+
+int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int nwg, int nload, hipStream_t s) {
+    FastGeom g;
+    if (!ahom_fast_geom(prec, FAST_REAL, dim, L, &g)) return -1;
+    dim3 grid(nwg, nload), block(g.threads);
+#define AHOM_FR(LL)                                                                                   \
+    case LL: {                                                                                        \
+        if (prec == 0) {                                                                              \
+            if (dim == 3) { auto fn = kf_real<double, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
+            else { auto fn = kf_real<double, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+        } else {                                                                                      \
+            if (dim == 3) { auto fn = kf_real<float, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
+            else { auto fn = kf_real<float, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }         \
+        }                                                                                             \
+        break;                                                                                        \
+    }
+    AHOM_FAST_SWITCH(AHOM_FR)
+#undef AHOM_FR
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int nwg, int nfield, int nload, hipStream_t s) {
+    FastGeom g;
+    if (!ahom_fast_geom(prec, FAST_AXIS, 3, L, &g)) return -1;
+    dim3 grid(nwg, nfield, nload), block(g.threads);
+#define AHOM_FA(LL)                                                                                   \
+    case LL: {                                                                                        \
+        if (prec == 0) {                                                                              \
+            if (dir < 0) { auto fn = kf_axis<double, LL, -1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
+            else { auto fn = kf_axis<double, LL, 1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }       \
+        } else {                                                                                      \
+            if (dir < 0) { auto fn = kf_axis<float, LL, -1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
+            else { auto fn = kf_axis<float, LL, 1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+        }                                                                                             \
+        break;                                                                                        \
+    }
+    AHOM_FAST_SWITCH(AHOM_FA)
+#undef AHOM_FA
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int nwg, int nload, hipStream_t s) {
+    FastGeom g;
+    if (!ahom_fast_geom(prec, FAST_SPEC, dim, L, &g)) return -1;
+    dim3 grid(nwg, nload), block(g.threads);
+#define AHOM_FS(LL)                                                                                   \
+    case LL: {                                                                                        \
+        if (prec == 0) {                                                                              \
+            if (dim == 3) { auto fn = kf_spec<double, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
+            else { auto fn = kf_spec<double, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+        } else {                                                                                      \
+            if (dim == 3) { auto fn = kf_spec<float, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
+            else { auto fn = kf_spec<float, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }         \
+        }                                                                                             \
+        break;                                                                                        \
+    }
+    AHOM_FAST_SWITCH(AHOM_FS)
+#undef AHOM_FS
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}

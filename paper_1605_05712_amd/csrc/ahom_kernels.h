@@ -100,3 +100,14 @@ int ahom_launch_fill(int prec, const FillArgs& a, int nload, hipStream_t s);
 int ahom_launch_reset(LoadState* st, int n, hipStream_t s);
 int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s);
 int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s);
+
+// ---- power-of-two fast path (ahom_fast.hip)
+enum { FAST_REAL = 0, FAST_AXIS = 1, FAST_SPEC = 2 };
+struct FastGeom {
+    int NC = 1, threads = 64;
+    size_t lds = 0;
+};
+bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g);
+int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int nwg, int nload, hipStream_t s);
+int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int nwg, int nfield, int nload, hipStream_t s);
+int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int nwg, int nload, hipStream_t s);

@@ -228,3 +228,32 @@ def test_repeat_solve_is_bitwise_deterministic():
     b = S.solve(eb, want_strain=True)
     assert np.array_equal(a["strain"], b["strain"])
     assert np.array_equal(a["mean_stress"], b["mean_stress"])
+
+
+FASTGEN_CASES = [
+    ("3-D 64^3", [[64, 0, 0], [0, 64, 0], [0, 0, 64]], ahom.FP64),
+    ("3-D 32x64x128", [[32, 0, 0], [0, 64, 0], [0, 0, 128]], ahom.FP64),
+    ("3-D 256x16x16 fp32", [[16, 0, 0], [0, 16, 0], [0, 0, 256]], ahom.FP32_MIXED),
+    ("2-D 256x128 sheared", [[128, 0], [64, 256]], ahom.FP64),
+    ("rank-1 2^16", [[65536, 0], [1, 1]], ahom.FP64),
+]
+
+
+@pytest.mark.parametrize("name,M,prec", FASTGEN_CASES, ids=[c[0] for c in FASTGEN_CASES])
+def test_fast_path_matches_generic_path(name, M, prec, monkeypatch):
+    """The power-of-two kernels and the generic mixed-radix kernels agree."""
+    say("fast-vs-generic", name, M, prec)
+    P = ahom.Pattern(M)
+    d = len(M)
+    ph = rnd_phase(13, 3)(P.points(), P.m)
+    eb = (np.eye(3) * 0.01)[None]
+    outs = []
+    for generic in ("0", "1"):
+        monkeypatch.setenv("AHOM_GENERIC_ONLY", generic)
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=4)
+        S.set_material(LAM3, ph)
+        outs.append(S.solve(eb, want_strain=True))
+        del S
+    tol = 1e-12 if prec == ahom.FP64 else 2e-5
+    assert rel_err(outs[0]["strain"], outs[1]["strain"]) < tol
+    assert np.allclose(outs[0]["resid"], outs[1]["resid"], rtol=tol * 10)
