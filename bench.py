@@ -115,6 +115,9 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
+    ap.add_argument("--fp64-only", action="store_true", help="throughput of the FP64 path only (profiling runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -124,6 +127,15 @@ def main():
     import numpy as np
     import torch
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(calib_copy_bytes=n, dispatches=3)))
+        return
     from paper_1605_05712_amd import ahom
 
     print(f"[bench] building workload diag({args.size},{args.size},{args.size})", file=sys.stderr, flush=True)
@@ -138,7 +150,8 @@ def main():
 
     # ---- throughput: fixed number of iterations, FP64 (plain scheme)
     results = {}
-    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
+    precs = (("fp64", ahom.FP64),) if args.fp64_only else (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED))
+    for name, prec in precs:
         Sw = make(prec, 0.0, max(args.warmup, 1) - 1, max(args.warmup, 1))
         Sw.solve(loads)
         del Sw
@@ -195,7 +208,8 @@ def main():
                              f"6 Mandel unit loads per step, plain Basic Scheme FP64", m=P.m, loads=nload,
                     pattern=f"diag({args.size},{args.size},{args.size})"),
         roofline=roofline, cpu_baseline=cpu,
-        fp32_mixed=dict(value=round(results["fp32"]["value"], 1), ms_per_step=round(results["fp32"]["ms_per_step"], 4)),
+        fp32_mixed=(dict(value=round(results["fp32"]["value"], 1), ms_per_step=round(results["fp32"]["ms_per_step"], 4))
+                    if "fp32" in results else None),
         device_ms_per_step=round(main_res["device_ms_per_step"], 4),
         time_to_1e6=ttt,
     )
