@@ -65,7 +65,8 @@ def e_eff_from_ceff(C, g):
 
 def traffic_record(kernel):
     """HBM bytes per launch from committed rocprofv3 counter runs, if current."""
-    src = open(os.path.join(ROOT, "paper_1605_05712_amd", "csrc", "ahom_kernels.hip"), "rb").read()
+    src = b"".join(open(os.path.join(ROOT, "paper_1605_05712_amd", "csrc", f), "rb").read()
+                   for f in ("ahom_kernels.hip", "ahom_fast.hip"))
     sha = hashlib.sha256(src).hexdigest()[:16]
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
