@@ -113,7 +113,9 @@ constexpr int pow2floor(int v) {
 template <typename T, int L, int NF> struct Geo {
     static constexpr int es = 2 * (int)sizeof(T);
     static constexpr int N1 = Split<L>::N1;
-    static constexpr int CS = L + 1;
+    // column stride: room for the padded exchange (N2 rows of N1 + 1) and odd,
+    // so that 8 consecutive columns start in distinct LDS bank groups
+    static constexpr int CS = N1 == 1 ? L + 1 : L + Split<L>::N2 + 1;
     static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
     static constexpr int by_thr = 512 / (NF * N1);
     static constexpr int NC = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
@@ -121,7 +123,10 @@ template <typename T, int L, int NF> struct Geo {
     static constexpr int TILE = NF * NC * CS;  // complex elements of LDS tile
 };
 
-// FFT of `ncols` columns (stride CS) of an LDS tile in place; twl = W_L^j in LDS.
+// FFT of `ncols` columns (stride CS) of an LDS tile in place.  twl holds the
+// inter-stage twiddles as twl[ka * N1 + tau] = W_L^{tau ka}; the exchange
+// between the stages uses rows of N1 + 1 elements so that the N1 threads of a
+// column read distinct LDS banks.
 template <int L, int DIR, int CS, typename C>
 __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
     constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2;
@@ -150,11 +155,11 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
             dft<N2, DIR>(v);
 #pragma unroll
             for (int ka = 1; ka < N2; ++ka) {
-                const C w = twl[tau * ka];
+                const C w = twl[ka * N1 + tau];
                 v[ka] = DIR < 0 ? cmul(v[ka], w) : cmulc(v[ka], w);
             }
 #pragma unroll
-            for (int ka = 0; ka < N2; ++ka) base[ka * N1 + tau] = v[ka];
+            for (int ka = 0; ka < N2; ++ka) base[ka * (N1 + 1) + tau] = v[ka];
         }
         __syncthreads();
         constexpr int B = N2 / N1;
@@ -162,7 +167,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
             for (int b = 0; b < B; ++b)
 #pragma unroll
-                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * N1 + t];
+                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * (N1 + 1) + t];
         }
         __syncthreads();
         if (act) {
@@ -177,9 +182,14 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
     }
 }
 
-template <typename C>
-__device__ __forceinline__ void load_twiddles(C* twl, const C* tw, int L) {
-    for (int j = threadIdx.x; j < L; j += blockDim.x) twl[j] = tw[j];
+// inter-stage twiddles twl[ka * N1 + tau] = W_L^{tau ka} from the table tw[j] = W_L^j
+template <int L, typename C>
+__device__ __forceinline__ void load_twiddles(C* twl, const C* tw) {
+    constexpr int N1 = Split<L>::N1;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        const int ka = j / N1, tau = j % N1;
+        twl[j] = tw[ka * tau];
+    }
 }
 
 template <typename C>
@@ -269,7 +279,7 @@ __global__ void __launch_bounds__(512) kf_real(RealArgs a) {
     const int src_buf = st.iter & 1;
     const C* src = reinterpret_cast<const C*>(src_buf ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
     C* dst = reinterpret_cast<C*>(src_buf ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
-    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
 
     for (int e = tid; e < H * NC; e += blockDim.x) {
         const int k = e / NC, j = e % NC;
@@ -384,7 +394,7 @@ __global__ void __launch_bounds__(512) kf_axis(AxisArgs a) {
     int64_t* cbase = reinterpret_cast<int64_t*>(twl + L);
     C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)blockIdx.y * a.field_stride;
     const int tid = threadIdx.x;
-    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
     if (tid < NC) {
         const int64_t col = c0 + tid;
         cbase[tid] = (col / I) * (int64_t)L * I + (col % I);
@@ -435,7 +445,7 @@ __global__ void __launch_bounds__(512) kf_spec(SpecArgs a) {
     int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
     C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
     C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
-    load_twiddles(twl, reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, L);
+    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off);
     if (tid < NC) {
         int64_t o = c0 + tid;
         int64_t kap[3] = {0, 0, 0};
