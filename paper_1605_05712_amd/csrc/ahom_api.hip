@@ -137,8 +137,16 @@ struct ahom_solver {
     // geometry: generic kernels (always available) and the power-of-two fast path
     PassGeom g_real, g_spec, g_axis[AHOM_MAX_AXES];
     bool f_real = false, f_spec = false, f_axis[AHOM_MAX_AXES] = {};
-    int fn_real = 0, fn_spec = 0, fn_axis[AHOM_MAX_AXES] = {};
+    int fn_real = 0, fn_spec = 0, fn_axis[AHOM_MAX_AXES] = {};   // tiles per load (and field)
+    size_t fl_real = 0, fl_spec = 0, fl_axis[AHOM_MAX_AXES] = {}; // LDS bytes per workgroup
+    int ncu = 256;
     bool use_fast = true;
+    // persistent grid: at most the workgroups that fit on the device at once
+    int persistent_grid(int64_t total, size_t lds) const {
+        int per_cu = lds ? (int)((160 * 1024) / lds) : 8;
+        per_cu = std::max(1, std::min(per_cu, 8));
+        return (int)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)ncu * per_cu));
+    }
     int n_real_wg() const { return f_real ? fn_real : g_real.nwg; }
     int n_spec_wg() const { return f_spec ? fn_spec : g_spec.nwg; }
     // timing
@@ -242,15 +250,28 @@ struct ahom_solver {
     }
 
     int launch_real_turn(int nload, hipStream_t s) {
-        if (f_real) return ahom_launch_fast_real(prec, dim, pat->plan.ax[0].len, real_args(REAL_TURN), fn_real, nload, s);
+        if (f_real) {
+            RealArgs ra = real_args(REAL_TURN);
+            ra.nload = nload;
+            return ahom_launch_fast_real(prec, dim, pat->plan.ax[0].len, ra, (int64_t)fn_real * nload, ncu, s);
+        }
         return ahom_launch_real(prec, dim, REAL_TURN, real_args(REAL_TURN), g_real.nwg, nload, g_real.lds, s);
     }
     int launch_axis(int a, int dir, int nload, hipStream_t s) {
-        if (f_axis[a]) return ahom_launch_fast_axis(prec, dir, pat->plan.ax[a].len, axis_args(a), fn_axis[a], ncomp, nload, s);
+        if (f_axis[a]) {
+            AxisArgs aa = axis_args(a);
+            aa.nload = nload;
+            aa.nfield = ncomp;
+            return ahom_launch_fast_axis(prec, dir, pat->plan.ax[a].len, aa, (int64_t)fn_axis[a] * ncomp * nload, ncu, s);
+        }
         return ahom_launch_axis(prec, dir, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s);
     }
     int launch_spec(int nload, hipStream_t s) {
-        if (f_spec) return ahom_launch_fast_spec(prec, dim, pat->plan.ax[pat->plan.D - 1].len, spec_args(), fn_spec, nload, s);
+        if (f_spec) {
+            SpecArgs sa = spec_args();
+            sa.nload = nload;
+            return ahom_launch_fast_spec(prec, dim, pat->plan.ax[pat->plan.D - 1].len, sa, (int64_t)fn_spec * nload, ncu, s);
+        }
         return ahom_launch_spec(prec, dim, spec_args(), g_spec.nwg, nload, g_spec.lds, s);
     }
 
@@ -435,17 +456,26 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
         const char* env = getenv("AHOM_GENERIC_ONLY");
         s->use_fast = !(env && env[0] == '1');
     }
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int n = 0;
+            if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) s->ncu = n;
+        }
+    }
     if (s->use_fast) {
         FastGeom fg;
         if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, &fg)) {
             const int64_t I = P.S / P.ax[0].slen;
             s->f_real = true;
             s->fn_real = (int)((I + fg.NC - 1) / fg.NC);
+            s->fl_real = fg.lds;
         }
         if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, &fg)) {
             const int64_t nc = P.S / P.ax[P.D - 1].len;
             s->f_spec = true;
             s->fn_spec = (int)((nc + fg.NC - 1) / fg.NC);
+            s->fl_spec = fg.lds;
         }
         for (int a = 1; a <= P.D - 2; ++a)
             if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, &fg)) {
@@ -454,6 +484,7 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
                 for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
                 s->f_axis[a] = true;
                 s->fn_axis[a] = (int)((O * I + fg.NC - 1) / fg.NC);
+                s->fl_axis[a] = fg.lds;
             }
     }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)

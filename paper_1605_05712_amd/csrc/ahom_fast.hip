@@ -10,14 +10,55 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ahom_internal.h"
 #include "ahom_kernels.h"
 
 namespace {
 
+// plain aggregates (not HIP vector types) so that register arrays of them are
+// promoted out of scratch; same layout as double2 / float2
+struct alignas(16) cplx64 { double x, y; };
+struct alignas(8) cplx32 { float x, y; };
 template <typename T> struct CT;
-template <> struct CT<double> { using t = double2; };
-template <> struct CT<float> { using t = float2; };
+template <> struct CT<double> { using t = cplx64; };
+template <> struct CT<float> { using t = cplx32; };
+
+// global-memory element access through native 2-vectors (one 16 B / 8 B
+// access, and no aggregate copy that would pin register arrays to scratch)
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cplx64 ldg(const cplx64* p) {
+    const v2d v = *reinterpret_cast<const v2d*>(p);
+    return cplx64{v.x, v.y};
+}
+__device__ __forceinline__ cplx32 ldg(const cplx32* p) {
+    const v2f v = *reinterpret_cast<const v2f*>(p);
+    return cplx32{v.x, v.y};
+}
+__device__ __forceinline__ void stg(cplx64* p, cplx64 c) {
+    v2d v;
+    v.x = c.x;
+    v.y = c.y;
+    *reinterpret_cast<v2d*>(p) = v;
+}
+__device__ __forceinline__ void stg(cplx32* p, cplx32 c) {
+    v2f v;
+    v.x = c.x;
+    v.y = c.y;
+    *reinterpret_cast<v2f*>(p) = v;
+}
+
+// compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).  Array
+// indices in the body are constants from the start, so register arrays are
+// split into scalars before any alloca promotion decision.
+template <int B, int E, typename F> __device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
 
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
@@ -113,9 +154,7 @@ constexpr int pow2floor(int v) {
 template <typename T, int L, int NF> struct Geo {
     static constexpr int es = 2 * (int)sizeof(T);
     static constexpr int N1 = Split<L>::N1;
-    // column stride: room for the padded exchange (N2 rows of N1 + 1) and odd,
-    // so that 8 consecutive columns start in distinct LDS bank groups
-    static constexpr int CS = N1 == 1 ? L + 1 : L + Split<L>::N2 + 1;
+    static constexpr int CS = L + 1;  // odd: consecutive columns start in distinct LDS banks
     static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
     static constexpr int by_thr = 512 / (NF * N1);
     static constexpr int NC = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
@@ -124,9 +163,9 @@ template <typename T, int L, int NF> struct Geo {
 };
 
 // FFT of `ncols` columns (stride CS) of an LDS tile in place.  twl holds the
-// inter-stage twiddles as twl[ka * N1 + tau] = W_L^{tau ka}; the exchange
-// between the stages uses rows of N1 + 1 elements so that the N1 threads of a
-// column read distinct LDS banks.
+// inter-stage twiddles as twl[ka * N1 + tau] = W_L^{tau ka}.  The exchange
+// between the stages stores row r, entry c at r * N1 + (c ^ (r % N1)) so that
+// the N1 threads of a column touch distinct LDS banks in both stages.
 template <int L, int DIR, int CS, typename C>
 __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
     constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2;
@@ -159,7 +198,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
                 v[ka] = DIR < 0 ? cmul(v[ka], w) : cmulc(v[ka], w);
             }
 #pragma unroll
-            for (int ka = 0; ka < N2; ++ka) base[ka * (N1 + 1) + tau] = v[ka];
+            for (int ka = 0; ka < N2; ++ka) base[ka * N1 + (tau ^ (ka & (N1 - 1)))] = v[ka];
         }
         __syncthreads();
         constexpr int B = N2 / N1;
@@ -167,7 +206,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
             for (int b = 0; b < B; ++b)
 #pragma unroll
-                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * (N1 + 1) + t];
+                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * N1 + (t ^ tau)];
         }
         __syncthreads();
         if (act) {
@@ -256,168 +295,265 @@ __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_
 
 }  // namespace
 
+
+// Work distribution of the pass kernels below: a persistent grid walks the
+// tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...; while tile t is being
+// transformed, the global loads of the next tile are already in flight into
+// registers (pre[]), so every workgroup overlaps HBM latency with its own
+// LDS work.  Partial sums are written per (load, tile) and reduced in a
+// fixed order.
+
 // =============================================================================
 // real-space turnaround along axis 0
 // =============================================================================
 template <typename T, int DIM, int L>
-__global__ void __launch_bounds__(512) kf_real(RealArgs a) {
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP>::THREADS)) kf_real(RealArgs a) {
     using C = typename CT<T>::t;
     constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
     using G = Geo<T, L, NP>;
-    constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1;
+    constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1, TH = G::THREADS;
+    constexpr int EPT = (H * NC + TH - 1) / TH;     // half-spectrum rows per thread
     const Plan& P = *a.plan;
-    const int load = blockIdx.y;
-    const LoadState& st = a.st[load];
-    if (st.done) return;
     const AxisDesc& ax = P.ax[0];
     const int64_t I = P.S / H;
-    const int64_t c0 = (int64_t)blockIdx.x * NC;
-    const int ncol = (int)((I - c0) < NC ? (I - c0) : NC);
+    const int64_t nct = (I + NC - 1) / NC;
+    const int64_t total = nct * a.nload;
     const int tid = threadIdx.x;
     C* Z = smem<C>();
     C* twl = Z + G::TILE;
-    const int src_buf = st.iter & 1;
-    const C* src = reinterpret_cast<const C*>(src_buf ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
-    C* dst = reinterpret_cast<C*>(src_buf ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
     load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
-
-    for (int e = tid; e < H * NC; e += blockDim.x) {
-        const int k = e / NC, j = e % NC;
-        if (j >= ncol) continue;
-        const int64_t col = c0 + j;
-        C w = C{(T)1, (T)0};
-        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const int fa = 2 * p, fb = 2 * p + 1;
-            C A = src[(int64_t)fa * P.S + (int64_t)k * I + col];
-            C B = fb < NCOMP ? src[(int64_t)fb * P.S + (int64_t)k * I + col] : C{(T)0, (T)0};
-            if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
-            if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
-            C* Zp = Z + (p * NC + j) * CS;
-            Zp[k] = C{A.x - B.y, A.y + B.x};
-            if (k > 0 && 2 * k != L) Zp[L - k] = C{A.x + B.y, B.x - A.y};
-        }
-    }
-    __syncthreads();
-    fft_cols<L, +1, CS>(Z, NP * NC, twl);
-
-    double sig[NCOMP];
-#pragma unroll
-    for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
     const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        const int n = e / NC, j = e % NC;
-        if (j >= ncol) continue;
-        const int64_t pt = (int64_t)n * I + c0 + j;
-        T lam, mu;
-        if (a.lame_pts) {
-            lam = (T)a.lame_pts[2 * pt];
-            mu = (T)a.lame_pts[2 * pt + 1];
-        } else {
-            const int ph = a.phase[pt];
-            lam = (T)a.lame_tab[2 * ph];
-            mu = (T)a.lame_tab[2 * ph + 1];
-        }
-        T eps[NCOMP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const C z = Z[(p * NC + j) * CS + n];
-            eps[2 * p] = z.x;
-            if (2 * p + 1 < NCOMP) eps[2 * p + 1] = z.y;
-        }
-        const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
-        const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
-        T tau[NCOMP];
-#pragma unroll
-        for (int c = 0; c < NCOMP; ++c) {
-            const bool diag = DIM == 3 ? c < 3 : c < 2;
-            sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
-            tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-            Z[(p * NC + j) * CS + n] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
-    }
-    __syncthreads();
-    fft_cols<L, -1, CS>(Z, NP * NC, twl);
 
-    for (int e = tid; e < H * NC; e += blockDim.x) {
-        const int k = e / NC, j = e % NC;
-        if (j >= ncol) continue;
-        const int64_t col = c0 + j;
-        C w = C{(T)1, (T)0};
-        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
-        const int km = k == 0 ? 0 : L - k;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const C* Zp = Z + (p * NC + j) * CS;
-            const C zk = Zp[k], zm = Zp[km];
-            C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
-            C B = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
-            if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
-            dst[(int64_t)(2 * p) * P.S + (int64_t)k * I + col] = A;
-            if (2 * p + 1 < NCOMP) dst[(int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col] = B;
+    C pre[EPT][NCOMP];
+    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
+        const int load = (int)(t / nct);
+        const int64_t c0 = (t % nct) * NC;
+        const LoadState& st = a.st[load];
+        if (st.done) return false;
+        const C* src = reinterpret_cast<const C*>((st.iter & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const int k = e / NC, j = e % NC;
+            if (e < H * NC && c0 + j < I) {
+                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                    constexpr int f = fc;
+                    pre[q][f] = ldg(src + (int64_t)f * P.S + (int64_t)k * I + c0 + j);
+                });
+            }
+        });
+        return true;
+    };
+
+    int64_t t = blockIdx.x;
+    bool have = t < total ? fetch(t) : false;
+    for (; t < total; t += gridDim.x) {
+        const bool cur = have;
+        const int load = (int)(t / nct);
+        const int64_t c0 = (t % nct) * NC;
+        const int ncol = (int)((I - c0) < NC ? (I - c0) : NC);
+        if (cur) {
+            // packed full spectra Z_p = A + i B from the half spectra
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int k = e / NC, j = e % NC;
+                if (e >= H * NC || j >= ncol) return;
+                C w = C{(T)1, (T)0};
+                if (ax.split) w = split_twiddle<C>(ax, a.tw64, ((c0 + j) / ax.qdiv) * (int64_t)k);
+                sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+                    constexpr int p = pc;
+                    C A = pre[q][2 * p];
+                    C B = C{(T)0, (T)0};
+                    if constexpr (2 * p + 1 < NCOMP) B = pre[q][2 * p + 1];
+                    if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
+                    if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
+                    C* Zp = Z + (p * NC + j) * CS;
+                    Zp[k] = C{A.x - B.y, A.y + B.x};
+                    if (k > 0 && 2 * k != L) Zp[L - k] = C{A.x + B.y, B.x - A.y};
+                });
+            });
         }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        have = tn < total ? fetch(tn) : false;
+        if (!cur) continue;
+        const LoadState& st = a.st[load];
+        C* dst = reinterpret_cast<C*>((st.iter & 1) ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
+        fft_cols<L, +1, CS>(Z, NP * NC, twl);
+
+        double sig[NCOMP];
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
+        for (int e = tid; e < L * NC; e += TH) {
+            const int n = e / NC, j = e % NC;
+            if (j >= ncol) continue;
+            const int64_t pt = (int64_t)n * I + c0 + j;
+            T lam, mu;
+            if (a.lame_pts) {
+                lam = (T)a.lame_pts[2 * pt];
+                mu = (T)a.lame_pts[2 * pt + 1];
+            } else {
+                const int ph = a.phase[pt];
+                lam = (T)a.lame_tab[2 * ph];
+                mu = (T)a.lame_tab[2 * ph + 1];
+            }
+            T eps[NCOMP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const C z = Z[(p * NC + j) * CS + n];
+                eps[2 * p] = z.x;
+                if (2 * p + 1 < NCOMP) eps[2 * p + 1] = z.y;
+            }
+            const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+            const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+            T tau[NCOMP];
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) {
+                const bool diag = DIM == 3 ? c < 3 : c < 2;
+                sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
+                tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+            }
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                Z[(p * NC + j) * CS + n] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
+        }
+        __syncthreads();
+        fft_cols<L, -1, CS>(Z, NP * NC, twl);
+
+        for (int e = tid; e < H * NC; e += TH) {
+            const int k = e / NC, j = e % NC;
+            if (j >= ncol) continue;
+            const int64_t col = c0 + j;
+            C w = C{(T)1, (T)0};
+            if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+            const int km = k == 0 ? 0 : L - k;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const C* Zp = Z + (p * NC + j) * CS;
+                const C zk = Zp[k], zm = Zp[km];
+                C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+                C B = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
+                if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
+                stg(dst + (int64_t)(2 * p) * P.S + (int64_t)k * I + col, A);
+                if (2 * p + 1 < NCOMP) stg(dst + (int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col, B);
+            }
+        }
+        __syncthreads();
+        block_sum<NCOMP>(sig, reinterpret_cast<double*>(Z));
+        if (tid == 0)
+            for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * nct + t % nct) * NCOMP + c] = sig[c];
+        __syncthreads();
     }
-    __syncthreads();
-    block_sum<NCOMP>(sig, reinterpret_cast<double*>(Z));
-    if (tid == 0)
-        for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NCOMP + c] = sig[c];
 }
 
 // =============================================================================
 // middle axes
 // =============================================================================
 template <typename T, int L, int DIR>
-__global__ void __launch_bounds__(512) kf_axis(AxisArgs a) {
+__global__ void __launch_bounds__((Geo<T, L, 1>::THREADS)) kf_axis(AxisArgs a) {
     using C = typename CT<T>::t;
     using G = Geo<T, L, 1>;
-    constexpr int NC = G::NC, CS = G::CS;
+    constexpr int NC = G::NC, CS = G::CS, TH = G::THREADS;
+    constexpr int EPT = (NC * L + TH - 1) / TH;
     const Plan& P = *a.plan;
-    const int load = blockIdx.z;
-    int par = 0;
-    if (a.st) {
-        const LoadState& st = a.st[load];
-        if (st.done) return;
-        par = (st.iter + 1) & 1;
-    }
     const AxisDesc& ax = P.ax[a.axis];
     int64_t O = 1, I = 1;
     for (int b = 0; b < a.axis; ++b) O *= (a.slen0_full && b == 0) ? P.ax[0].len : P.ax[b].slen;
     for (int b = a.axis + 1; b < P.D; ++b) I *= P.ax[b].slen;
     const int64_t ncols = O * I;
-    const int64_t c0 = (int64_t)blockIdx.x * NC;
-    const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+    const int64_t nct = (ncols + NC - 1) / NC;
+    const int64_t total = nct * a.nfield * a.nload;
+    const bool rowmajor = I >= NC;
+    const bool aligned = rowmajor && (I % NC) == 0;
+    const int tid = threadIdx.x;
     C* X = smem<C>();
     C* twl = X + G::TILE;
-    int64_t* cbase = reinterpret_cast<int64_t*>(twl + L);
-    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)blockIdx.y * a.field_stride;
-    const int tid = threadIdx.x;
     load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
-    if (tid < NC) {
-        const int64_t col = c0 + tid;
-        cbase[tid] = (col / I) * (int64_t)L * I + (col % I);
-    }
-    __syncthreads();
-    const bool rowmajor = I >= NC;
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        int j, l;
+
+    // element e of a tile -> (column j, position l)
+    auto map = [&](int e, int& j, int& l) __attribute__((always_inline)) {
         if (rowmajor) { l = e / NC; j = e % NC; } else { j = e / L; l = e % L; }
-        if (j >= ncol) continue;
-        C v = base[cbase[j] + (int64_t)l * I];
-        if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
-        X[j * CS + l] = v;
-    }
-    __syncthreads();
-    fft_cols<L, DIR, CS>(X, NC, twl);
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        int j, l;
-        if (rowmajor) { l = e / NC; j = e % NC; } else { j = e / L; l = e % L; }
-        if (j >= ncol) continue;
-        C v = X[j * CS + l];
-        if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
-        base[cbase[j] + (int64_t)l * I] = v;
+    };
+    auto addr = [&](int64_t c0, int64_t cbase_aligned, int j, int l) __attribute__((always_inline)) -> int64_t {
+        if (aligned) return cbase_aligned + j + (int64_t)l * I;
+        const int64_t col = c0 + j;
+        return (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+    };
+    auto tile_base = [&](int64_t t, int& load, int64_t& c0) __attribute__((always_inline)) -> C* {
+        const int64_t ct = t % nct;
+        const int64_t rest = t / nct;
+        const int field = (int)(rest % a.nfield);
+        load = (int)(rest / a.nfield);
+        c0 = ct * NC;
+        int par = 0;
+        if (a.st) par = (a.st[load].iter + 1) & 1;
+        return reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)field * a.field_stride;
+    };
+
+    C pre[EPT];
+    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
+        int load;
+        int64_t c0;
+        const C* base = tile_base(t, load, c0);
+        if (a.st && a.st[load].done) return false;
+        if (aligned && TH % NC == 0) {
+            // thread keeps its column j; position advances by TH / NC per step
+            const int j = tid % NC, l0 = tid / NC;
+            const C* p0 = base + (c0 / I) * (int64_t)L * I + (c0 % I) + j + (int64_t)l0 * I;
+            const int64_t step = (int64_t)(TH / NC) * I;
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                if (tid + q * TH < NC * L) pre[q] = ldg(p0 + q * step);
+            });
+            return true;
+        }
+        const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            int j, l;
+            map(e, j, l);
+            if (e < NC * L && c0 + j < ncols) pre[q] = ldg(base + addr(c0, cb, j, l));
+        });
+        return true;
+    };
+
+    int64_t t = blockIdx.x;
+    bool have = t < total ? fetch(t) : false;
+    for (; t < total; t += gridDim.x) {
+        const bool cur = have;
+        int load;
+        int64_t c0;
+        C* base = tile_base(t, load, c0);
+        const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+        if (cur) {
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                int j, l;
+                map(e, j, l);
+                if (e >= NC * L || j >= ncol) return;
+                C v = pre[q];
+                if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+                X[j * CS + l] = v;
+            });
+        }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        have = tn < total ? fetch(tn) : false;
+        if (!cur) continue;
+        fft_cols<L, DIR, CS>(X, NC, twl);
+        const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
+        for (int e = tid; e < L * NC; e += TH) {
+            int j, l;
+            map(e, j, l);
+            if (j >= ncol) continue;
+            C v = X[j * CS + l];
+            if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+            stg(base + addr(c0, cb, j, l), v);
+        }
+        __syncthreads();
     }
 }
 
@@ -425,150 +561,205 @@ __global__ void __launch_bounds__(512) kf_axis(AxisArgs a) {
 // spectral turnaround along the last axis
 // =============================================================================
 template <typename T, int DIM, int L>
-__global__ void __launch_bounds__(512) kf_spec(SpecArgs a) {
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N>::THREADS)) kf_spec(SpecArgs a) {
     using C = typename CT<T>::t;
     constexpr int NCOMP = Comp<DIM>::N, NT = Comp<DIM>::NT;
     using G = Geo<T, L, NCOMP>;
-    constexpr int NC = G::NC, CS = G::CS;
+    constexpr int NC = G::NC, CS = G::CS, TH = G::THREADS;
+    constexpr int EPT = (NC * L + TH - 1) / TH;
     const Plan& P = *a.plan;
-    const int load = blockIdx.y;
-    const LoadState& st = a.st[load];
-    if (st.done) return;
-    const int par = (st.iter + 1) & 1;
     const int D = P.D;
     const int64_t ncols = P.S / L;
-    const int64_t c0 = (int64_t)blockIdx.x * NC;
-    const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+    const int64_t nct = (ncols + NC - 1) / NC;
+    const int64_t total = nct * a.nload;
     const int tid = threadIdx.x;
     C* F = smem<C>();
     C* twl = F + G::TILE;
     int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
-    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
-    C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
     load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off);
-    if (tid < NC) {
-        int64_t o = c0 + tid;
-        int64_t kap[3] = {0, 0, 0};
-        int64_t k0 = 0;
-        for (int b = D - 2; b >= 0; --b) {
-            const int64_t sl = P.ax[b].slen;
-            const int64_t kk = o % sl;
-            o /= sl;
-            kap[P.ax[b].snf] += P.ax[b].mult * kk;
-            if (b == 0) k0 = kk;
-        }
-        kb[tid * 4 + 0] = kap[0];
-        kb[tid * 4 + 1] = kap[1];
-        kb[tid * 4 + 2] = kap[2];
-        kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
-    }
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        const int j = e / L, l = e % L;
-        if (j >= ncol) continue;
-        const int64_t addr = (c0 + j) * L + l;
-#pragma unroll
-        for (int f = 0; f < NCOMP; ++f) F[(f * NC + j) * CS + l] = base[(int64_t)f * P.S + addr];
-    }
-    __syncthreads();
-    fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
-
-    const double* eb = a.eps_bar + (int64_t)load * NCOMP;
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
     const int last_snf = P.ax[D - 1].snf;
     const int64_t last_mult = P.ax[D - 1].mult;
-    double res = 0.0;
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        const int j = e / L, l = e % L;
-        if (j >= ncol) continue;
-        int64_t kap[3] = {kb[j * 4 + 0], kb[j * 4 + 1], kb[j * 4 + 2]};
-        kap[last_snf] += last_mult * l;
-        C* fp[NCOMP];
-#pragma unroll
-        for (int f = 0; f < NCOMP; ++f) fp[f] = F + (f * NC + j) * CS + l;
-        if (kap[0] == 0 && kap[1] == 0 && kap[2] == 0) {
-#pragma unroll
-            for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)eb[f], (T)0};
-            continue;
+
+    C pre[EPT][NCOMP];
+    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
+        const int load = (int)(t / nct);
+        const int64_t c0 = (t % nct) * NC;
+        const LoadState& st = a.st[load];
+        if (st.done) return false;
+        const C* base = reinterpret_cast<const C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            if (e < NC * L && c0 + e / L < ncols) {
+                const int64_t addr = c0 * L + e;
+                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                    constexpr int f = fc;
+                    pre[q][f] = ldg(base + (int64_t)f * P.S + addr);
+                });
+            }
+        });
+        return true;
+    };
+
+    int64_t t = blockIdx.x;
+    bool have = t < total ? fetch(t) : false;
+    for (; t < total; t += gridDim.x) {
+        const bool cur = have;
+        const int load = (int)(t / nct);
+        const int64_t c0 = (t % nct) * NC;
+        const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+        if (cur) {
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int j = e / L, l = e % L;
+                if (e >= NC * L || j >= ncol) return;
+                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                    constexpr int f = fc;
+                    F[(f * NC + j) * CS + l] = pre[q][f];
+                });
+            });
+            if (tid < NC) {
+                int64_t o = c0 + tid;
+                int64_t k0 = 0, kq0 = 0, kq1 = 0, kq2 = 0;
+                for (int b = D - 2; b >= 0; --b) {
+                    const int64_t sl = P.ax[b].slen;
+                    const int64_t kk = o % sl;
+                    o /= sl;
+                    const int64_t v = P.ax[b].mult * kk;
+                    const int sn = P.ax[b].snf;
+                    kq0 += sn == 0 ? v : 0;
+                    kq1 += sn == 1 ? v : 0;
+                    kq2 += sn == 2 ? v : 0;
+                    if (b == 0) k0 = kk;
+                }
+                kb[tid * 4 + 0] = kq0;
+                kb[tid * 4 + 1] = kq1;
+                kb[tid * 4 + 2] = kq2;
+                kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
+            }
         }
-        int64_t N[3];
-        const int half = centred_numerators(P.fm, kap, N, DIM);
-        if (half && !ahom_self_conjugate(P.fm, kap)) {
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        have = tn < total ? fetch(tn) : false;
+        if (!cur) continue;
+        const LoadState& st = a.st[load];
+        C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
+        // previous traction of this tile: in flight during the forward transform
+        C oldv[EPT][NT];
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            if (e < NC * L && c0 + e / L < ncols) {
+                sfor<0, NT>([&](auto cc) __attribute__((always_inline)) {
+                    constexpr int c = cc;
+                    oldv[q][c] = ldg(tb + (int64_t)c * P.S + c0 * L + e);
+                });
+            }
+        });
+        fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
+
+        const double* eb = a.eps_bar + (int64_t)load * NCOMP;
+        double res = 0.0;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const int j = e / L, l = e % L;
+            if (e >= NC * L || j >= ncol) return;
+            const int64_t add = last_mult * l;
+            int64_t kap[3] = {kb[j * 4 + 0] + (last_snf == 0 ? add : 0), kb[j * 4 + 1] + (last_snf == 1 ? add : 0),
+                              kb[j * 4 + 2] + (last_snf == 2 ? add : 0)};
+            C* fp[NCOMP];
 #pragma unroll
-            for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)0, (T)0};
-            continue;
+            for (int f = 0; f < NCOMP; ++f) fp[f] = F + (f * NC + j) * CS + l;
+            if (kap[0] == 0 && kap[1] == 0 && kap[2] == 0) {
+#pragma unroll
+                for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)eb[f], (T)0};
+                return;
+            }
+            int64_t N[3];
+            const int half = centred_numerators(P.fm, kap, N, DIM);
+            if (half && !ahom_self_conjugate(P.fm, kap)) {
+#pragma unroll
+                for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)0, (T)0};
+                return;
+            }
+            double hd[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                hd[i] = 0.0;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) hd[i] += (double)P.fm.MT[i][r] * (double)N[r];
+            }
+            double hn = 0.0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) hn += hd[i] * hd[i];
+            hn = rsqrt(hn);
+            T xi[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) xi[i] = (T)(hd[i] * hn);
+            C tv[NCOMP];
+#pragma unroll
+            for (int f = 0; f < NCOMP; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
+            C tt[NT];
+            if constexpr (DIM == 3) {
+                const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
+                tt[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
+                tt[1] = C{T01.x * xi[0] + T11.x * xi[1] + T12.x * xi[2], T01.y * xi[0] + T11.y * xi[1] + T12.y * xi[2]};
+                tt[2] = C{T02.x * xi[0] + T12.x * xi[1] + T22.x * xi[2], T02.y * xi[0] + T12.y * xi[1] + T22.y * xi[2]};
+            } else {
+                const C T00 = tv[0], T11 = tv[1], T01 = tv[2];
+                tt[0] = C{T00.x * xi[0] + T01.x * xi[1], T00.y * xi[0] + T01.y * xi[1]};
+                tt[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
+            }
+            const int64_t spos = c0 * L + e;
+            double r2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
+                r2 += dx * dx + dy * dy;
+                stg(tb + (int64_t)c * P.S + spos, tt[c]);
+            }
+            res += (double)kb[j * 4 + 3] * r2;
+            C xt = C{(T)0, (T)0};
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * tt[i].x; xt.y += xi[i] * tt[i].y; }
+            const T im0 = (T)1 / mu0;
+            C v[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) v[i] = C{(tt[i].x - beta * xt.x * xi[i]) * im0, (tt[i].y - beta * xt.y * xi[i]) * im0};
+            if constexpr (DIM == 3) {
+                *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+                *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+                *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
+                *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
+                *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
+                *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+            } else {
+                *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+                *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+                *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+            }
+        });
+        __syncthreads();
+        fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
+        for (int e = tid; e < L * NC; e += TH) {
+            const int j = e / L;
+            if (j >= ncol) continue;
+            const int64_t addr = c0 * L + e;
+            const int l = e % L;
+#pragma unroll
+            for (int f = 0; f < NCOMP; ++f) stg(base + (int64_t)f * P.S + addr, F[(f * NC + j) * CS + l]);
         }
-        double hd[DIM];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-            hd[i] = 0.0;
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) hd[i] += (double)P.fm.MT[i][q] * (double)N[q];
-        }
-        double hn = 0.0;
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) hn += hd[i] * hd[i];
-        hn = rsqrt(hn);
-        T xi[DIM];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) xi[i] = (T)(hd[i] * hn);
-        C tv[NCOMP];
-#pragma unroll
-        for (int f = 0; f < NCOMP; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
-        C t[NT];
-        if constexpr (DIM == 3) {
-            const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
-            t[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
-            t[1] = C{T01.x * xi[0] + T11.x * xi[1] + T12.x * xi[2], T01.y * xi[0] + T11.y * xi[1] + T12.y * xi[2]};
-            t[2] = C{T02.x * xi[0] + T12.x * xi[1] + T22.x * xi[2], T02.y * xi[0] + T12.y * xi[1] + T22.y * xi[2]};
-        } else {
-            const C T00 = tv[0], T11 = tv[1], T01 = tv[2];
-            t[0] = C{T00.x * xi[0] + T01.x * xi[1], T00.y * xi[0] + T01.y * xi[1]};
-            t[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
-        }
-        const int64_t spos = (c0 + j) * L + l;
-        double r2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const C old = tb[(int64_t)c * P.S + spos];
-            const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
-            r2 += dx * dx + dy * dy;
-            tb[(int64_t)c * P.S + spos] = t[c];
-        }
-        res += (double)kb[j * 4 + 3] * r2;
-        C xt = C{(T)0, (T)0};
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * t[i].x; xt.y += xi[i] * t[i].y; }
-        const T im0 = (T)1 / mu0;
-        C v[DIM];
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) v[i] = C{(t[i].x - beta * xt.x * xi[i]) * im0, (t[i].y - beta * xt.y * xi[i]) * im0};
-        if constexpr (DIM == 3) {
-            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
-            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
-            *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
-            *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
-            *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
-            *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
-        } else {
-            *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
-            *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
-            *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
-        }
+        __syncthreads();
+        double rv[1] = {res};
+        block_sum<1>(rv, reinterpret_cast<double*>(F));
+        if (tid == 0) a.res_part[(int64_t)load * nct + t % nct] = rv[0];
+        __syncthreads();
     }
-    __syncthreads();
-    fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
-    for (int e = tid; e < L * NC; e += blockDim.x) {
-        const int j = e / L, l = e % L;
-        if (j >= ncol) continue;
-        const int64_t addr = (c0 + j) * L + l;
-#pragma unroll
-        for (int f = 0; f < NCOMP; ++f) base[(int64_t)f * P.S + addr] = F[(f * NC + j) * CS + l];
-    }
-    __syncthreads();
-    double rv[1] = {res};
-    block_sum<1>(rv, reinterpret_cast<double*>(F));
-    if (tid == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
 }
 
 // ----------------------------------------------------------------- dispatch
@@ -606,11 +797,18 @@ bool geom_T(int kind, int dim, int L, FastGeom* g) {
 #undef AHOM_G
 }
 
+// Set the LDS attribute and return the persistent grid: the tiles that fit on
+// the device at once (occupancy API: registers, LDS and threads), capped by
+// the number of tiles.
 template <typename F>
-int launch(F fn, const FastGeom& g) {
+int prepare(F fn, const FastGeom& g, int64_t total, int ncu) {
     if (g.lds > 64 * 1024)
         if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess) return -1;
-    return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, g.threads, g.lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    int64_t grid = (int64_t)ncu * per_cu;
+    if (grid > total) grid = total;
+    return (int)(grid < 1 ? 1 : grid);
 }
 
 }  // namespace
@@ -625,18 +823,18 @@ bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g) {
         default: return -1;     \
     }
 
-int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int nwg, int nload, hipStream_t s) {
+int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
     if (!ahom_fast_geom(prec, FAST_REAL, dim, L, &g)) return -1;
-    dim3 grid(nwg, nload), block(g.threads);
+    dim3 block(g.threads);
 #define AHOM_FR(LL)                                                                                   \
     case LL: {                                                                                        \
         if (prec == 0) {                                                                              \
-            if (dim == 3) { auto fn = kf_real<double, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
-            else { auto fn = kf_real<double, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+            if (dim == 3) { auto fn = kf_real<double, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
+            else { auto fn = kf_real<double, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
         } else {                                                                                      \
-            if (dim == 3) { auto fn = kf_real<float, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
-            else { auto fn = kf_real<float, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }         \
+            if (dim == 3) { auto fn = kf_real<float, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
+            else { auto fn = kf_real<float, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }         \
         }                                                                                             \
         break;                                                                                        \
     }
@@ -645,18 +843,18 @@ int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int nwg, 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int nwg, int nfield, int nload, hipStream_t s) {
+int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
     if (!ahom_fast_geom(prec, FAST_AXIS, 3, L, &g)) return -1;
-    dim3 grid(nwg, nfield, nload), block(g.threads);
+    dim3 block(g.threads);
 #define AHOM_FA(LL)                                                                                   \
     case LL: {                                                                                        \
         if (prec == 0) {                                                                              \
-            if (dir < 0) { auto fn = kf_axis<double, LL, -1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
-            else { auto fn = kf_axis<double, LL, 1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }       \
+            if (dir < 0) { auto fn = kf_axis<double, LL, -1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
+            else { auto fn = kf_axis<double, LL, 1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }       \
         } else {                                                                                      \
-            if (dir < 0) { auto fn = kf_axis<float, LL, -1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
-            else { auto fn = kf_axis<float, LL, 1>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+            if (dir < 0) { auto fn = kf_axis<float, LL, -1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
+            else { auto fn = kf_axis<float, LL, 1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
         }                                                                                             \
         break;                                                                                        \
     }
@@ -665,18 +863,18 @@ int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int nwg, 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int nwg, int nload, hipStream_t s) {
+int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
     if (!ahom_fast_geom(prec, FAST_SPEC, dim, L, &g)) return -1;
-    dim3 grid(nwg, nload), block(g.threads);
+    dim3 block(g.threads);
 #define AHOM_FS(LL)                                                                                   \
     case LL: {                                                                                        \
         if (prec == 0) {                                                                              \
-            if (dim == 3) { auto fn = kf_spec<double, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); } \
-            else { auto fn = kf_spec<double, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }        \
+            if (dim == 3) { auto fn = kf_spec<double, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
+            else { auto fn = kf_spec<double, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
         } else {                                                                                      \
-            if (dim == 3) { auto fn = kf_spec<float, 3, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }  \
-            else { auto fn = kf_spec<float, 2, LL>; if (launch(fn, g)) return -1; hipLaunchKernelGGL(fn, grid, block, g.lds, s, a); }         \
+            if (dim == 3) { auto fn = kf_spec<float, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
+            else { auto fn = kf_spec<float, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }         \
         }                                                                                             \
         break;                                                                                        \
     }

@@ -36,6 +36,7 @@ struct RealArgs {
     double* real_io;          // [load][ncomp][m] for TO_REAL / FROM_REAL
     const double* eps_bar;    // [load][ncomp]
     int NC, CS;
+    int nload;                // fast path: load cases covered by the persistent grid
 };
 
 struct AxisArgs {
@@ -49,6 +50,7 @@ struct AxisArgs {
     int axis;
     int slen0_full;           // 1: axis 0 stored at full length (bare DFT)
     int NC, CS;
+    int nload, nfield;        // fast path: work items covered by the persistent grid
 };
 
 struct SpecArgs {
@@ -63,6 +65,7 @@ struct SpecArgs {
     double lam0_init;          // lambda0 (used by SPEC_INIT)
     double* res_part;         // [load][wg]
     int NC, CS;
+    int nload;                // fast path: load cases covered by the persistent grid
 };
 
 struct ReduceArgs {
@@ -108,6 +111,7 @@ struct FastGeom {
     size_t lds = 0;
 };
 bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g);
-int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int nwg, int nload, hipStream_t s);
-int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int nwg, int nfield, int nload, hipStream_t s);
-int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int nwg, int nload, hipStream_t s);
+// total = tiles of the pass (all loads/fields); the grid is sized from the occupancy API
+int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
+int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s);
+int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s);
