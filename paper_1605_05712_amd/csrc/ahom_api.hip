@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -139,14 +142,43 @@ struct ahom_solver {
     bool f_real = false, f_spec = false, f_axis[AHOM_MAX_AXES] = {};
     int fn_real = 0, fn_spec = 0, fn_axis[AHOM_MAX_AXES] = {};   // tiles per load (and field)
     size_t fl_real = 0, fl_spec = 0, fl_axis[AHOM_MAX_AXES] = {}; // LDS bytes per workgroup
+    int v_real = 0, v_spec = 0, v_axis[AHOM_MAX_AXES] = {};       // tile variants (autotuned)
+    bool tuned = false;
     int ncu = 256;
     bool use_fast = true;
-    // persistent grid: at most the workgroups that fit on the device at once
-    int persistent_grid(int64_t total, size_t lds) const {
-        int per_cu = lds ? (int)((160 * 1024) / lds) : 8;
-        per_cu = std::max(1, std::min(per_cu, 8));
-        return (int)std::max<int64_t>(1, std::min<int64_t>(total, (int64_t)ncu * per_cu));
+    // tiles per load (and field) of each fast pass for the chosen variants
+    void apply_variants() {
+        const Plan& P = pat->plan;
+        FastGeom fg;
+        if (f_real && ahom_fast_geom(prec, FAST_REAL, dim, P.ax[0].len, v_real, &fg)) {
+            const int64_t I = P.S / P.ax[0].slen;
+            fn_real = (int)((I + fg.NC - 1) / fg.NC);
+            fl_real = fg.lds;
+        }
+        if (f_spec && ahom_fast_geom(prec, FAST_SPEC, dim, P.ax[P.D - 1].len, v_spec, &fg)) {
+            const int64_t nc = P.S / P.ax[P.D - 1].len;
+            fn_spec = (int)((nc + fg.NC - 1) / fg.NC);
+            fl_spec = fg.lds;
+        }
+        for (int a = 1; a <= P.D - 2; ++a)
+            if (f_axis[a] && ahom_fast_geom(prec, FAST_AXIS, dim, P.ax[a].len, v_axis[a], &fg)) {
+                int64_t O = 1, I = 1;
+                for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
+                for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
+                fn_axis[a] = (int)((O * I + fg.NC - 1) / fg.NC);
+                fl_axis[a] = fg.lds;
+            }
     }
+    // largest tile count over all variants (partial-sum buffers)
+    int max_tiles(int kind, int L, int64_t ncols) const {
+        int best = 1;
+        for (int v = 0; v < AHOM_FAST_VARIANTS; ++v) {
+            FastGeom fg;
+            if (ahom_fast_geom(prec, kind, dim, L, v, &fg)) best = std::max<int>(best, (int)((ncols + fg.NC - 1) / fg.NC));
+        }
+        return best;
+    }
+    int autotune(int nload);
     int n_real_wg() const { return f_real ? fn_real : g_real.nwg; }
     int n_spec_wg() const { return f_spec ? fn_spec : g_spec.nwg; }
     // timing
@@ -176,8 +208,10 @@ struct ahom_solver {
         HIPCHK(hipMalloc(&d_tbuf, (size_t)nload * nt * P.S * es()));
         HIPCHK(hipMalloc((void**)&d_st, nload * sizeof(LoadState)));
         HIPCHK(hipHostMalloc((void**)&h_st, nload * sizeof(LoadState), hipHostMallocDefault));
-        HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * std::max(g_real.nwg, fn_real) * ncomp * sizeof(double)));
-        HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * std::max(g_spec.nwg, fn_spec) * sizeof(double)));
+        const int mt_real = max_tiles(FAST_REAL, P.ax[0].len, P.S / P.ax[0].slen);
+        const int mt_spec = max_tiles(FAST_SPEC, P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len);
+        HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * std::max(g_real.nwg, mt_real) * ncomp * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * std::max(g_spec.nwg, mt_spec) * sizeof(double)));
         hist_cap = cfg.max_iter + 1;
         HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
@@ -253,7 +287,7 @@ struct ahom_solver {
         if (f_real) {
             RealArgs ra = real_args(REAL_TURN);
             ra.nload = nload;
-            return ahom_launch_fast_real(prec, dim, pat->plan.ax[0].len, ra, (int64_t)fn_real * nload, ncu, s);
+            return ahom_launch_fast_real(prec, dim, pat->plan.ax[0].len, v_real, ra, (int64_t)fn_real * nload, ncu, s);
         }
         return ahom_launch_real(prec, dim, REAL_TURN, real_args(REAL_TURN), g_real.nwg, nload, g_real.lds, s);
     }
@@ -262,7 +296,7 @@ struct ahom_solver {
             AxisArgs aa = axis_args(a);
             aa.nload = nload;
             aa.nfield = ncomp;
-            return ahom_launch_fast_axis(prec, dir, pat->plan.ax[a].len, aa, (int64_t)fn_axis[a] * ncomp * nload, ncu, s);
+            return ahom_launch_fast_axis(prec, dir, pat->plan.ax[a].len, v_axis[a], aa, (int64_t)fn_axis[a] * ncomp * nload, ncu, s);
         }
         return ahom_launch_axis(prec, dir, axis_args(a), g_axis[a].nwg, ncomp, nload, g_axis[a].lds, s);
     }
@@ -270,7 +304,7 @@ struct ahom_solver {
         if (f_spec) {
             SpecArgs sa = spec_args();
             sa.nload = nload;
-            return ahom_launch_fast_spec(prec, dim, pat->plan.ax[pat->plan.D - 1].len, sa, (int64_t)fn_spec * nload, ncu, s);
+            return ahom_launch_fast_spec(prec, dim, pat->plan.ax[pat->plan.D - 1].len, v_spec, sa, (int64_t)fn_spec * nload, ncu, s);
         }
         return ahom_launch_spec(prec, dim, spec_args(), g_spec.nwg, nload, g_spec.lds, s);
     }
@@ -299,6 +333,91 @@ struct ahom_solver {
         return AHOM_OK;
     }
 };
+
+// ---------------------------------------------------------------- autotuner
+// Times every compiled tile variant of each power-of-two pass on the solver's
+// own buffers and keeps the fastest.  Results are cached per process by
+// (pass, precision, dimension, length, columns, loads), so later solvers of
+// the same shape reuse them without timing.
+namespace {
+struct TuneKey {
+    int kind, prec, dim, L, axis, nload;
+    int64_t ncols;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(kind, prec, dim, L, axis, nload, ncols) < std::tie(o.kind, o.prec, o.dim, o.L, o.axis, o.nload, o.ncols);
+    }
+};
+std::map<TuneKey, int>& tune_cache() {
+    static std::map<TuneKey, int> c;
+    return c;
+}
+std::mutex& tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+}  // namespace
+
+int ahom_solver::autotune(int nload) {
+    if (tuned || !use_fast) return AHOM_OK;
+    const Plan& P = pat->plan;
+    hipStream_t st = stream;
+    if (ahom_launch_reset(d_st, nload, st)) return fail(AHOM_E_DEVICE, "reset");
+    auto time_pass = [&](auto&& launch, float* best_ms) -> int {
+        // one warm launch, then the minimum of three timed launches
+        if (launch()) return -1;
+        float best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            if (hipEventRecord(ev0, st) != hipSuccess) return -1;
+            if (launch()) return -1;
+            if (hipEventRecord(ev1, st) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess) return -1;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) return -1;
+            best = std::min(best, ms);
+        }
+        *best_ms = best;
+        return 0;
+    };
+    auto tune_one = [&](int kind, int L, int axis, int64_t ncols, int* vsel, auto&& launch_v) -> int {
+        TuneKey key{kind, prec, dim, L, axis, nload, ncols};
+        {
+            std::lock_guard<std::mutex> g(tune_mutex());
+            auto it = tune_cache().find(key);
+            if (it != tune_cache().end()) { *vsel = it->second; return AHOM_OK; }
+        }
+        int best_v = 0;
+        float best = 1e30f;
+        std::vector<FastGeom> seen;
+        for (int v = 0; v < AHOM_FAST_VARIANTS; ++v) {
+            FastGeom fg;
+            if (!ahom_fast_geom(prec, kind, dim, L, v, &fg)) continue;
+            bool dup = false;
+            for (auto& o : seen) dup = dup || (o.NC == fg.NC && o.persistent == fg.persistent);
+            if (dup) continue;
+            seen.push_back(fg);
+            *vsel = v;
+            apply_variants();
+            float ms = 0.f;
+            if (time_pass([&]() { return launch_v(); }, &ms)) return fail(AHOM_E_DEVICE, "autotune launch failed");
+            if (ms < best) { best = ms; best_v = v; }
+        }
+        *vsel = best_v;
+        apply_variants();
+        std::lock_guard<std::mutex> g(tune_mutex());
+        tune_cache()[key] = best_v;
+        return AHOM_OK;
+    };
+    int rc;
+    if (f_real && (rc = tune_one(FAST_REAL, P.ax[0].len, 0, P.S / P.ax[0].slen, &v_real, [&]() { return launch_real_turn(nload, st); }))) return rc;
+    for (int a = 1; a <= P.D - 2; ++a) {
+        int64_t O = 1, I = 1;
+        for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
+        for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
+        if (f_axis[a] && (rc = tune_one(FAST_AXIS, P.ax[a].len, a, O * I, &v_axis[a], [&]() { return launch_axis(a, -1, nload, st); }))) return rc;
+    }
+    if (f_spec && (rc = tune_one(FAST_SPEC, P.ax[P.D - 1].len, P.D - 1, P.S / P.ax[P.D - 1].len, &v_spec, [&]() { return launch_spec(nload, st); }))) return rc;
+    tuned = true;
+    return AHOM_OK;
+}
 
 // ============================================================================ API
 extern "C" {
@@ -465,27 +584,18 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     }
     if (s->use_fast) {
         FastGeom fg;
-        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, &fg)) {
-            const int64_t I = P.S / P.ax[0].slen;
-            s->f_real = true;
-            s->fn_real = (int)((I + fg.NC - 1) / fg.NC);
-            s->fl_real = fg.lds;
-        }
-        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, &fg)) {
-            const int64_t nc = P.S / P.ax[P.D - 1].len;
-            s->f_spec = true;
-            s->fn_spec = (int)((nc + fg.NC - 1) / fg.NC);
-            s->fl_spec = fg.lds;
-        }
+        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, 0, &fg)) s->f_real = true;
+        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, 0, &fg)) s->f_spec = true;
         for (int a = 1; a <= P.D - 2; ++a)
-            if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, &fg)) {
-                int64_t O = 1, I = 1;
-                for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
-                for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
-                s->f_axis[a] = true;
-                s->fn_axis[a] = (int)((O * I + fg.NC - 1) / fg.NC);
-                s->fl_axis[a] = fg.lds;
-            }
+            if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, 0, &fg)) s->f_axis[a] = true;
+        const char* venv = getenv("AHOM_FAST_VARIANT");
+        if (venv && venv[0] >= '0' && venv[0] <= '3') {
+            const int v = venv[0] - '0';
+            s->v_real = s->v_spec = v;
+            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v;
+            s->tuned = true;
+        }
+        s->apply_variants();
     }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
         return bad(fail(AHOM_E_DEVICE, "event create"));
@@ -564,6 +674,7 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
+    if ((rc = s->autotune(n_load))) return rc;
     const Plan& P = s->pat->plan;
     const int nc = s->ncomp;
     const int* comp = s->dim == 3 ? kComp3 : kComp2;

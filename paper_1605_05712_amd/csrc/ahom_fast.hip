@@ -151,13 +151,17 @@ constexpr int pow2floor(int v) {
 
 // columns per workgroup: NF fields x NC columns x N1 threads <= 512 threads,
 // NF x NC x (L + 1) elements <= 50 KB of LDS
-template <typename T, int L, int NF> struct Geo {
+// Tile variants V (chosen per pass by the autotuner): bit 0 halves the
+// columns per tile, bit 1 selects the persistent prefetching schedule.
+template <typename T, int L, int NF, int V = 0> struct Geo {
     static constexpr int es = 2 * (int)sizeof(T);
     static constexpr int N1 = Split<L>::N1;
     static constexpr int CS = L + 1;  // odd: consecutive columns start in distinct LDS banks
     static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
     static constexpr int by_thr = 512 / (NF * N1);
-    static constexpr int NC = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
+    static constexpr int NCMAX = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
+    static constexpr int NC = (V & 1) && NCMAX > 1 ? NCMAX / 2 : NCMAX;
+    static constexpr bool PERSIST = (V & 2) != 0;
     static constexpr int THREADS = ((NF * NC * N1 + 63) / 64) * 64;
     static constexpr int TILE = NF * NC * CS;  // complex elements of LDS tile
 };
@@ -306,11 +310,11 @@ __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_
 // =============================================================================
 // real-space turnaround along axis 0
 // =============================================================================
-template <typename T, int DIM, int L>
-__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP>::THREADS)) kf_real(RealArgs a) {
+template <typename T, int DIM, int L, int V>
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_real(RealArgs a) {
     using C = typename CT<T>::t;
     constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
-    using G = Geo<T, L, NP>;
+    using G = Geo<T, L, NP, V>;
     constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1, TH = G::THREADS;
     constexpr int EPT = (H * NC + TH - 1) / TH;     // half-spectrum rows per thread
     const Plan& P = *a.plan;
@@ -376,7 +380,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP>::THREADS)) kf_real(R
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        else have = false;
         if (!cur) continue;
         const LoadState& st = a.st[load];
         C* dst = reinterpret_cast<C*>((st.iter & 1) ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
@@ -450,10 +455,10 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP>::THREADS)) kf_real(R
 // =============================================================================
 // middle axes
 // =============================================================================
-template <typename T, int L, int DIR>
-__global__ void __launch_bounds__((Geo<T, L, 1>::THREADS)) kf_axis(AxisArgs a) {
+template <typename T, int L, int DIR, int V>
+__global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a) {
     using C = typename CT<T>::t;
-    using G = Geo<T, L, 1>;
+    using G = Geo<T, L, 1, V>;
     constexpr int NC = G::NC, CS = G::CS, TH = G::THREADS;
     constexpr int EPT = (NC * L + TH - 1) / TH;
     const Plan& P = *a.plan;
@@ -541,7 +546,8 @@ __global__ void __launch_bounds__((Geo<T, L, 1>::THREADS)) kf_axis(AxisArgs a) {
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        else have = false;
         if (!cur) continue;
         fft_cols<L, DIR, CS>(X, NC, twl);
         const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
@@ -560,11 +566,11 @@ __global__ void __launch_bounds__((Geo<T, L, 1>::THREADS)) kf_axis(AxisArgs a) {
 // =============================================================================
 // spectral turnaround along the last axis
 // =============================================================================
-template <typename T, int DIM, int L>
-__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N>::THREADS)) kf_spec(SpecArgs a) {
+template <typename T, int DIM, int L, int V>
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec(SpecArgs a) {
     using C = typename CT<T>::t;
     constexpr int NCOMP = Comp<DIM>::N, NT = Comp<DIM>::NT;
-    using G = Geo<T, L, NCOMP>;
+    using G = Geo<T, L, NCOMP, V>;
     constexpr int NC = G::NC, CS = G::CS, TH = G::THREADS;
     constexpr int EPT = (NC * L + TH - 1) / TH;
     const Plan& P = *a.plan;
@@ -643,7 +649,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N>::THREADS)) kf_spec(Sp
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        else have = false;
         if (!cur) continue;
         const LoadState& st = a.st[load];
         C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
@@ -765,14 +772,15 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N>::THREADS)) kf_spec(Sp
 // ----------------------------------------------------------------- dispatch
 namespace {
 
-template <typename T, int L, int NF>
+template <typename T, int L, int NF, int V>
 FastGeom geom_of(int kind) {
-    using G = Geo<T, L, NF>;
+    using G = Geo<T, L, NF, V>;
     FastGeom g;
     g.NC = G::NC;
     g.threads = G::THREADS;
-    // tile + twiddles + per-column integers (axis: base offsets, spec: kappa + weight)
-    size_t extra = kind == FAST_AXIS ? (size_t)G::NC * 8 : (kind == FAST_SPEC ? (size_t)G::NC * 32 : 0);
+    g.persistent = G::PERSIST;
+    // tile + twiddles + per-column integers (spec: kappa + weight)
+    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * 32 : 0;
     size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
     // block reduction reuses the tile: NV doubles per thread
     const size_t red = (size_t)G::THREADS * 8 * (kind == FAST_REAL ? 6 : 1);
@@ -780,15 +788,18 @@ FastGeom geom_of(int kind) {
     return g;
 }
 
-template <typename T>
-bool geom_T(int kind, int dim, int L, FastGeom* g) {
+// lengths with tile variants; shorter transforms use variant 0 only
+constexpr bool tuned_length(int L) { return L >= 32; }
+
+template <typename T, int V>
+bool geom_TV(int kind, int dim, int L, FastGeom* g) {
     const int nf = kind == FAST_REAL ? (dim == 3 ? 3 : 2) : (kind == FAST_SPEC ? (dim == 3 ? 6 : 3) : 1);
 #define AHOM_G(LL)                                                     \
     case LL:                                                           \
-        if (nf == 1) *g = geom_of<T, LL, 1>(kind);                     \
-        else if (nf == 2) *g = geom_of<T, LL, 2>(kind);                \
-        else if (nf == 3) *g = geom_of<T, LL, 3>(kind);                \
-        else *g = geom_of<T, LL, 6>(kind);                             \
+        if (nf == 1) *g = geom_of<T, LL, 1, V>(kind);                  \
+        else if (nf == 2) *g = geom_of<T, LL, 2, V>(kind);             \
+        else if (nf == 3) *g = geom_of<T, LL, 3, V>(kind);             \
+        else *g = geom_of<T, LL, 6, V>(kind);                          \
         return true;
     switch (L) {
         AHOM_G(1) AHOM_G(2) AHOM_G(4) AHOM_G(8) AHOM_G(16) AHOM_G(32) AHOM_G(64) AHOM_G(128) AHOM_G(256)
@@ -797,13 +808,14 @@ bool geom_T(int kind, int dim, int L, FastGeom* g) {
 #undef AHOM_G
 }
 
-// Set the LDS attribute and return the persistent grid: the tiles that fit on
-// the device at once (occupancy API: registers, LDS and threads), capped by
-// the number of tiles.
+// Set the LDS attribute and return the grid: one workgroup per tile, or for
+// the persistent schedule the workgroups that fit on the device at once
+// (occupancy API: registers, LDS and threads), capped by the tiles.
 template <typename F>
 int prepare(F fn, const FastGeom& g, int64_t total, int ncu) {
     if (g.lds > 64 * 1024)
         if (hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess) return -1;
+    if (!g.persistent) return (int)total;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, g.threads, g.lds) != hipSuccess || per_cu < 1) per_cu = 1;
     int64_t grid = (int64_t)ncu * per_cu;
@@ -811,74 +823,111 @@ int prepare(F fn, const FastGeom& g, int64_t total, int ncu) {
     return (int)(grid < 1 ? 1 : grid);
 }
 
+template <typename F, typename A>
+int go(F fn, const FastGeom& g, int64_t total, int ncu, hipStream_t s, const A& a) {
+    const int nb = prepare(fn, g, total, ncu);
+    if (nb < 0) return -1;
+    hipLaunchKernelGGL(fn, dim3(nb), dim3(g.threads), g.lds, s, a);
+    return 0;
+}
+
+template <typename T, int V>
+int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
+    FastGeom g;
+    if (!geom_TV<T, V>(FAST_REAL, dim, L, &g)) return -1;
+#define AHOM_FR(LL)                                                                    \
+    case LL:                                                                           \
+        return dim == 3 ? go(kf_real<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
+                        : go(kf_real<T, 2, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a);
+    switch (L) {
+        AHOM_FR(1) AHOM_FR(2) AHOM_FR(4) AHOM_FR(8) AHOM_FR(16) AHOM_FR(32) AHOM_FR(64) AHOM_FR(128) AHOM_FR(256)
+        default: return -1;
+    }
+#undef AHOM_FR
+}
+
+template <typename T, int V>
+int axis_TV(int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
+    FastGeom g;
+    if (!geom_TV<T, V>(FAST_AXIS, 3, L, &g)) return -1;
+#define AHOM_FA(LL)                                                                    \
+    case LL:                                                                           \
+        return dir < 0 ? go(kf_axis<T, LL, -1, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
+                       : go(kf_axis<T, LL, 1, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a);
+    switch (L) {
+        AHOM_FA(1) AHOM_FA(2) AHOM_FA(4) AHOM_FA(8) AHOM_FA(16) AHOM_FA(32) AHOM_FA(64) AHOM_FA(128) AHOM_FA(256)
+        default: return -1;
+    }
+#undef AHOM_FA
+}
+
+template <typename T, int V>
+int spec_TV(int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
+    FastGeom g;
+    if (!geom_TV<T, V>(FAST_SPEC, dim, L, &g)) return -1;
+#define AHOM_FS(LL)                                                                    \
+    case LL:                                                                           \
+        return dim == 3 ? go(kf_spec<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
+                        : go(kf_spec<T, 2, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a);
+    switch (L) {
+        AHOM_FS(1) AHOM_FS(2) AHOM_FS(4) AHOM_FS(8) AHOM_FS(16) AHOM_FS(32) AHOM_FS(64) AHOM_FS(128) AHOM_FS(256)
+        default: return -1;
+    }
+#undef AHOM_FS
+}
+
+template <typename T>
+bool geom_T(int kind, int dim, int L, int v, FastGeom* g) {
+    if (!tuned_length(L)) v = 0;
+    switch (v) {
+        case 0: return geom_TV<T, 0>(kind, dim, L, g);
+        case 1: return geom_TV<T, 1>(kind, dim, L, g);
+        case 2: return geom_TV<T, 2>(kind, dim, L, g);
+        default: return geom_TV<T, 3>(kind, dim, L, g);
+    }
+}
+
 }  // namespace
 
-bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g) {
-    return prec == 0 ? geom_T<double>(kind, dim, L, g) : geom_T<float>(kind, dim, L, g);
+bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g) {
+    return prec == 0 ? geom_T<double>(kind, dim, L, variant, g) : geom_T<float>(kind, dim, L, variant, g);
 }
 
-#define AHOM_FAST_SWITCH(MACRO) \
-    switch (L) {                \
-        MACRO(1) MACRO(2) MACRO(4) MACRO(8) MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) \
-        default: return -1;     \
-    }
+#define AHOM_VSWITCH(FN, ...)                                                  \
+    do {                                                                       \
+        if (prec == 0) {                                                       \
+            switch (variant) {                                                 \
+                case 0: return FN<double, 0>(__VA_ARGS__);                     \
+                case 1: return FN<double, 1>(__VA_ARGS__);                     \
+                case 2: return FN<double, 2>(__VA_ARGS__);                     \
+                default: return FN<double, 3>(__VA_ARGS__);                    \
+            }                                                                  \
+        }                                                                      \
+        switch (variant) {                                                     \
+            case 0: return FN<float, 0>(__VA_ARGS__);                          \
+            case 1: return FN<float, 1>(__VA_ARGS__);                          \
+            case 2: return FN<float, 2>(__VA_ARGS__);                          \
+            default: return FN<float, 3>(__VA_ARGS__);                         \
+        }                                                                      \
+    } while (0)
 
-int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
-    FastGeom g;
-    if (!ahom_fast_geom(prec, FAST_REAL, dim, L, &g)) return -1;
-    dim3 block(g.threads);
-#define AHOM_FR(LL)                                                                                   \
-    case LL: {                                                                                        \
-        if (prec == 0) {                                                                              \
-            if (dim == 3) { auto fn = kf_real<double, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
-            else { auto fn = kf_real<double, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
-        } else {                                                                                      \
-            if (dim == 3) { auto fn = kf_real<float, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
-            else { auto fn = kf_real<float, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }         \
-        }                                                                                             \
-        break;                                                                                        \
-    }
-    AHOM_FAST_SWITCH(AHOM_FR)
-#undef AHOM_FR
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
+    int rc;
+    auto run = [&]() -> int { AHOM_VSWITCH(real_TV, dim, L, a, total, ncu, s); };
+    rc = run();
+    return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
-    FastGeom g;
-    if (!ahom_fast_geom(prec, FAST_AXIS, 3, L, &g)) return -1;
-    dim3 block(g.threads);
-#define AHOM_FA(LL)                                                                                   \
-    case LL: {                                                                                        \
-        if (prec == 0) {                                                                              \
-            if (dir < 0) { auto fn = kf_axis<double, LL, -1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
-            else { auto fn = kf_axis<double, LL, 1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }       \
-        } else {                                                                                      \
-            if (dir < 0) { auto fn = kf_axis<float, LL, -1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
-            else { auto fn = kf_axis<float, LL, 1>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
-        }                                                                                             \
-        break;                                                                                        \
-    }
-    AHOM_FAST_SWITCH(AHOM_FA)
-#undef AHOM_FA
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+int ahom_launch_fast_axis(int prec, int dir, int L, int variant, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
+    int rc;
+    auto run = [&]() -> int { AHOM_VSWITCH(axis_TV, dir, L, a, total, ncu, s); };
+    rc = run();
+    return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
-    FastGeom g;
-    if (!ahom_fast_geom(prec, FAST_SPEC, dim, L, &g)) return -1;
-    dim3 block(g.threads);
-#define AHOM_FS(LL)                                                                                   \
-    case LL: {                                                                                        \
-        if (prec == 0) {                                                                              \
-            if (dim == 3) { auto fn = kf_spec<double, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } } \
-            else { auto fn = kf_spec<double, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }        \
-        } else {                                                                                      \
-            if (dim == 3) { auto fn = kf_spec<float, 3, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }  \
-            else { auto fn = kf_spec<float, 2, LL>; { const int nb = prepare(fn, g, total, ncu); if (nb < 0) return -1; hipLaunchKernelGGL(fn, dim3(nb), block, g.lds, s, a); } }         \
-        }                                                                                             \
-        break;                                                                                        \
-    }
-    AHOM_FAST_SWITCH(AHOM_FS)
-#undef AHOM_FS
-    return hipGetLastError() == hipSuccess ? 0 : -1;
+int ahom_launch_fast_spec(int prec, int dim, int L, int variant, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
+    int rc;
+    auto run = [&]() -> int { AHOM_VSWITCH(spec_TV, dim, L, a, total, ncu, s); };
+    rc = run();
+    return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }

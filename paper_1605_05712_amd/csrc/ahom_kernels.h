@@ -108,10 +108,12 @@ int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s
 enum { FAST_REAL = 0, FAST_AXIS = 1, FAST_SPEC = 2 };
 struct FastGeom {
     int NC = 1, threads = 64;
+    bool persistent = false;
     size_t lds = 0;
 };
-bool ahom_fast_geom(int prec, int kind, int dim, int L, FastGeom* g);
+constexpr int AHOM_FAST_VARIANTS = 4;   // tile width x schedule, chosen by the autotuner
+bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g);
 // total = tiles of the pass (all loads/fields); the grid is sized from the occupancy API
-int ahom_launch_fast_real(int prec, int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
-int ahom_launch_fast_axis(int prec, int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s);
-int ahom_launch_fast_spec(int prec, int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s);
+int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
+int ahom_launch_fast_axis(int prec, int dir, int L, int variant, const AxisArgs& a, int64_t total, int ncu, hipStream_t s);
+int ahom_launch_fast_spec(int prec, int dim, int L, int variant, const SpecArgs& a, int64_t total, int ncu, hipStream_t s);
