@@ -415,6 +415,7 @@ int ahom_solver::autotune(int nload) {
         if (f_axis[a] && (rc = tune_one(FAST_AXIS, P.ax[a].len, a, O * I, &v_axis[a], [&]() { return launch_axis(a, -1, nload, st); }))) return rc;
     }
     if (f_spec && (rc = tune_one(FAST_SPEC, P.ax[P.D - 1].len, P.D - 1, P.S / P.ax[P.D - 1].len, &v_spec, [&]() { return launch_spec(nload, st); }))) return rc;
+    apply_variants();  // tile counts must follow the chosen variants (also on cache hits)
     tuned = true;
     return AHOM_OK;
 }

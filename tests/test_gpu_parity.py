@@ -257,3 +257,43 @@ def test_fast_path_matches_generic_path(name, M, prec, monkeypatch):
     tol = 1e-12 if prec == ahom.FP64 else 2e-5
     assert rel_err(outs[0]["strain"], outs[1]["strain"]) < tol
     assert np.allclose(outs[0]["resid"], outs[1]["resid"], rtol=tol * 10)
+
+
+VARIANT_CASES = [
+    ("3-D 64x128x128", [[64, 0, 0], [0, 128, 0], [0, 0, 128]], ahom.FP64),
+    ("3-D 128x64x256 fp32", [[128, 0, 0], [0, 64, 0], [0, 0, 256]], ahom.FP32_MIXED),
+    ("2-D 256x256 sheared", [[256, 0], [64, 256]], ahom.FP64),
+    ("rank-1 2^18", [[262144, 0, 0], [5, 1, 0], [25, 0, 1]], ahom.FP64),
+]
+
+
+@pytest.mark.parametrize("name,M,prec", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
+def test_every_tile_variant_matches_generic(name, M, prec, monkeypatch):
+    """Each compiled tile variant (width x schedule) gives the generic-path result."""
+    say("variants", name, M, prec)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(17, 3)(P.points(), P.m)
+    eb = np.stack([np.eye(3) * 0.01, np.array([[0, 1, 0], [1, 0, 0], [0, 0, 0.5]]) * 0.01])
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "1")
+    S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=3)
+    S.set_material(LAM3, ph)
+    ref = S.solve(eb, want_strain=True)
+    del S
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "0")
+    tol = 1e-12 if prec == ahom.FP64 else 2e-5
+    for v in "0123":
+        monkeypatch.setenv("AHOM_FAST_VARIANT", v)
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=3)
+        S.set_material(LAM3, ph)
+        out = S.solve(eb, want_strain=True)
+        assert rel_err(out["strain"], ref["strain"]) < tol, v
+        assert np.allclose(out["resid"], ref["resid"], rtol=tol * 10)
+        del S
+    monkeypatch.delenv("AHOM_FAST_VARIANT")
+    # autotuned solver twice (second hits the per-process tuning cache)
+    for _ in range(2):
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=3)
+        S.set_material(LAM3, ph)
+        out = S.solve(eb, want_strain=True)
+        assert rel_err(out["strain"], ref["strain"]) < tol
+        del S
