@@ -9,7 +9,10 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libahom.so")
 
-SOURCES = ["ahom_plan.cpp", "ahom_kernels.hip", "ahom_fast.hip", "ahom_api.hip"]
+# (source, extra defines): the power-of-two kernels are compiled in parts
+SOURCES = [("ahom_plan.cpp", []), ("ahom_kernels.hip", []), ("ahom_api.hip", []), ("ahom_fast.hip", [])] + [
+    ("ahom_fast.hip", [f"-DAHOM_FAST_PART={k}"]) for k in range(7)
+]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
@@ -21,19 +24,28 @@ HIP_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
-    for src in SOURCES:
+    cmds, objs = [], []
+    for n, (src, defs) in enumerate(SOURCES):
         path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, "_obj_" + os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(CSRC, f"_obj_{n}_" + os.path.splitext(src)[0] + ".o")
         if src.endswith(".hip"):
-            cmd = [hipcc, *HIP_FLAGS, "-x", "hip", "-c", path, "-o", obj]
+            cmd = [hipcc, *HIP_FLAGS, *defs, "-x", "hip", "-c", path, "-o", obj]
         else:
             cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-c", path, "-o", obj]
+        cmds.append(cmd)
+        objs.append(obj)
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 16))
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

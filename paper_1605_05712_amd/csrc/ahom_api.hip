@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -361,6 +362,8 @@ int ahom_solver::autotune(int nload) {
     if (tuned || !use_fast) return AHOM_OK;
     const Plan& P = pat->plan;
     hipStream_t st = stream;
+    const char* venv = getenv("AHOM_VERBOSE");
+    const bool verbose = venv && venv[0] == '1';
     if (ahom_launch_reset(d_st, nload, st)) return fail(AHOM_E_DEVICE, "reset");
     auto time_pass = [&](auto&& launch, float* best_ms) -> int {
         // one warm launch, then the minimum of three timed launches
@@ -398,6 +401,9 @@ int ahom_solver::autotune(int nload) {
             apply_variants();
             float ms = 0.f;
             if (time_pass([&]() { return launch_v(); }, &ms)) return fail(AHOM_E_DEVICE, "autotune launch failed");
+            if (verbose)
+                fprintf(stderr, "[ahom tune] pass %d L %d axis %d variant %d (NC %d, %s): %.4f ms\n", kind, L, axis, v, fg.NC,
+                        fg.persistent ? "persistent" : "one tile per WG", ms);
             if (ms < best) { best = ms; best_v = v; }
         }
         *vsel = best_v;

@@ -382,7 +382,10 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         const int64_t tn = t + gridDim.x;
         if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
         else have = false;
-        if (!cur) continue;
+        if (!cur) {
+            if constexpr (!G::PERSIST) break;
+            continue;
+        }
         const LoadState& st = a.st[load];
         C* dst = reinterpret_cast<C*>((st.iter & 1) ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
         fft_cols<L, +1, CS>(Z, NP * NC, twl);
@@ -449,6 +452,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         if (tid == 0)
             for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * nct + t % nct) * NCOMP + c] = sig[c];
         __syncthreads();
+        if constexpr (!G::PERSIST) break;  // one tile per workgroup
     }
 }
 
@@ -548,7 +552,10 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
         const int64_t tn = t + gridDim.x;
         if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
         else have = false;
-        if (!cur) continue;
+        if (!cur) {
+            if constexpr (!G::PERSIST) break;
+            continue;
+        }
         fft_cols<L, DIR, CS>(X, NC, twl);
         const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
         for (int e = tid; e < L * NC; e += TH) {
@@ -560,6 +567,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             stg(base + addr(c0, cb, j, l), v);
         }
         __syncthreads();
+        if constexpr (!G::PERSIST) break;  // one tile per workgroup
     }
 }
 
@@ -651,7 +659,10 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         const int64_t tn = t + gridDim.x;
         if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
         else have = false;
-        if (!cur) continue;
+        if (!cur) {
+            if constexpr (!G::PERSIST) break;
+            continue;
+        }
         const LoadState& st = a.st[load];
         C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
         C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
@@ -766,11 +777,16 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         block_sum<1>(rv, reinterpret_cast<double*>(F));
         if (tid == 0) a.res_part[(int64_t)load * nct + t % nct] = rv[0];
         __syncthreads();
+        if constexpr (!G::PERSIST) break;  // one tile per workgroup
     }
 }
 
 // ----------------------------------------------------------------- dispatch
-namespace {
+// The launchers are explicit template instantiations split over several
+// compilation parts (AHOM_FAST_PART, see the build script) so that the many
+// kernel instantiations compile in parallel; part "dispatch" holds the
+// exported entry points.
+namespace ahom_fast_detail {
 
 template <typename T, int L, int NF, int V>
 FastGeom geom_of(int kind) {
@@ -876,6 +892,9 @@ int spec_TV(int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream
 #undef AHOM_FS
 }
 
+}  // namespace ahom_fast_detail
+
+namespace ahom_fast_detail {
 template <typename T>
 bool geom_T(int kind, int dim, int L, int v, FastGeom* g) {
     if (!tuned_length(L)) v = 0;
@@ -887,7 +906,39 @@ bool geom_T(int kind, int dim, int L, int v, FastGeom* g) {
     }
 }
 
-}  // namespace
+#define AHOM_DECL_TV(T, V)                                                                                          \
+    extern template int real_TV<T, V>(int, int, const RealArgs&, int64_t, int, hipStream_t);                     \
+    extern template int axis_TV<T, V>(int, int, const AxisArgs&, int64_t, int, hipStream_t);                     \
+    extern template int spec_TV<T, V>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+#define AHOM_INST_REAL(T, V) template int real_TV<T, V>(int, int, const RealArgs&, int64_t, int, hipStream_t);
+#define AHOM_INST_AXIS(T, V) template int axis_TV<T, V>(int, int, const AxisArgs&, int64_t, int, hipStream_t);
+#define AHOM_INST_SPEC(T, V) template int spec_TV<T, V>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+
+#if defined(AHOM_FAST_PART)
+#if AHOM_FAST_PART == 0
+AHOM_INST_REAL(double, 0) AHOM_INST_REAL(double, 1) AHOM_INST_REAL(double, 2) AHOM_INST_REAL(double, 3)
+#elif AHOM_FAST_PART == 1
+AHOM_INST_REAL(float, 0) AHOM_INST_REAL(float, 1) AHOM_INST_REAL(float, 2) AHOM_INST_REAL(float, 3)
+#elif AHOM_FAST_PART == 2
+AHOM_INST_AXIS(double, 0) AHOM_INST_AXIS(double, 1) AHOM_INST_AXIS(double, 2) AHOM_INST_AXIS(double, 3)
+#elif AHOM_FAST_PART == 3
+AHOM_INST_AXIS(float, 0) AHOM_INST_AXIS(float, 1) AHOM_INST_AXIS(float, 2) AHOM_INST_AXIS(float, 3)
+#elif AHOM_FAST_PART == 4
+AHOM_INST_SPEC(double, 0) AHOM_INST_SPEC(double, 1)
+#elif AHOM_FAST_PART == 5
+AHOM_INST_SPEC(double, 2) AHOM_INST_SPEC(double, 3)
+#elif AHOM_FAST_PART == 6
+AHOM_INST_SPEC(float, 0) AHOM_INST_SPEC(float, 1) AHOM_INST_SPEC(float, 2) AHOM_INST_SPEC(float, 3)
+#endif
+#else
+AHOM_DECL_TV(double, 0) AHOM_DECL_TV(double, 1) AHOM_DECL_TV(double, 2) AHOM_DECL_TV(double, 3)
+AHOM_DECL_TV(float, 0) AHOM_DECL_TV(float, 1) AHOM_DECL_TV(float, 2) AHOM_DECL_TV(float, 3)
+#endif
+
+}  // namespace ahom_fast_detail
+
+#if !defined(AHOM_FAST_PART)
+using namespace ahom_fast_detail;
 
 bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g) {
     return prec == 0 ? geom_T<double>(kind, dim, L, variant, g) : geom_T<float>(kind, dim, L, variant, g);
@@ -931,3 +982,4 @@ int ahom_launch_fast_spec(int prec, int dim, int L, int variant, const SpecArgs&
     rc = run();
     return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }
+#endif  // !AHOM_FAST_PART
