@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
     ap.add_argument("--fp64-only", action="store_true", help="throughput of the FP64 path only (profiling runs)")
+    ap.add_argument("--ttt-resid-period", type=int, default=4,
+                    help="residual evaluated every k iterations in the time-to-tolerance solves")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -144,8 +146,8 @@ def main():
     loads = mandel_loads()
     nload = loads.shape[0]
 
-    def make(prec, tol, max_iter, check):
-        S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=check)
+    def make(prec, tol, max_iter, check, resid_period=1):
+        S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=check, resid_period=resid_period)
         S.set_material(lame, ph)
         return S
 
@@ -187,7 +189,7 @@ def main():
     if not args.no_ttt:
         ttt = {}
         for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
-            S = make(prec, 1e-6, 3000, 16)
+            S = make(prec, 1e-6, 3000, 16, resid_period=args.ttt_resid_period)
             C, it = S.effective_stiffness()
             dev_ms, enq = S.last_timing()
             ttt[name] = dict(ms=round(dev_ms, 2), iters=[int(v) for v in it], e_eff=round(e_eff_from_ceff(C, g), 6),
@@ -213,6 +215,7 @@ def main():
                     if "fp32" in results else None),
         device_ms_per_step=round(main_res["device_ms_per_step"], 4),
         time_to_1e6=ttt,
+        time_to_1e6_resid_period=args.ttt_resid_period,
     )
     print(json.dumps(line))
 

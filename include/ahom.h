@@ -69,6 +69,10 @@ typedef struct ahom_config {
     int check_period;   /* iterations enqueued between host-side status reads (>= 1) */
     int nyquist;        /* AHOM_NYQUIST_HERMITIAN */
     void* stream;       /* hipStream_t to run on; NULL = the null stream */
+    int resid_period;   /* evaluate r(n) only for n = 0 (mod resid_period) and at max_iter
+                           (<= 1: every iteration).  The stop is the first evaluated n with
+                           r(n) <= tol; the traction terms are only read and written around
+                           evaluated iterations, which saves memory traffic. */
 } ahom_config;
 
 /* Library version, (major << 16) | (minor << 8) | patch. */

@@ -42,7 +42,8 @@ EXPORTS = [
 
 class Config(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
-                ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p)]
+                ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p),
+                ("resid_period", ct.c_int)]
 
 
 _P = ct.c_void_p
@@ -152,10 +153,10 @@ class Pattern:
 class Solver:
     """Algorithm 1 on a pattern (device buffers owned by the library)."""
 
-    def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None):
+    def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1):
         self.pattern = pattern
         self.ncomp = 6 if pattern.d == 3 else 3
-        self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream)
+        self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period)
         h = _P()
         _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
         self._h = h

@@ -123,6 +123,8 @@ struct ahom_solver {
     double lam0 = 0, mu0 = 0;
     double lam_lo = 0, lam_hi = 0, mu_lo = 0, mu_hi = 0;
     uint8_t* d_phase = nullptr;
+    uint8_t* d_phase_t = nullptr;      // transposed copies for the real-space pass
+    double* d_lame_pts_t = nullptr;
     double* d_lame_tab = nullptr;
     double* d_lame_pts = nullptr;
     // buffers
@@ -223,7 +225,7 @@ struct ahom_solver {
 
     ~ahom_solver() {
         release_buffers();
-        dfree(d_phase); dfree(d_lame_tab); dfree(d_lame_pts);
+        dfree(d_phase); dfree(d_lame_tab); dfree(d_lame_pts); dfree(d_phase_t); dfree(d_lame_pts_t);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -239,6 +241,8 @@ struct ahom_solver {
         a.phase = d_phase;
         a.lame_tab = d_lame_tab;
         a.lame_pts = d_lame_pts;
+        a.phase_t = d_phase_t;
+        a.lame_pts_t = d_lame_pts_t;
         a.lam0 = lam0;
         a.mu0 = mu0;
         a.sig_part = d_sig;
@@ -281,6 +285,8 @@ struct ahom_solver {
         a.res_part = d_res;
         a.NC = g_spec.NC;
         a.CS = g_spec.CS;
+        a.resid_period = cfg.resid_period;
+        a.max_iter = cfg.max_iter;
         return a;
     }
 
@@ -330,6 +336,7 @@ struct ahom_solver {
         r.m = P.m;
         r.tol = cfg.tol;
         r.max_iter = cfg.max_iter;
+        r.resid_period = cfg.resid_period;
         if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
         return AHOM_OK;
     }
@@ -561,6 +568,7 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     s->pat = p;
     s->cfg = *cfg;
     if (s->cfg.check_period < 1) s->cfg.check_period = 1;
+    if (s->cfg.resid_period < 1) s->cfg.resid_period = 1;
     s->prec = cfg->precision;
     s->dim = p->sf.d;
     s->ncomp = s->dim == 3 ? 6 : 3;
@@ -634,6 +642,14 @@ int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, co
             if (chk[i] >= n_phase) return fail(AHOM_E_ARG, "phase id out of range");
         HIPCHK(hipMemcpy(s->d_phase, phase, m, hipMemcpyHostToDevice));
     }
+    {
+        const Plan& P = s->pat->plan;
+        dfree(s->d_lame_pts_t);
+        if (!s->d_phase_t) HIPCHK(hipMalloc((void**)&s->d_phase_t, m));
+        if (ahom_launch_transpose(s->d_phase, s->d_phase_t, P.ax[0].len, m / P.ax[0].len, 1, s->stream))
+            return fail(AHOM_E_DEVICE, "transpose phase ids");
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     s->n_phase = n_phase;
     s->lam_lo = llo; s->lam_hi = lhi; s->mu_lo = mlo; s->mu_hi = mhi;
     s->has_material = true;
@@ -660,6 +676,14 @@ int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int 
     dfree(s->d_lame_pts);
     HIPCHK(hipMalloc((void**)&s->d_lame_pts, 2 * m * sizeof(double)));
     HIPCHK(hipMemcpy(s->d_lame_pts, hp, 2 * m * sizeof(double), hipMemcpyHostToDevice));
+    {
+        const Plan& P = s->pat->plan;
+        dfree(s->d_lame_pts_t);
+        HIPCHK(hipMalloc((void**)&s->d_lame_pts_t, 2 * m * sizeof(double)));
+        if (ahom_launch_transpose(s->d_lame_pts, s->d_lame_pts_t, P.ax[0].len, m / P.ax[0].len, 16, s->stream))
+            return fail(AHOM_E_DEVICE, "transpose stiffness field");
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     s->lam_lo = llo; s->lam_hi = lhi; s->mu_lo = mlo; s->mu_hi = mhi;
     s->has_material = true;
     if (!s->ref_set) { s->lam0 = 0.5 * (llo + lhi); s->mu0 = 0.5 * (mlo + mhi); }
@@ -816,7 +840,7 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
     ReduceArgs r{};
     r.st = s->d_st; r.sig_part = s->d_sig; r.res_part = s->d_res; r.hist = s->d_hist;
     r.n_real = s->n_real_wg(); r.n_spec = s->n_spec_wg(); r.hist_cap = s->hist_cap; r.m = P.m;
-    r.tol = -1.0; r.max_iter = 1 << 30;
+    r.tol = -1.0; r.max_iter = 1 << 30; r.resid_period = s->cfg.resid_period;
     for (int it = 0; it < n_iter; ++it) {
         int p = 0;
         HIPCHK(hipEventRecord(ev[p], st));

@@ -394,15 +394,17 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
         for (int e = tid; e < L * NC; e += TH) {
-            const int n = e / NC, j = e % NC;
+            // material arrays are stored column-major for this pass: one
+            // contiguous block of NC * L entries per tile
+            const int j = e / L, n = e % L;
             if (j >= ncol) continue;
-            const int64_t pt = (int64_t)n * I + c0 + j;
+            const int64_t pt_t = (c0 + j) * (int64_t)L + n;
             T lam, mu;
-            if (a.lame_pts) {
-                lam = (T)a.lame_pts[2 * pt];
-                mu = (T)a.lame_pts[2 * pt + 1];
+            if (a.lame_pts_t) {
+                lam = (T)a.lame_pts_t[2 * pt_t];
+                mu = (T)a.lame_pts_t[2 * pt_t + 1];
             } else {
-                const int ph = a.phase[pt];
+                const int ph = a.phase_t[pt_t];
                 lam = (T)a.lame_tab[2 * ph];
                 mu = (T)a.lame_tab[2 * ph + 1];
             }
@@ -666,12 +668,14 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         const LoadState& st = a.st[load];
         C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
         C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
+        const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
+        const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
         // previous traction of this tile: in flight during the forward transform
         C oldv[EPT][NT];
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
-            if (e < NC * L && c0 + e / L < ncols) {
+            if (chk && e < NC * L && c0 + e / L < ncols) {
                 sfor<0, NT>([&](auto cc) __attribute__((always_inline)) {
                     constexpr int c = cc;
                     oldv[q][c] = ldg(tb + (int64_t)c * P.S + c0 * L + e);
@@ -734,14 +738,19 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 tt[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
             }
             const int64_t spos = c0 * L + e;
-            double r2 = 0.0;
+            if (chk) {
+                double r2 = 0.0;
 #pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
-                r2 += dx * dx + dy * dy;
-                stg(tb + (int64_t)c * P.S + spos, tt[c]);
+                for (int c = 0; c < NT; ++c) {
+                    const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
+                    r2 += dx * dx + dy * dy;
+                }
+                res += (double)kb[j * 4 + 3] * r2;
             }
-            res += (double)kb[j * 4 + 3] * r2;
+            if (wrt) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c) stg(tb + (int64_t)c * P.S + spos, tt[c]);
+            }
             C xt = C{(T)0, (T)0};
 #pragma unroll
             for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * tt[i].x; xt.y += xi[i] * tt[i].y; }

@@ -31,6 +31,8 @@ struct RealArgs {
     const uint8_t* phase;
     const double* lame_tab;   // (lambda, mu) per phase
     const double* lame_pts;   // or per point (nullptr if unused)
+    const uint8_t* phase_t;   // the same, transposed to [column][axis-0 position]
+    const double* lame_pts_t; //   (point n*I + c stored at c*L0 + n; fast kernels)
     double lam0, mu0;
     double* sig_part;         // [load][wg][ncomp]
     double* real_io;          // [load][ncomp][m] for TO_REAL / FROM_REAL
@@ -66,7 +68,17 @@ struct SpecArgs {
     double* res_part;         // [load][wg]
     int NC, CS;
     int nload;                // fast path: load cases covered by the persistent grid
+    int resid_period;         // evaluate the residual for iter = 0 (mod resid_period) and at max_iter
+    int max_iter;
 };
+
+// traction traffic of iteration n: read (and evaluate r(n)) / write t(n + 1)
+__host__ __device__ inline bool ahom_check_iter(int n, int period, int max_iter) {
+    return period <= 1 || n % period == 0 || n >= max_iter;
+}
+__host__ __device__ inline bool ahom_write_traction(int n, int period, int max_iter) {
+    return period <= 1 || ahom_check_iter(n + 1, period, max_iter);
+}
 
 struct ReduceArgs {
     LoadState* st;
@@ -77,6 +89,7 @@ struct ReduceArgs {
     int64_t m;
     double tol;
     int max_iter;
+    int resid_period;
 };
 
 struct FillArgs {
@@ -103,6 +116,8 @@ int ahom_launch_fill(int prec, const FillArgs& a, int nload, hipStream_t s);
 int ahom_launch_reset(LoadState* st, int n, hipStream_t s);
 int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s);
 int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s);
+// dst[c * L0 + n] = src[n * I + c] for elements of `bytes` bytes (1 or 16)
+int ahom_launch_transpose(const void* src, void* dst, int64_t L0, int64_t I, int bytes, hipStream_t s);
 
 // ---- power-of-two fast path (ahom_fast.hip)
 enum { FAST_REAL = 0, FAST_AXIS = 1, FAST_SPEC = 2 };

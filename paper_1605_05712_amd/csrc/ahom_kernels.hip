@@ -532,13 +532,17 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
         }
         // residual: sigma_hat(n) xi = t(n+1) - t(n) on active frequencies
         const double wgt = (kpos[0] == 0 || 2 * kpos[0] == L0) ? 1.0 : 2.0;
+        const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
+        const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
         double r2 = 0.0;
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
-            const C old = tb[(int64_t)c * P.S + spos];
-            const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
-            r2 += dx * dx + dy * dy;
-            tb[(int64_t)c * P.S + spos] = t[c];
+            if (chk) {
+                const C old = tb[(int64_t)c * P.S + spos];
+                const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
+                r2 += dx * dx + dy * dy;
+            }
+            if (wrt) tb[(int64_t)c * P.S + spos] = t[c];
         }
         res += wgt * r2;
         // v = (t - beta (xi . t) xi) / mu0 ; eps_hat = -sym(xi (x) v)
@@ -603,12 +607,18 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
         const bool diag = DIM == 3 ? c < 3 : c < 2;
         fro += (diag ? 1.0 : 2.0) * mean[c] * mean[c];
     }
-    const double r = sqrt(v[NC_]) / sqrt(fro);
     const int n = st.iter;
+    for (int c = 0; c < NC_; ++c) st.mean[c] = mean[c];
+    if (!ahom_check_iter(n, a.resid_period, a.max_iter)) {
+        // residual not evaluated on this iteration (recorded as -1)
+        if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = -1.0;
+        st.iter = n + 1;
+        return;
+    }
+    const double r = sqrt(v[NC_]) / sqrt(fro);
     if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = r;
     if (n == 0) st.r0 = r;
     st.resid = r;
-    for (int c = 0; c < NC_; ++c) st.mean[c] = mean[c];
     const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
     if (bad) { st.done = 1; st.status = 2; st.final_buf = n & 1; return; }
     if (r <= a.tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; return; }
@@ -766,5 +776,25 @@ int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s
     if (blocks > 4096) blocks = 4096;
     if (prec == 0) hipLaunchKernelGGL(k_reorder<double>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, a);
     else hipLaunchKernelGGL(k_reorder<float>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, a);
+    return AHOM_CHECK_LAUNCH();
+}
+
+template <typename E>
+__global__ void k_transpose(const E* __restrict__ src, E* __restrict__ dst, int64_t L0, int64_t I) {
+    const int64_t n_all = L0 * I;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_all; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / L0, n = i - c * L0;
+        dst[i] = src[n * I + c];
+    }
+}
+
+int ahom_launch_transpose(const void* src, void* dst, int64_t L0, int64_t I, int bytes, hipStream_t s) {
+    int64_t blocks = (L0 * I + AHOM_WG - 1) / AHOM_WG;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    if (bytes == 1)
+        hipLaunchKernelGGL(k_transpose<uint8_t>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (const uint8_t*)src, (uint8_t*)dst, L0, I);
+    else
+        hipLaunchKernelGGL(k_transpose<double2>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (const double2*)src, (double2*)dst, L0, I);
     return AHOM_CHECK_LAUNCH();
 }

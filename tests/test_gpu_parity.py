@@ -297,3 +297,28 @@ def test_every_tile_variant_matches_generic(name, M, prec, monkeypatch):
         out = S.solve(eb, want_strain=True)
         assert rel_err(out["strain"], ref["strain"]) < tol
         del S
+
+
+@pytest.mark.parametrize("M,period", [([[32, 0, 0], [0, 32, 0], [0, 0, 32]], 3), ([[24, 0], [0, 40]], 4)])
+def test_residual_period(M, period):
+    """Evaluating r(n) every `period` iterations: same iterates, same r at evaluated n."""
+    say("resid period", M, period)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(21, 3)(P.points(), P.m)
+    eb = np.eye(3)[None] * 0.01
+    S1 = ahom.Solver(P, tol=1e-6, max_iter=500)
+    S1.set_material(LAM3, ph)
+    o1 = S1.solve(eb)
+    h1 = S1.history(0)
+    Sk = ahom.Solver(P, tol=1e-6, max_iter=500, resid_period=period)
+    Sk.set_material(LAM3, ph)
+    ok = Sk.solve(eb)
+    hk = Sk.history(0)
+    n1 = int(o1["iters"][0])
+    expect = next(n for n in range(0, 501, period) if h1[n] <= 1e-6) if n1 < 500 else 500
+    assert int(ok["iters"][0]) == expect
+    for n in range(len(hk)):
+        if n % period == 0:
+            assert np.isclose(hk[n], h1[n], rtol=1e-9)
+        else:
+            assert hk[n] == -1.0
