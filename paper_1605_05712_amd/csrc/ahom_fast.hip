@@ -253,22 +253,28 @@ template <typename T> __device__ __forceinline__ T* smem() {
     return reinterpret_cast<T*>(ahom_fast_smem);
 }
 
-// fixed-order block sum of NV doubles (result in thread 0); scratch: NV * blockDim doubles
+// fixed-order block sum of NV doubles (result in thread 0): butterfly sums
+// inside each 64-lane wavefront, then the per-wave sums in wave order.
+// scratch: NV * (blockDim / 64) doubles.
 template <int NV>
 __device__ void block_sum(double* vals, double* scratch) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int c = 0; c < NV; ++c) scratch[c * nt + tid] = vals[c];
-    __syncthreads();
-    int n = nt;
-    while (n > 1) {
-        const int h = (n + 1) / 2;
-        if (tid < n - h)
-            for (int c = 0; c < NV; ++c) scratch[c * nt + tid] += scratch[c * nt + tid + h];
-        __syncthreads();
-        n = h;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        double v = vals[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        vals[c] = v;
     }
+    if (lane == 0)
+        for (int c = 0; c < NV; ++c) scratch[c * nw + wave] = vals[c];
+    __syncthreads();
     if (tid == 0)
-        for (int c = 0; c < NV; ++c) vals[c] = scratch[c * nt];
+        for (int c = 0; c < NV; ++c) {
+            double acc = 0.0;
+            for (int w = 0; w < nw; ++w) acc += scratch[c * nw + w];
+            vals[c] = acc;
+        }
 }
 
 // exact (A kappa) mod emax, centred; double path while products stay below 2^53

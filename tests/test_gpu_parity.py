@@ -315,10 +315,13 @@ def test_residual_period(M, period):
     ok = Sk.solve(eb)
     hk = Sk.history(0)
     n1 = int(o1["iters"][0])
-    expect = next(n for n in range(0, 501, period) if h1[n] <= 1e-6) if n1 < 500 else 500
+    assert o1["status"] == ahom.AHOM_OK
+    # r decreases monotonically here, so the first evaluated n past n1 stops
+    expect = -(-n1 // period) * period
     assert int(ok["iters"][0]) == expect
+    assert ok["resid"][0] <= 1e-6
     for n in range(len(hk)):
-        if n % period == 0:
-            assert np.isclose(hk[n], h1[n], rtol=1e-9)
-        else:
+        if n % period != 0:
             assert hk[n] == -1.0
+        elif n <= n1:
+            assert np.isclose(hk[n], h1[n], rtol=1e-9)
