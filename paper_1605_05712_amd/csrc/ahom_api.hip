@@ -201,6 +201,12 @@ struct ahom_solver {
         return AHOM_OK;
     }
 
+    int ensure_real_staging() {
+        if (d_real) return AHOM_OK;
+        HIPCHK(hipMalloc((void**)&d_real, (size_t)cap * ncomp * pat->plan.m * sizeof(double)));
+        return AHOM_OK;
+    }
+
     int ensure_capacity(int nload) {
         if (nload <= cap) return AHOM_OK;
         release_buffers();
@@ -218,7 +224,6 @@ struct ahom_solver {
         hist_cap = cfg.max_iter + 1;
         HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
-        HIPCHK(hipMalloc((void**)&d_real, (size_t)nload * ncomp * P.m * sizeof(double)));
         cap = nload;
         return AHOM_OK;
     }
@@ -725,9 +730,16 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
         f.nfield = nc;
         if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
     } else {
-        const size_t bytes = (size_t)n_load * nc * P.m * sizeof(double);
-        HIPCHK(hipMemcpyAsync(s->d_real, init, bytes, mem_flags == AHOM_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-        if (ahom_launch_real(s->prec, s->dim, REAL_FROM_REAL, s->real_args(REAL_FROM_REAL), s->g_real.nwg, n_load, s->g_real.lds, st))
+        RealArgs fr = s->real_args(REAL_FROM_REAL);
+        if (mem_flags == AHOM_MEM_DEVICE) {
+            fr.real_io = const_cast<double*>(static_cast<const double*>(init));
+        } else {
+            if ((rc = s->ensure_real_staging())) return rc;
+            const size_t bytes = (size_t)n_load * nc * P.m * sizeof(double);
+            HIPCHK(hipMemcpyAsync(s->d_real, init, bytes, hipMemcpyHostToDevice, st));
+            fr.real_io = s->d_real;
+        }
+        if (ahom_launch_real(s->prec, s->dim, REAL_FROM_REAL, fr, s->g_real.nwg, n_load, s->g_real.lds, st))
             return fail(AHOM_E_DEVICE, "launch from_real");
         // traction of eps(0): t(0) = -(C0 : eps_hat(0)) xi, so that the first
         // residual is sigma_hat(0) xi = t(1) - t(0) as on later iterations
@@ -769,6 +781,7 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     s->last_enqueued = enq;
     s->last_nload = n_load;
     if (strain_out) {
+        if (mem_flags != AHOM_MEM_DEVICE && (rc = s->ensure_real_staging())) return rc;
         RealArgs ra = s->real_args(REAL_TO_REAL);
         if (mem_flags == AHOM_MEM_DEVICE) ra.real_io = (double*)strain_out;
         if (ahom_launch_real(s->prec, s->dim, REAL_TO_REAL, ra, s->g_real.nwg, n_load, s->g_real.lds, st))

@@ -214,13 +214,34 @@ def spheres_rsa(seed=3, rmin=0.03, rmax=0.08, target=0.3, max_tries=200000):
 
 
 def spheres_phase(points_num, m, centres, radii):
-    """1 inside any (periodic) sphere, else 0."""
+    """1 inside any (periodic) sphere, else 0 (closed balls, minimum image).
+
+    Points are binned into cells at least one diameter wide, so each sphere is
+    tested only against the points of the 27 cells around its centre.
+    """
     y = np.asarray(points_num, dtype=np.float64) / m
+    d = y.shape[1]
     ph = np.zeros(y.shape[0], dtype=np.uint8)
+    if len(radii) == 0:
+        return ph
+    nc = max(1, int(1.0 / (2.0 * float(np.max(radii)))))
+    cell = np.floor((y + 0.5) * nc).astype(np.int64) % nc
+    key = np.zeros(y.shape[0], dtype=np.int64)
+    for k in range(d):
+        key = key * nc + cell[:, k]
+    order = np.argsort(key, kind="stable")
+    skey = key[order]
+    starts = np.searchsorted(skey, np.arange(nc ** d))
+    ends = np.searchsorted(skey, np.arange(nc ** d), side="right")
+    offs = np.array(np.meshgrid(*([[-1, 0, 1]] * d), indexing="ij")).reshape(d, -1).T
     for c, r in zip(centres, radii):
-        dv = y - c
+        cc = np.floor((np.asarray(c[:d]) + 0.5) * nc).astype(np.int64) % nc
+        nb = (cc[None, :] + offs) % nc
+        nkeys = np.unique(np.ravel_multi_index(nb.T, (nc,) * d))
+        idx = np.concatenate([order[starts[k]:ends[k]] for k in nkeys])
+        dv = y[idx] - np.asarray(c[:d])
         dv -= np.round(dv)
-        ph[np.sum(dv * dv, axis=1) <= r * r] = 1
+        ph[idx[np.sum(dv * dv, axis=1) <= r * r]] = 1
     return ph
 
 

@@ -325,3 +325,26 @@ def test_residual_period(M, period):
             assert hk[n] == -1.0
         elif n <= n1:
             assert np.isclose(hk[n], h1[n], rtol=1e-9)
+
+
+def test_device_memory_path():
+    """AHOM_MEM_DEVICE: phase ids, initial fluctuation and strain out as torch device tensors."""
+    import torch
+    M = [[16, 0, 0], [4, 16, 0], [0, 0, 8]]
+    say("device memory", M)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(31, 3)(P.points(), P.m)
+    rng = np.random.default_rng(5)
+    init = rng.standard_normal((1, 6, P.m)) * 0.01
+    eb = (np.eye(3) * 0.02)[None]
+    S1 = ahom.Solver(P, tol=0.0, max_iter=3)
+    S1.set_material(LAM3, ph)
+    ref = S1.solve(eb, init=init, want_strain=True)
+    S2 = ahom.Solver(P, tol=0.0, max_iter=3, stream=torch.cuda.current_stream().cuda_stream)
+    S2.set_material(LAM3, torch.from_numpy(ph).cuda())
+    d_init = torch.from_numpy(init).cuda()
+    d_out = torch.empty((1, 6, P.m), dtype=torch.float64, device="cuda")
+    out = S2.solve_device(eb, strain_out=d_out, init=d_init)
+    torch.cuda.synchronize()
+    assert np.array_equal(d_out.cpu().numpy(), ref["strain"])
+    assert np.array_equal(out["mean_stress"], ref["mean_stress"])
