@@ -73,6 +73,16 @@ typedef struct ahom_config {
                            (<= 1: every iteration).  The stop is the first evaluated n with
                            r(n) <= tol; the traction terms are only read and written around
                            evaluated iterations, which saves memory traffic. */
+    double refine;      /* AHOM_FP32_MIXED only: defect-correction restarts.  The FP32
+                           iteration runs until r(n) <= max(tol, refine * r_stage), where
+                           r_stage is 1 for the first stage; then the strain is handed to
+                           FP64, two FP64 updates give the accurate defect (traction step)
+                           of the FP64 iterate, and a new FP32 stage iterates on the
+                           correction to that iterate with the defect as a fixed traction
+                           offset, so FP32 rounding scales with the correction rather than
+                           with the whole field.  0 = default 1e-3; < 0 = no restarts (the
+                           plain FP32 iteration, whose residual floor is set by FP32
+                           rounding of the polarization). */
 } ahom_config;
 
 /* Library version, (major << 16) | (minor << 8) | patch. */
@@ -163,6 +173,10 @@ int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0);
  * Returns AHOM_OK if every load converged, AHOM_W_NOT_CONVERGED if some load
  * reached max_iter (outputs hold that iterate), AHOM_E_DIVERGED if some
  * load diverged, or an error.
+ * AHOM_FP32_MIXED with refine > 0: after each FP32 stage the iterate is
+ * handed to FP64 (see ahom_config.refine); a restart performs two FP64
+ * updates and advances n_k by one, and the returned strain is the FP64
+ * iterate plus the FP32 correction.  The history keeps one value per n.
  */
 int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* init, void* strain_out,
                int* iters, double* resid, double* mean_stress, int mem_flags);
@@ -180,6 +194,12 @@ int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters);
  * solver's stream), and the number of iterations enqueued.
  */
 int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* iterations_enqueued);
+
+/*
+ * Number of FP64 defect-correction restarts in the last ahom_solve (0 for
+ * AHOM_FP64, for refine < 0, or when the first FP32 stage met tol).
+ */
+int ahom_solver_last_restarts(const ahom_solver* s, int* n);
 
 /*
  * Per-pass device timing (profiling mode): runs n_iter iterations of the

@@ -1,8 +1,14 @@
 """Thin ctypes binding of libahom (argument marshalling only).
 
 Every step of the computation runs in the HIP library; this module only
-converts Python/numpy/torch arguments to pointers and sizes.  Importing it
-fails loudly if the library has not been built.
+converts Python/numpy arguments to pointers and sizes.  Importing it fails
+loudly if the library has not been built.
+
+Device-resident arguments (MEM_DEVICE) are objects with a ``data_ptr()``
+method: ``DeviceArray`` below, which allocates through the HIP runtime that
+the library itself links, or any other device allocation of the same
+runtime.  PyTorch wheels bundle a HIP runtime of their own; two runtimes in
+one process are not supported by this binding.
 """
 from __future__ import annotations
 
@@ -36,14 +42,15 @@ EXPORTS = [
     "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_destroy", "ahom_pattern_info",
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
-    "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_history", "ahom_solver_pass_times",
+    "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
+    "ahom_solver_pass_times",
 ]
 
 
 class Config(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p),
-                ("resid_period", ct.c_int)]
+                ("resid_period", ct.c_int), ("refine", ct.c_double)]
 
 
 _P = ct.c_void_p
@@ -69,6 +76,7 @@ _lib.ahom_solver_set_reference.argtypes = [_P, ct.c_double, ct.c_double]
 _lib.ahom_solve.argtypes = [_P, ct.c_int, _dp, _P, _P, _ip, _dp, _dp, ct.c_int]
 _lib.ahom_effective_stiffness.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
+_lib.ahom_solver_last_restarts.argtypes = [_P, _ip]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
 
@@ -93,8 +101,66 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(ct.POINTER(ctype))
 
 
-def _is_torch(x):
-    return type(x).__module__.startswith("torch")
+def _is_device(x):
+    return hasattr(x, "data_ptr")
+
+
+# the HIP runtime the library is linked against (already loaded with it)
+_hip = ct.CDLL("libamdhip64.so.7")
+_hip.hipMalloc.argtypes = [ct.POINTER(ct.c_void_p), ct.c_size_t]
+_hip.hipFree.argtypes = [ct.c_void_p]
+_hip.hipMemcpy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_int]
+_hip.hipGetDeviceCount.argtypes = [ct.POINTER(ct.c_int)]
+_HIP_H2D, _HIP_D2H, _HIP_D2D = 1, 2, 3
+
+
+def device_count():
+    """Number of HIP devices visible to the library's runtime (0 if none)."""
+    n = ct.c_int(0)
+    return n.value if _hip.hipGetDeviceCount(ct.byref(n)) == 0 else 0
+
+
+class DeviceArray:
+    """A device allocation of the library's HIP runtime with a numpy shape/dtype."""
+
+    def __init__(self, shape, dtype):
+        self.shape = tuple(int(v) for v in np.atleast_1d(shape))
+        self.dtype = np.dtype(dtype)
+        self.nbytes = int(np.prod(self.shape)) * self.dtype.itemsize
+        p = ct.c_void_p()
+        rc = _hip.hipMalloc(ct.byref(p), max(self.nbytes, 1))
+        if rc != 0:
+            raise AhomError(AHOM_E_DEVICE, f"hipMalloc of {self.nbytes} bytes failed ({rc})")
+        self._p = p
+
+    @classmethod
+    def from_numpy(cls, a):
+        a = np.ascontiguousarray(a)
+        d = cls(a.shape, a.dtype)
+        if d.nbytes and _hip.hipMemcpy(d._p, a.ctypes.data, d.nbytes, _HIP_H2D) != 0:
+            raise AhomError(AHOM_E_DEVICE, "hipMemcpy to device failed")
+        return d
+
+    def numpy(self):
+        out = np.empty(self.shape, self.dtype)
+        if self.nbytes and _hip.hipMemcpy(out.ctypes.data, self._p, self.nbytes, _HIP_D2H) != 0:
+            raise AhomError(AHOM_E_DEVICE, "hipMemcpy to host failed")
+        return out
+
+    def copy_from(self, other):
+        """Device-to-device copy of another DeviceArray of the same size."""
+        if other.nbytes != self.nbytes:
+            raise ValueError("size mismatch")
+        if self.nbytes and _hip.hipMemcpy(self._p, other._p, self.nbytes, _HIP_D2D) != 0:
+            raise AhomError(AHOM_E_DEVICE, "hipMemcpy device to device failed")
+
+    def data_ptr(self):
+        return self._p.value
+
+    def __del__(self):
+        if getattr(self, "_p", None) and self._p.value:
+            _hip.hipFree(self._p)
+            self._p = ct.c_void_p()
 
 
 class Pattern:
@@ -128,13 +194,12 @@ class Pattern:
         _check(_lib.ahom_pattern_freqs(self._h, _ptr(out, ct.c_int64)))
         return out
 
-    def dft(self, a, sign=-1, precision=FP64, stream=None):
-        """Pattern DFT of m complex values (numpy: host path; torch cuda: device path)."""
-        if _is_torch(a):
-            import torch
-            out = torch.empty_like(a)
-            s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
-            _check(_lib.ahom_dft(self._h, sign, precision, a.data_ptr(), out.data_ptr(), MEM_DEVICE, s))
+    def dft(self, a, sign=-1, precision=FP64, stream=None, out=None):
+        """Pattern DFT of m complex values (numpy: host path; DeviceArray: device path)."""
+        if _is_device(a):
+            if out is None:
+                out = DeviceArray(a.shape, a.dtype)
+            _check(_lib.ahom_dft(self._h, sign, precision, a.data_ptr(), out.data_ptr(), MEM_DEVICE, stream))
             return out
         dt = np.complex128 if precision == FP64 else np.complex64
         a = np.ascontiguousarray(np.asarray(a, dtype=dt))
@@ -153,17 +218,18 @@ class Pattern:
 class Solver:
     """Algorithm 1 on a pattern (device buffers owned by the library)."""
 
-    def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1):
+    def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1,
+                 refine=0.0):
         self.pattern = pattern
         self.ncomp = 6 if pattern.d == 3 else 3
-        self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period)
+        self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period, refine)
         h = _P()
         _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
         self._h = h
 
     def set_material(self, lame, phase):
         lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
-        if _is_torch(phase):
+        if _is_device(phase):
             _check(_lib.ahom_solver_set_material(self._h, lame.shape[0], _ptr(lame, ct.c_double), phase.data_ptr(), MEM_DEVICE))
         else:
             ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
@@ -195,7 +261,7 @@ class Solver:
         return dict(status=rc, iters=iters, resid=resid, mean_stress=mean.reshape(n, 3, 3), strain=strain)
 
     def solve_device(self, eps_bar, strain_out=None, init=None, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
-        """Like solve() with device-resident field arrays (torch cuda tensors, float64)."""
+        """Like solve() with device-resident field arrays (DeviceArray, float64)."""
         eb = np.ascontiguousarray(np.asarray(eps_bar, dtype=np.float64).reshape(-1, 9))
         n = eb.shape[0]
         iters = np.zeros(n, np.int32)
@@ -221,6 +287,12 @@ class Solver:
         enq = ct.c_int()
         _check(_lib.ahom_solver_last_timing(self._h, ct.byref(ms), ct.byref(enq)))
         return ms.value, enq.value
+
+    def last_restarts(self):
+        """FP64 defect-correction restarts of the last solve."""
+        n = ct.c_int()
+        _check(_lib.ahom_solver_last_restarts(self._h, ct.byref(n)))
+        return n.value
 
     def pass_times(self, n_iter=10):
         """Mean ms per pass and algorithmic bytes per launch (profiling mode)."""

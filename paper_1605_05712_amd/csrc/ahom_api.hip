@@ -140,6 +140,19 @@ struct ahom_solver {
     double* d_epsbar = nullptr;
     double* d_real = nullptr;
     int hist_cap = 0;
+    // FP32 defect-correction restarts: an FP64 solver on the same pattern that
+    // borrows this solver's material arrays, the FP32 traction offset and the
+    // mean stress of the FP64 iterate
+    ahom_solver* ref64 = nullptr;
+    bool borrowed = false;
+    void* d_toff = nullptr;
+    double* d_sigbase = nullptr;
+    // per-stage settings read by the launches
+    double cur_tol = 0.0;
+    const void* spec_toff = nullptr;
+    void* spec_dout = nullptr;
+    void* spec_dneg = nullptr;
+    const double* red_sig_base = nullptr;
     // geometry: generic kernels (always available) and the power-of-two fast path
     PassGeom g_real, g_spec, g_axis[AHOM_MAX_AXES];
     bool f_real = false, f_spec = false, f_axis[AHOM_MAX_AXES] = {};
@@ -189,12 +202,13 @@ struct ahom_solver {
     double last_ms = 0;
     int last_enqueued = 0;
     int last_nload = 0;
+    int last_restarts = 0;
 
     size_t es() const { return prec == AHOM_FP64 ? 16 : 8; }
 
     int release_buffers() {
         dfree(d_buf0); dfree(d_buf1); dfree(d_tbuf); dfree(d_st); dfree(d_sig);
-        dfree(d_res); dfree(d_hist); dfree(d_epsbar); dfree(d_real);
+        dfree(d_res); dfree(d_hist); dfree(d_epsbar); dfree(d_real); dfree(d_toff); dfree(d_sigbase);
         if (h_st) (void)hipHostFree(h_st);
         h_st = nullptr;
         cap = 0;
@@ -224,12 +238,23 @@ struct ahom_solver {
         hist_cap = cfg.max_iter + 1;
         HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_sigbase, (size_t)nload * ncomp * sizeof(double)));
+        if (prec == AHOM_FP32_MIXED && cfg.refine > 0.0) {
+            const size_t tb = (size_t)nload * nt * P.S * sizeof(float2);
+            HIPCHK(hipMalloc(&d_toff, tb));
+            HIPCHK(hipMemset(d_toff, 0, tb));
+        }
         cap = nload;
         return AHOM_OK;
     }
 
     ~ahom_solver() {
         release_buffers();
+        delete ref64;
+        if (borrowed) {
+            d_phase = d_phase_t = nullptr;
+            d_lame_tab = d_lame_pts = d_lame_pts_t = nullptr;
+        }
         dfree(d_phase); dfree(d_lame_tab); dfree(d_lame_pts); dfree(d_phase_t); dfree(d_lame_pts_t);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -292,6 +317,9 @@ struct ahom_solver {
         a.CS = g_spec.CS;
         a.resid_period = cfg.resid_period;
         a.max_iter = cfg.max_iter;
+        a.toff = spec_toff;
+        a.dout = spec_dout;
+        a.dneg = spec_dneg;
         return a;
     }
 
@@ -339,9 +367,10 @@ struct ahom_solver {
         r.n_spec = n_spec_wg();
         r.hist_cap = hist_cap;
         r.m = P.m;
-        r.tol = cfg.tol;
+        r.tol = cur_tol;
         r.max_iter = cfg.max_iter;
         r.resid_period = cfg.resid_period;
+        r.sig_base = red_sig_base;
         if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
         return AHOM_OK;
     }
@@ -439,6 +468,101 @@ int ahom_solver::autotune(int nload) {
 }
 
 // ============================================================================ API
+namespace {
+int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
+    *out = nullptr;
+    if (p->sf.m < 2) return fail(AHOM_E_ARG, "trivial pattern (m = 1): the strain is eps_bar");
+    int rc = p->ensure_device();
+    if (rc) return rc;
+    ahom_solver* s = new (std::nothrow) ahom_solver();
+    if (!s) return fail(AHOM_E_NOMEM, "host allocation failed");
+    s->pat = p;
+    s->cfg = *cfg;
+    s->cur_tol = cfg->tol;
+    if (s->cfg.refine == 0.0) s->cfg.refine = 1e-3;
+    if (s->cfg.check_period < 1) s->cfg.check_period = 1;
+    if (s->cfg.resid_period < 1) s->cfg.resid_period = 1;
+    s->prec = cfg->precision;
+    s->dim = p->sf.d;
+    s->ncomp = s->dim == 3 ? 6 : 3;
+    s->npack = s->dim == 3 ? 3 : 2;
+    s->nt = s->dim == 3 ? 3 : 2;
+    s->stream = (hipStream_t)cfg->stream;
+    const Plan& P = p->plan;
+    const size_t es = s->es();
+    auto bad = [&](int code) { delete s; return code; };
+    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)s->ncomp * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
+    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
+    for (int a = 1; a <= P.D - 2; ++a) {
+        int64_t O = 1, I = 1;
+        for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
+        for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
+        if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, s->prec, &s->g_axis[a]))) return bad(rc);
+    }
+    {
+        const char* env = getenv("AHOM_GENERIC_ONLY");
+        s->use_fast = !(env && env[0] == '1');
+    }
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int n = 0;
+            if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) s->ncu = n;
+        }
+    }
+    if (s->use_fast) {
+        FastGeom fg;
+        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, 0, &fg)) s->f_real = true;
+        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, 0, &fg)) s->f_spec = true;
+        for (int a = 1; a <= P.D - 2; ++a)
+            if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, 0, &fg)) s->f_axis[a] = true;
+        const char* venv = getenv("AHOM_FAST_VARIANT");
+        if (venv && venv[0] >= '0' && venv[0] <= '3') {
+            const int v = venv[0] - '0';
+            s->v_real = s->v_spec = v;
+            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v;
+            s->tuned = true;
+        }
+        s->apply_variants();
+    }
+    if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
+        return bad(fail(AHOM_E_DEVICE, "event create"));
+    *out = s;
+    return AHOM_OK;
+}
+
+// FP64 companion of an FP32 solver for the defect-correction restarts: two
+// updates per restart, no stop on the residual, the parent's material arrays
+int ensure_ref64(ahom_solver* s, int nload) {
+    if (!s->ref64) {
+        ahom_config c = s->cfg;
+        c.precision = AHOM_FP64;
+        c.max_iter = 1;
+        c.resid_period = 1;
+        c.check_period = 2;
+        c.refine = -1.0;
+        int rc = create_solver(s->pat, &c, &s->ref64);
+        if (rc) return rc;
+        s->ref64->borrowed = true;
+        s->ref64->cur_tol = -1.0;
+    }
+    ahom_solver* r = s->ref64;
+    r->d_phase = s->d_phase;
+    r->d_phase_t = s->d_phase_t;
+    r->d_lame_tab = s->d_lame_tab;
+    r->d_lame_pts = s->d_lame_pts;
+    r->d_lame_pts_t = s->d_lame_pts_t;
+    r->n_phase = s->n_phase;
+    r->lam0 = s->lam0;
+    r->mu0 = s->mu0;
+    r->has_material = true;
+    int rc = r->ensure_capacity(nload);
+    if (rc) return rc;
+    return r->autotune(nload);
+}
+
+}  // namespace
+
 extern "C" {
 
 int ahom_version(void) { return (0 << 16) | (1 << 8) | 0; }
@@ -564,63 +688,8 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     if (cfg->precision != AHOM_FP64 && cfg->precision != AHOM_FP32_MIXED) return fail(AHOM_E_ARG, "bad precision");
     if (cfg->max_iter < 0 || !(cfg->tol >= 0.0)) return fail(AHOM_E_ARG, "bad tol/max_iter");
     if (cfg->nyquist != AHOM_NYQUIST_HERMITIAN) return fail(AHOM_E_ARG, "unsupported Nyquist rule");
-    ahom_pattern* p = const_cast<ahom_pattern*>(pc);
-    if (p->sf.m < 2) return fail(AHOM_E_ARG, "trivial pattern (m = 1): the strain is eps_bar");
-    int rc = p->ensure_device();
-    if (rc) return rc;
-    ahom_solver* s = new (std::nothrow) ahom_solver();
-    if (!s) return fail(AHOM_E_NOMEM, "host allocation failed");
-    s->pat = p;
-    s->cfg = *cfg;
-    if (s->cfg.check_period < 1) s->cfg.check_period = 1;
-    if (s->cfg.resid_period < 1) s->cfg.resid_period = 1;
-    s->prec = cfg->precision;
-    s->dim = p->sf.d;
-    s->ncomp = s->dim == 3 ? 6 : 3;
-    s->npack = s->dim == 3 ? 3 : 2;
-    s->nt = s->dim == 3 ? 3 : 2;
-    s->stream = (hipStream_t)cfg->stream;
-    const Plan& P = p->plan;
-    const size_t es = s->es();
-    auto bad = [&](int code) { delete s; return code; };
-    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)s->ncomp * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
-    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
-    for (int a = 1; a <= P.D - 2; ++a) {
-        int64_t O = 1, I = 1;
-        for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
-        for (int b = a + 1; b < P.D; ++b) I *= P.ax[b].slen;
-        if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, s->prec, &s->g_axis[a]))) return bad(rc);
-    }
-    {
-        const char* env = getenv("AHOM_GENERIC_ONLY");
-        s->use_fast = !(env && env[0] == '1');
-    }
-    {
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) {
-            int n = 0;
-            if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) s->ncu = n;
-        }
-    }
-    if (s->use_fast) {
-        FastGeom fg;
-        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, 0, &fg)) s->f_real = true;
-        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, 0, &fg)) s->f_spec = true;
-        for (int a = 1; a <= P.D - 2; ++a)
-            if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, 0, &fg)) s->f_axis[a] = true;
-        const char* venv = getenv("AHOM_FAST_VARIANT");
-        if (venv && venv[0] >= '0' && venv[0] <= '3') {
-            const int v = venv[0] - '0';
-            s->v_real = s->v_spec = v;
-            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v;
-            s->tuned = true;
-        }
-        s->apply_variants();
-    }
-    if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
-        return bad(fail(AHOM_E_DEVICE, "event create"));
-    *out = s;
-    return AHOM_OK;
+    if (!(cfg->refine < 1.0)) return fail(AHOM_E_ARG, "refine must be < 1");
+    return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
 }
 
 void ahom_solver_destroy(ahom_solver* s) { delete s; }
@@ -710,25 +779,36 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
+    s->spec_toff = nullptr;
+    s->spec_dout = s->spec_dneg = nullptr;
+    s->red_sig_base = nullptr;
+    s->cur_tol = s->cfg.tol;
     if ((rc = s->autotune(n_load))) return rc;
     const Plan& P = s->pat->plan;
     const int nc = s->ncomp;
     const int* comp = s->dim == 3 ? kComp3 : kComp2;
     hipStream_t st = s->stream;
+    const bool refine = s->prec == AHOM_FP32_MIXED && s->cfg.refine > 0.0;
+    if (refine) s->cur_tol = std::max(s->cfg.tol, s->cfg.refine);
+    // set up the FP64 companion ahead of the timed region when a restart is expected
+    if (refine && s->cfg.tol < s->cur_tol && (rc = ensure_ref64(s, n_load))) return rc;
     std::vector<double> eb((size_t)n_load * nc);
     for (int l = 0; l < n_load; ++l)
         for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
     HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
     if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
     if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
-    if (!init) {
+    auto fill = [&](void* buf) -> int {
         FillArgs f{};
-        f.buf = s->d_buf0;
+        f.buf = buf;
         f.eps_bar = s->d_epsbar;
         f.S = P.S;
         f.row = P.S / P.ax[0].slen;
         f.nfield = nc;
-        if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+        return ahom_launch_fill(s->prec, f, n_load, st);
+    };
+    if (!init) {
+        if (fill(s->d_buf0)) return fail(AHOM_E_DEVICE, "fill");
     } else {
         RealArgs fr = s->real_args(REAL_FROM_REAL);
         if (mem_flags == AHOM_MEM_DEVICE) {
@@ -760,36 +840,132 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     }
     HIPCHK(hipEventRecord(s->ev0, st));
     int enq = 0;
-    const int limit = s->cfg.max_iter + 1;
-    bool all_done = false;
-    while (!all_done) {
-        const int k = std::min(s->cfg.check_period, std::max(1, limit - enq));
-        for (int i = 0; i < k; ++i) {
-            if ((rc = s->enqueue_iteration(n_load))) return rc;
-            ++enq;
+    // iterate until every load case has stopped (device-side loop control);
+    // the host reads the load states every check_period iterations
+    auto run_stage = [&]() -> int {
+        const int limit = s->cfg.max_iter + 1;
+        int local = 0;
+        bool all_done = false;
+        while (!all_done) {
+            const int k = std::min(s->cfg.check_period, std::max(1, limit - local));
+            for (int i = 0; i < k; ++i) {
+                int rc2 = s->enqueue_iteration(n_load);
+                if (rc2) return rc2;
+                ++local;
+                ++enq;
+            }
+            HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(s->ev1, st));
+            HIPCHK(hipStreamSynchronize(st));
+            all_done = true;
+            for (int l = 0; l < n_load; ++l) all_done = all_done && s->h_st[l].done;
+            if (local > limit + 2 * s->cfg.check_period) return fail(AHOM_E_DEVICE, "loop control did not terminate");
         }
-        HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(s->ev1, st));
+        return AHOM_OK;
+    };
+    if ((rc = run_stage())) return rc;
+
+    // FP32 defect-correction restarts (see ahom_config.refine).  With the FP64
+    // iterate eps_b = F(eps_h) (one FP64 update of eps_h = FP64 base + FP32
+    // state) and its traction step d = t(eps_b) - t(eps_h), the correction
+    // e = eps - eps_b obeys e(k+1) = Gamma0-map of (t(e(k)) + d) with zero
+    // mean, and the residual of eps_b + e(k) is t(e(k)) - t(e(k-1)), with
+    // t(e(-1)) = -d.  The mean stress is that of eps_b plus that of e.
+    int nrestart = 0;
+    std::vector<double> hsig((size_t)n_load * nc), zeros((size_t)n_load * nc, 0.0), hrec(n_load);
+    while (refine) {
+        bool need = false, stop = false;
+        for (int l = 0; l < n_load; ++l) {
+            const LoadState& ls = s->h_st[l];
+            if (ls.status != 0) stop = true;
+            else if (ls.resid > s->cfg.tol) need = true;
+        }
+        if (stop || !need) break;
+        if ((rc = ensure_ref64(s, n_load))) return rc;
+        ahom_solver* r = s->ref64;
+        HIPCHK(hipMemcpyAsync(r->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        GatherArgs g{};
+        g.out = static_cast<double2*>(r->d_buf0);
+        g.base = nrestart ? static_cast<const double2*>(r->d_buf1) : nullptr;
+        g.in0 = static_cast<const float2*>(s->d_buf0);
+        g.in1 = static_cast<const float2*>(s->d_buf1);
+        g.st = s->d_st;
+        g.per_load = (int64_t)nc * P.S;
+        if (ahom_launch_refine_gather(g, n_load, st)) return fail(AHOM_E_DEVICE, "launch refine gather");
+        if (ahom_launch_reset(r->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+        if (ahom_launch_zero(AHOM_FP64, r->d_tbuf, (int64_t)n_load * r->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+        r->spec_dout = s->d_toff;
+        r->spec_dneg = s->d_tbuf;
+        for (int i = 0; i < 2; ++i)
+            if ((rc = r->enqueue_iteration(n_load))) { r->spec_dout = r->spec_dneg = nullptr; return rc; }
+        r->spec_dout = r->spec_dneg = nullptr;
+        enq += 2;
+        HIPCHK(hipMemcpyAsync(r->h_st, r->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        all_done = true;
-        for (int l = 0; l < n_load; ++l) all_done = all_done && s->h_st[l].done;
-        if (enq > limit + 2 * s->cfg.check_period) return fail(AHOM_E_DEVICE, "loop control did not terminate");
+        double rmax = 0.0;
+        bool any = false;
+        for (int l = 0; l < n_load; ++l) {
+            const LoadState& lr = r->h_st[l];
+            LoadState ls{};
+            ls.iter = std::min(s->h_st[l].iter + 1, s->cfg.max_iter);
+            ls.r0 = s->h_st[l].r0;
+            ls.resid = lr.resid;
+            for (int c = 0; c < nc; ++c) ls.mean[c] = hsig[(size_t)l * nc + c] = lr.mean[c];
+            ls.final_buf = ls.iter & 1;
+            if (!(lr.resid == lr.resid) || std::isinf(lr.resid)) { ls.done = 1; ls.status = 2; }
+            else if (lr.resid <= s->cfg.tol) { ls.done = 1; ls.status = 0; }
+            else if (ls.iter >= s->cfg.max_iter) { ls.done = 1; ls.status = 1; }
+            else { rmax = std::max(rmax, lr.resid); any = true; }
+            hrec[l] = lr.resid;
+            if (ls.done && ls.iter < s->hist_cap)
+                HIPCHK(hipMemcpyAsync(s->d_hist + (size_t)l * s->hist_cap + ls.iter, &hrec[l], sizeof(double), hipMemcpyHostToDevice, st));
+            s->h_st[l] = ls;
+        }
+        HIPCHK(hipMemcpyAsync(s->d_st, s->h_st, n_load * sizeof(LoadState), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->d_sigbase, hsig.data(), hsig.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->d_epsbar, zeros.data(), zeros.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        if (fill(s->d_buf0) || fill(s->d_buf1)) return fail(AHOM_E_DEVICE, "fill");
+        HIPCHK(hipStreamSynchronize(st));
+        ++nrestart;
+        if (!any) break;
+        s->spec_toff = s->d_toff;
+        s->red_sig_base = s->d_sigbase;
+        s->cur_tol = std::max(s->cfg.tol, s->cfg.refine * rmax);
+        rc = run_stage();
+        s->spec_toff = nullptr;
+        s->red_sig_base = nullptr;
+        if (rc) return rc;
     }
+    s->cur_tol = s->cfg.tol;
+
     float ms = 0.f;
+    HIPCHK(hipEventRecord(s->ev1, st));
+    HIPCHK(hipEventSynchronize(s->ev1));
     HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
     s->last_ms = ms;
     s->last_enqueued = enq;
     s->last_nload = n_load;
     if (strain_out) {
         if (mem_flags != AHOM_MEM_DEVICE && (rc = s->ensure_real_staging())) return rc;
+        double* dst = mem_flags == AHOM_MEM_DEVICE ? static_cast<double*>(strain_out) : s->d_real;
         RealArgs ra = s->real_args(REAL_TO_REAL);
-        if (mem_flags == AHOM_MEM_DEVICE) ra.real_io = (double*)strain_out;
+        ra.real_io = dst;
+        if (nrestart) {
+            // strain = FP64 iterate + FP32 correction
+            ahom_solver* r = s->ref64;
+            RealArgs rb = r->real_args(REAL_TO_REAL);
+            rb.real_io = dst;
+            if (ahom_launch_real(AHOM_FP64, r->dim, REAL_TO_REAL, rb, r->g_real.nwg, n_load, r->g_real.lds, st))
+                return fail(AHOM_E_DEVICE, "launch to_real (FP64 iterate)");
+            ra.accumulate = 1;
+        }
         if (ahom_launch_real(s->prec, s->dim, REAL_TO_REAL, ra, s->g_real.nwg, n_load, s->g_real.lds, st))
             return fail(AHOM_E_DEVICE, "launch to_real");
         if (mem_flags != AHOM_MEM_DEVICE)
             HIPCHK(hipMemcpyAsync(strain_out, s->d_real, (size_t)n_load * nc * P.m * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
     }
+    s->last_restarts = nrestart;
     int ret = AHOM_OK;
     for (int l = 0; l < n_load; ++l) {
         const LoadState& ls = s->h_st[l];
@@ -805,7 +981,7 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
             }
         }
         if (ls.status == 2) ret = AHOM_E_DIVERGED;
-        else if (ls.status == 1 && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
+        else if ((ls.status == 1 || ls.resid > s->cfg.tol) && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
     }
     if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
     return ret;
@@ -899,6 +1075,12 @@ int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* enq) {
     if (!s) return fail(AHOM_E_ARG, "null solver");
     if (ms) *ms = s->last_ms;
     if (enq) *enq = s->last_enqueued;
+    return AHOM_OK;
+}
+
+int ahom_solver_last_restarts(const ahom_solver* s, int* n) {
+    if (!s || !n) return fail(AHOM_E_ARG, "null argument");
+    *n = s->last_restarts;
     return AHOM_OK;
 }
 

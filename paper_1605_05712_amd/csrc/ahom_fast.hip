@@ -750,12 +750,25 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 for (int c = 0; c < NT; ++c) {
                     const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
                     r2 += dx * dx + dy * dy;
+                    if (a.dout) {
+                        const int64_t o = ((int64_t)load * NT + c) * P.S + spos;
+                        reinterpret_cast<float2*>(a.dout)[o] = float2{(float)dx, (float)dy};
+                        reinterpret_cast<float2*>(a.dneg)[o] = float2{(float)-dx, (float)-dy};
+                    }
                 }
                 res += (double)kb[j * 4 + 3] * r2;
             }
             if (wrt) {
 #pragma unroll
                 for (int c = 0; c < NT; ++c) stg(tb + (int64_t)c * P.S + spos, tt[c]);
+            }
+            if (a.toff) {
+                const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const C o = ldg(to + (int64_t)c * P.S + spos);
+                    tt[c] = C{tt[c].x + o.x, tt[c].y + o.y};
+                }
             }
             C xt = C{(T)0, (T)0};
 #pragma unroll

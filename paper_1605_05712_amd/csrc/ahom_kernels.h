@@ -39,6 +39,7 @@ struct RealArgs {
     const double* eps_bar;    // [load][ncomp]
     int NC, CS;
     int nload;                // fast path: load cases covered by the persistent grid
+    int accumulate;           // TO_REAL: add to real_io instead of overwriting it
 };
 
 struct AxisArgs {
@@ -70,6 +71,13 @@ struct SpecArgs {
     int nload;                // fast path: load cases covered by the persistent grid
     int resid_period;         // evaluate the residual for iter = 0 (mod resid_period) and at max_iter
     int max_iter;
+    // defect correction (FP32 refinement): the traction that enters Gamma0 is
+    // t + toff (toff in the working precision, [load][NT][S]); when dout is
+    // set, the traction step d = t(n) - t(n-1) is also stored as FP32 complex
+    // in dout and its negative in dneg (same layout).
+    const void* toff;
+    void* dout;
+    void* dneg;
 };
 
 // traction traffic of iteration n: read (and evaluate r(n)) / write t(n + 1)
@@ -90,6 +98,7 @@ struct ReduceArgs {
     double tol;
     int max_iter;
     int resid_period;
+    const double* sig_base;   // [load][ncomp] added to the mean stress (nullptr: none)
 };
 
 struct FillArgs {
@@ -116,6 +125,17 @@ int ahom_launch_fill(int prec, const FillArgs& a, int nload, hipStream_t s);
 int ahom_launch_reset(LoadState* st, int n, hipStream_t s);
 int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s);
 int ahom_launch_reorder(int prec, const ReorderArgs& a, int64_t m, hipStream_t s);
+// out64[l] = (base64 ? base64[l] : 0) + (double) in32[l], per load l, where in32
+// is the state buffer st32[l].final_buf of a working-precision-FP32 solver
+struct GatherArgs {
+    double2* out;
+    const double2* base;
+    const float2* in0;
+    const float2* in1;
+    const LoadState* st;
+    int64_t per_load;         // complex elements per load
+};
+int ahom_launch_refine_gather(const GatherArgs& a, int nload, hipStream_t s);
 // dst[c * L0 + n] = src[n * I + c] for elements of `bytes` bytes (1 or 16)
 int ahom_launch_transpose(const void* src, void* dst, int64_t L0, int64_t I, int bytes, hipStream_t s);
 

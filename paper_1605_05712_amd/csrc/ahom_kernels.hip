@@ -257,8 +257,10 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const C z = Z[p * a.NC * CS + j * CS + n];
-                out[(int64_t)(2 * p) * P.m + pt] = (double)z.x;
-                if (2 * p + 1 < NC_) out[(int64_t)(2 * p + 1) * P.m + pt] = (double)z.y;
+                double* oa = out + (int64_t)(2 * p) * P.m + pt;
+                double* ob = out + (int64_t)(2 * p + 1) * P.m + pt;
+                *oa = (double)z.x + (a.accumulate ? *oa : 0.0);
+                if (2 * p + 1 < NC_) *ob = (double)z.y + (a.accumulate ? *ob : 0.0);
             }
         }
         return;
@@ -541,10 +543,20 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
                 const C old = tb[(int64_t)c * P.S + spos];
                 const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
                 r2 += dx * dx + dy * dy;
+                if (a.dout) {
+                    const int64_t o = ((int64_t)load * NT + c) * P.S + spos;
+                    reinterpret_cast<float2*>(a.dout)[o] = float2{(float)dx, (float)dy};
+                    reinterpret_cast<float2*>(a.dneg)[o] = float2{(float)-dx, (float)-dy};
+                }
             }
             if (wrt) tb[(int64_t)c * P.S + spos] = t[c];
         }
         res += wgt * r2;
+        if (a.toff) {
+            const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) t[c] = cadd(t[c], to[(int64_t)c * P.S + spos]);
+        }
         // v = (t - beta (xi . t) xi) / mu0 ; eps_hat = -sym(xi (x) v)
         C xt = C{(T)0, (T)0};
 #pragma unroll
@@ -603,7 +615,7 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
     double mean[NC_];
     double fro = 0.0;
     for (int c = 0; c < NC_; ++c) {
-        mean[c] = v[c] * inv_m;
+        mean[c] = v[c] * inv_m + (a.sig_base ? a.sig_base[(int64_t)load * NC_ + c] : 0.0);
         const bool diag = DIM == 3 ? c < 3 : c < 2;
         fro += (diag ? 1.0 : 2.0) * mean[c] * mean[c];
     }
@@ -651,6 +663,20 @@ __global__ void k_reset_states(LoadState* st, int n) {
 template <typename T>
 __global__ void k_zero(T* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = (T)0;
+}
+
+// defect-correction restart: FP64 state = FP64 base + FP32 correction
+__global__ void k_refine_gather(GatherArgs a) {
+    const int load = blockIdx.y;
+    const float2* in = (a.st[load].final_buf ? a.in1 : a.in0) + (int64_t)load * a.per_load;
+    double2* out = a.out + (int64_t)load * a.per_load;
+    const double2* base = a.base ? a.base + (int64_t)load * a.per_load : nullptr;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.per_load; i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 v = in[i];
+        double2 r = double2{(double)v.x, (double)v.y};
+        if (base) { const double2 b = base[i]; r.x += b.x; r.y += b.y; }
+        out[i] = r;
+    }
 }
 
 // kernel order position <-> canonical kappa order; dir = 0 gather to canonical
@@ -768,6 +794,14 @@ int ahom_launch_zero(int prec, void* p, int64_t n_complex, hipStream_t s) {
     if (blocks < 1) blocks = 1;
     if (prec == 0) hipLaunchKernelGGL(k_zero<double>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (double*)p, n);
     else hipLaunchKernelGGL(k_zero<float>, dim3((unsigned)blocks), dim3(AHOM_WG), 0, s, (float*)p, n);
+    return AHOM_CHECK_LAUNCH();
+}
+
+int ahom_launch_refine_gather(const GatherArgs& a, int nload, hipStream_t s) {
+    int64_t blocks = (a.per_load + AHOM_WG - 1) / AHOM_WG;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_refine_gather, dim3((unsigned)blocks, nload), dim3(AHOM_WG), 0, s, a);
     return AHOM_CHECK_LAUNCH();
 }
 

@@ -161,7 +161,12 @@ def test_spheres_32_fp32_vs_fp64_oracle():
 
 
 def test_spheres_256_fp32_properties():
-    """Full size 256^3 (16.7M points), FP32, contrast 100, 6 loads at tol 1e-6."""
+    """Full size 256^3 (16.7M points), FP32, contrast 100, 6 loads at tol 1e-6.
+
+    Per-entry C_eff error against the FP64 GPU solve at the same size (that
+    path is checked against the oracle element by element on smaller sizes):
+    |C32_ij - C64_ij| <= 1e-5 max|C|.
+    """
     M = [[256, 0, 0], [0, 256, 0], [0, 0, 256]]
     say("spheres 256^3 fp32", M)
     c, r = synth.spheres_rsa(seed=3)
@@ -170,8 +175,16 @@ def test_spheres_256_fp32_properties():
     lame = sphere_lame()
     S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000, resid_period=4)
     S.set_material(lame, ph)
-    C, it = S.effective_stiffness()
+    C, it = S.effective_stiffness(allow=(ahom.AHOM_OK,))
+    print("fp32 iters", it, "restarts", S.last_restarts(), flush=True)
     assert np.all(np.asarray(it) < 5000)
+    S64 = ahom.Solver(P, precision=ahom.FP64, tol=1e-6, max_iter=5000, resid_period=4)
+    S64.set_material(lame, ph)
+    C64, it64 = S64.effective_stiffness(allow=(ahom.AHOM_OK,))
+    del S64
+    err = np.abs(C - C64) / np.abs(C64).max()
+    print("fp64 iters", it64, "\nper-entry error / max|C|:\n", np.array2string(err, precision=2), flush=True)
+    assert err.max() < 1e-5
     assert np.max(np.abs(C - C.T)) < 1e-5 * np.abs(C).max()
     f = ph.mean()
     Cm = [E.tensor4_to_mandel(E.iso_tensor(*l, 3)) for l in lame]
@@ -180,6 +193,16 @@ def test_spheres_256_fp32_properties():
     Cs = 0.5 * (C + C.T)
     assert np.linalg.eigvalsh(voigt - Cs).min() > -1e-6 * np.abs(C).max()
     assert np.linalg.eigvalsh(Cs - reuss).min() > -1e-6 * np.abs(C).max()
-    # close to the 32^3 oracle value (same microstructure, coarser pattern)
-    gold = np.array(json.load(open(os.path.join(GOLD, "spheres_c3_32.json")))["ceff"])
-    assert np.abs(Cs - gold).max() / np.abs(gold).max() < 0.1
+    # isotropic projection within the Hashin-Shtrikman bounds of the two phases
+    a = np.mean(np.diag(Cs)[:3])
+    b = np.mean([Cs[0, 1], Cs[0, 2], Cs[1, 2]])
+    K = (a + 2 * b) / 3
+    G = ((a - b) + 1.5 * np.mean(np.diag(Cs)[3:])) / 5
+    (K1, G1), (K2, G2) = [(l + 2 * mu / 3, mu) for l, mu in lame]
+    f1, f2 = 1 - f, f
+    K_lo = K1 + f2 / (1 / (K2 - K1) + 3 * f1 / (3 * K1 + 4 * G1))
+    K_hi = K2 + f1 / (1 / (K1 - K2) + 3 * f2 / (3 * K2 + 4 * G2))
+    G_lo = G1 + f2 / (1 / (G2 - G1) + 6 * f1 * (K1 + 2 * G1) / (5 * G1 * (3 * K1 + 4 * G1)))
+    G_hi = G2 + f1 / (1 / (G1 - G2) + 6 * f2 * (K2 + 2 * G2) / (5 * G2 * (3 * K2 + 4 * G2)))
+    print(f"f {f:.5f} K {K:.4f} in [{K_lo:.4f}, {K_hi:.4f}], G {G:.4f} in [{G_lo:.4f}, {G_hi:.4f}]", flush=True)
+    assert K_lo < K < K_hi and G_lo < G < G_hi
