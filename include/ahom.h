@@ -220,6 +220,62 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
  */
 int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: Algorithm 1 on many patterns P(M_i) of uneven size (same
+ * dimension) in one persistent device launch.  A workgroup takes one
+ * (member, load) item from a device queue and iterates it to its own stop,
+ * so members of different sizes and iteration counts share the launch.  The
+ * plan (largest radix) and tile widths of each distinct Smith shape are
+ * chosen by timing the candidates on the device the first time the shape is
+ * seen in the process.  AHOM_FP32_MIXED items use the defect-correction
+ * restarts of ahom_config.refine inside the same launch.
+ * ------------------------------------------------------------------------ */
+typedef struct ahom_batch ahom_batch;
+
+/*
+ * n_members matrices M (n_members*d*d int64, row-major each), d in {2, 3}.
+ * cfg as for ahom_solver_create (stream: NULL or a hipStream_t of the
+ * library's HIP runtime).  Errors as ahom_pattern_create, per member.
+ */
+int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config* cfg, ahom_batch** out);
+void ahom_batch_destroy(ahom_batch* b);
+
+/* m = |det M_i| and the elementary divisors e[0..d-1] of member i. */
+int ahom_batch_member_info(const ahom_batch* b, int member, int64_t* m, int64_t* e);
+
+/* Canonical point order of member i (as ahom_pattern_points). */
+int ahom_batch_member_points(const ahom_batch* b, int member, int64_t* num);
+
+/*
+ * Phase table and phase ids of member i (host memory, canonical order), as
+ * ahom_solver_set_material; the reference defaults to the mean of the
+ * extreme phases of that member.
+ */
+int ahom_batch_set_material(ahom_batch* b, int member, int n_phase, const double* lame, const uint8_t* phase);
+int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double mu0);
+
+/*
+ * The same n_load macroscopic strains (n_load*9) for every member.  Outputs
+ * are indexed [member * n_load + load]: iters, resid, status (0 converged,
+ * 1 not converged, 2 diverged), mean_stress (9 doubles each); any may be NULL.
+ * use_graph != 0 replays the launch from a HIP graph captured on the first
+ * call (on a stream of the batch's own).  Returns as ahom_solve.
+ */
+int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iters, double* resid, double* mean_stress,
+                     int* status, int use_graph);
+
+/* Strain field of (member, load) after a solve: c*m doubles (host), component-major. */
+int ahom_batch_strain(ahom_batch* b, int member, int load, double* out);
+
+/* Residual history of (member, load), as ahom_solver_history. */
+int ahom_batch_history(const ahom_batch* b, int member, int load, double* hist, int cap, int* count);
+
+/* Device time of the last batch launch (HIP events) and total restarts. */
+int ahom_batch_last_timing(const ahom_batch* b, double* ms, int* restarts);
+
+/* Plan variant the autotuner chose for member i (index into the candidate list). */
+int ahom_batch_member_variant(const ahom_batch* b, int member, int* variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -43,7 +43,9 @@ EXPORTS = [
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
-    "ahom_solver_pass_times",
+    "ahom_solver_pass_times", "ahom_batch_create", "ahom_batch_destroy", "ahom_batch_member_info",
+    "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
+    "ahom_batch_strain", "ahom_batch_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
 ]
 
 
@@ -79,6 +81,18 @@ _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_restarts.argtypes = [_P, _ip]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
+_lib.ahom_batch_create.argtypes = [ct.c_int, ct.c_int, _i64p, _P, ct.POINTER(_P)]
+_lib.ahom_batch_destroy.argtypes = [_P]
+_lib.ahom_batch_destroy.restype = None
+_lib.ahom_batch_member_info.argtypes = [_P, ct.c_int, _i64p, _i64p]
+_lib.ahom_batch_member_points.argtypes = [_P, ct.c_int, _i64p]
+_lib.ahom_batch_set_material.argtypes = [_P, ct.c_int, ct.c_int, _dp, _P]
+_lib.ahom_batch_set_reference.argtypes = [_P, ct.c_int, ct.c_double, ct.c_double]
+_lib.ahom_batch_solve.argtypes = [_P, ct.c_int, _dp, _ip, _dp, _dp, _ip, ct.c_int]
+_lib.ahom_batch_strain.argtypes = [_P, ct.c_int, ct.c_int, _dp]
+_lib.ahom_batch_history.argtypes = [_P, ct.c_int, ct.c_int, _dp, ct.c_int, _ip]
+_lib.ahom_batch_last_timing.argtypes = [_P, _dp, _ip]
+_lib.ahom_batch_member_variant.argtypes = [_P, ct.c_int, _ip]
 
 
 class AhomError(RuntimeError):
@@ -311,4 +325,85 @@ class Solver:
     def __del__(self):
         if getattr(self, "_h", None):
             _lib.ahom_solver_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """Many patterns (same dimension) solved in one persistent device launch."""
+
+    def __init__(self, Ms, precision=FP64, tol=1e-8, max_iter=1000, resid_period=1, refine=0.0, stream=None):
+        Ms = [np.asarray(M, dtype=np.int64) for M in Ms]
+        self.d = Ms[0].shape[0]
+        if any(M.shape != (self.d, self.d) for M in Ms):
+            raise ValueError("all members need d x d matrices of one d")
+        self.n = len(Ms)
+        self.ncomp = 6 if self.d == 3 else 3
+        flat = np.ascontiguousarray(np.stack(Ms).reshape(-1))
+        self.cfg = Config(precision, tol, max_iter, 1, NYQUIST_HERMITIAN, stream, resid_period, refine)
+        h = _P()
+        _check(_lib.ahom_batch_create(self.d, self.n, _ptr(flat, ct.c_int64), ct.byref(self.cfg), ct.byref(h)))
+        self._h = h
+        self.nload = 0
+
+    def info(self, i):
+        m = ct.c_int64()
+        e = np.zeros(self.d, np.int64)
+        _check(_lib.ahom_batch_member_info(self._h, i, ct.byref(m), _ptr(e, ct.c_int64)))
+        return int(m.value), e
+
+    def points(self, i):
+        m, _ = self.info(i)
+        out = np.zeros((m, self.d), np.int64)
+        _check(_lib.ahom_batch_member_points(self._h, i, _ptr(out, ct.c_int64)))
+        return out
+
+    def set_material(self, i, lame, phase):
+        lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
+        _check(_lib.ahom_batch_set_material(self._h, i, lame.shape[0], _ptr(lame, ct.c_double), ph.ctypes.data))
+
+    def set_reference(self, i, lam0, mu0):
+        _check(_lib.ahom_batch_set_reference(self._h, i, float(lam0), float(mu0)))
+
+    def solve(self, eps_bar, use_graph=False, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        """eps_bar: (n_load, 3, 3).  Arrays indexed [member, load]."""
+        eb = np.ascontiguousarray(np.asarray(eps_bar, dtype=np.float64).reshape(-1, 9))
+        nl = eb.shape[0]
+        iters = np.zeros(self.n * nl, np.int32)
+        resid = np.zeros(self.n * nl, np.float64)
+        mean = np.zeros((self.n * nl, 9), np.float64)
+        status = np.zeros(self.n * nl, np.int32)
+        rc = _lib.ahom_batch_solve(self._h, nl, _ptr(eb, ct.c_double), _ptr(iters, ct.c_int), _ptr(resid, ct.c_double),
+                                   _ptr(mean, ct.c_double), _ptr(status, ct.c_int), 1 if use_graph else 0)
+        _check(rc, allow)
+        self.nload = nl
+        return dict(status=rc, iters=iters.reshape(self.n, nl), resid=resid.reshape(self.n, nl),
+                    mean_stress=mean.reshape(self.n, nl, 3, 3), item_status=status.reshape(self.n, nl))
+
+    def strain(self, i, load):
+        m, _ = self.info(i)
+        out = np.zeros((self.ncomp, m), np.float64)
+        _check(_lib.ahom_batch_strain(self._h, i, load, _ptr(out, ct.c_double)))
+        return out
+
+    def history(self, i, load, cap=100000):
+        h = np.zeros(cap, np.float64)
+        n = ct.c_int()
+        _check(_lib.ahom_batch_history(self._h, i, load, _ptr(h, ct.c_double), cap, ct.byref(n)))
+        return h[: n.value]
+
+    def last_timing(self):
+        ms = ct.c_double()
+        r = ct.c_int()
+        _check(_lib.ahom_batch_last_timing(self._h, ct.byref(ms), ct.byref(r)))
+        return ms.value, r.value
+
+    def variant(self, i):
+        v = ct.c_int()
+        _check(_lib.ahom_batch_member_variant(self._h, i, ct.byref(v)))
+        return v.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.ahom_batch_destroy(self._h)
             self._h = None

@@ -94,6 +94,8 @@ struct SmithForm {
 
 int ahom_smith_form(int d, const int64_t* M, SmithForm* out, std::string* err);
 int ahom_build_plan(const SmithForm& sf, int lmax, Plan* plan, std::string* err);
+// max_radix 8: radix-8 stages first; 4: radix 4 and 2 only for the powers of two
+int ahom_build_plan_ex(const SmithForm& sf, int lmax, int max_radix, Plan* plan, std::string* err);
 // Twiddle tables for a plan: FP64 values (and their FP32 rounding).
 void ahom_build_twiddles(Plan* plan, std::vector<double>* tw64);
 void ahom_canonical_points(const SmithForm& sf, int64_t* num);

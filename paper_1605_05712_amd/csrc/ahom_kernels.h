@@ -139,6 +139,47 @@ int ahom_launch_refine_gather(const GatherArgs& a, int nload, hipStream_t s);
 // dst[c * L0 + n] = src[n * I + c] for elements of `bytes` bytes (1 or 16)
 int ahom_launch_transpose(const void* src, void* dst, int64_t L0, int64_t I, int bytes, hipStream_t s);
 
+// ---- batched solves: one persistent launch over many (pattern, load) items.
+// A workgroup takes an item from the queue and runs Algorithm 1 for it to the
+// end (all passes, its own loop control), so no grid-wide synchronisation is
+// needed.  FP32 items with refine > 0 run the defect-correction restarts
+// in place (FP64 companion buffers per item).
+struct BatchItem {
+    RealArgs ra;                       // working-precision passes; load index 0
+    AxisArgs ax[AHOM_MAX_AXES];        // middle axes 1..D-2
+    SpecArgs sa;                       // plain stage (eps_bar = the load)
+    SpecArgs sa_corr;                  // correction stage (eps_bar = 0, toff set)
+    RealArgs ra64;                     // FP64 companion (defect evaluation)
+    AxisArgs ax64[AHOM_MAX_AXES];
+    SpecArgs sa64;                     // dout / dneg -> toff / tbuf of the item
+    int D;
+    int64_t S, row, m;                 // stored complex per field, fill row, points
+    int64_t t_real, t_spec, t_axis[AHOM_MAX_AXES];          // tiles per pass
+    int64_t t_real64, t_spec64, t_axis64[AHOM_MAX_AXES];
+    double* hist;                      // [hist_cap] residual history
+    int hist_cap;
+    LoadState* st;                     // result state of the item
+    int* restarts;
+};
+
+struct BatchArgs {
+    const BatchItem* items;
+    const int* order;                  // queue position -> item
+    int n_items;
+    int* counter;                      // queue head (zeroed before each launch)
+    double tol, refine;
+    int max_iter, resid_period;
+    int refine_on;                     // FP32 items: defect-correction restarts
+};
+
+// queue head and item states to zero (plain kernels: safe inside a captured graph)
+int ahom_launch_batch_reset(int* counter, int n_items, hipStream_t s);
+int ahom_launch_batch(int prec, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s);
+// static LDS bytes of the batch kernel (reduction scratch and item state)
+size_t ahom_batch_static_lds(int dim);
+// resident workgroups per CU of the batch kernel with `lds` dynamic LDS bytes
+int ahom_batch_occupancy(int prec, int dim, size_t lds);
+
 // ---- power-of-two fast path (ahom_fast.hip)
 enum { FAST_REAL = 0, FAST_AXIS = 1, FAST_SPEC = 2 };
 struct FastGeom {

@@ -17,6 +17,8 @@
 #include "ahom_internal.h"
 #include "ahom_kernels.h"
 
+#define AHOM_CHECK_LAUNCH() (hipGetLastError() == hipSuccess ? 0 : -1)
+
 namespace {
 
 template <typename T> struct CT;
@@ -197,25 +199,24 @@ template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
 // =============================================================================
 // axis 0: real-space turnaround
 // =============================================================================
+// One tile (a.NC columns) of the axis-0 pass for load case `load`; the
+// stress sums of REAL_TURN are added to sig (per thread).  All threads of
+// the workgroup take part (LDS barriers inside).
 template <typename T, int DIM, int MODE>
-__global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
+__device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int64_t tile, double* sig) {
     using C = typename CT<T>::t;
     constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
     const Plan& P = *a.plan;
-    const int load = blockIdx.y;
-    const LoadState& st = a.st[load];
-    if (MODE == REAL_TURN && st.done) return;
     const AxisDesc& ax = P.ax[0];
     const int L = ax.len, H = ax.slen;
     const int64_t I = P.S / H;
-    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int64_t c0 = tile * a.NC;
     const int ncol = (int)((I - c0) < a.NC ? (I - c0) : a.NC);
     const int CS = a.CS;
     const int tid = threadIdx.x;
 
     C* Z = lds_base<C>();
     C* tmp = Z + NP * a.NC * CS;
-    double* red = reinterpret_cast<double*>(tmp + a.NC * CS);
 
     int src_buf = 0;
     if (MODE == REAL_TURN) src_buf = st.iter & 1;
@@ -265,10 +266,6 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
         }
         return;
     }
-
-    double sig[NC_];
-#pragma unroll
-    for (int c = 0; c < NC_; ++c) sig[c] = 0.0;
 
     if (MODE == REAL_TURN) {
         const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
@@ -346,11 +343,23 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
             if (2 * p + 1 < NC_) dst[(int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col] = B;
         }
     }
+}
 
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    const int load = blockIdx.y;
+    if (MODE == REAL_TURN && a.st[load].done) return;
+    double sig[NC_];
+#pragma unroll
+    for (int c = 0; c < NC_; ++c) sig[c] = 0.0;
+    real_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, sig);
     if (MODE == REAL_TURN) {
         __syncthreads();
+        double* red = reinterpret_cast<double*>(lds_base<C>() + (NP + 1) * a.NC * a.CS);
         block_sum<NC_>(sig, red);
-        if (tid == 0)
+        if (threadIdx.x == 0)
             for (int c = 0; c < NC_; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NC_ + c] = sig[c];
     }
 }
@@ -358,27 +367,21 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
 // =============================================================================
 // middle axes: plain complex FFT passes (also the bare pattern DFT)
 // =============================================================================
+// One tile of a middle-axis pass (field `field` of load case `load`).
 template <typename T, int DIR>
-__global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
+__device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64_t tile) {
     using C = typename CT<T>::t;
     const Plan& P = *a.plan;
-    const int load = blockIdx.z;
-    int par = 0;
-    if (a.st) {
-        const LoadState& st = a.st[load];
-        if (st.done) return;
-        par = (st.iter + 1) & 1;
-    }
     const AxisDesc& ax = P.ax[a.axis];
     const int L = ax.len;
     int64_t O = 1, I = 1;
     for (int b = 0; b < a.axis; ++b) O *= a.slen0_full && b == 0 ? P.ax[0].len : P.ax[b].slen;
     for (int b = a.axis + 1; b < P.D; ++b) I *= P.ax[b].slen;
     const int64_t ncols = O * I;
-    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int64_t c0 = tile * a.NC;
     const int ncol = (int)((ncols - c0) < a.NC ? (ncols - c0) : a.NC);
     const int CS = a.CS;
-    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)blockIdx.y * a.field_stride;
+    C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * a.load_stride + (int64_t)field * a.field_stride;
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
     C* X = lds_base<C>();
     C* tmp = X + a.NC * CS;
@@ -409,23 +412,28 @@ __global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
     }
 }
 
+template <typename T, int DIR>
+__global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
+    const int load = blockIdx.z;
+    if (a.st && a.st[load].done) return;
+    axis_tile<T, DIR>(a, a.st ? (a.st[load].iter + 1) & 1 : 0, load, blockIdx.y, blockIdx.x);
+}
+
 // =============================================================================
 // last axis: spectral turnaround with Gamma0 and the residual terms
 // =============================================================================
+// One tile of the last-axis pass; the residual terms are added to res.
 template <typename T, int DIM, int MODE>
-__global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
+__device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int64_t tile, double& res) {
     using C = typename CT<T>::t;
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
     const Plan& P = *a.plan;
-    const int load = blockIdx.y;
-    const LoadState& st = a.st[load];
-    if (st.done) return;
     const int par = MODE == SPEC_INIT ? 0 : (st.iter + 1) & 1;
     const int D = P.D;
     const AxisDesc& ax = P.ax[D - 1];
     const int L = ax.len;
     const int64_t ncols = P.S / L;
-    const int64_t c0 = (int64_t)blockIdx.x * a.NC;
+    const int64_t c0 = tile * a.NC;
     const int ncol = (int)((ncols - c0) < a.NC ? (ncols - c0) : a.NC);
     const int CS = a.CS;
     const int tid = threadIdx.x;
@@ -434,7 +442,6 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
     C* F = lds_base<C>();
     C* tmp = F + NC_ * a.NC * CS;
-    double* red = reinterpret_cast<double*>(tmp + a.NC * CS);
 
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         const int j = e / L, l = e - j * L;
@@ -450,7 +457,6 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
     const int L0 = P.ax[0].len;
-    double res = 0.0;
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         const int j = e / L, l = e - j * L;
         if (j >= ncol) continue;
@@ -588,9 +594,20 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
 #pragma unroll
         for (int f = 0; f < NC_; ++f) base[(int64_t)f * P.S + addr] = F[f * a.NC * CS + j * CS + l];
     }
+}
+
+template <typename T, int DIM, int MODE>
+__global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
+    using C = typename CT<T>::t;
+    constexpr int NC_ = Comp<DIM>::N;
+    const int load = blockIdx.y;
+    if (a.st[load].done) return;
+    double res = 0.0;
+    spec_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, res);
+    if (MODE == SPEC_INIT) return;
     double rv[1] = {res};
-    block_sum<1>(rv, red);
-    if (tid == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
+    block_sum<1>(rv, reinterpret_cast<double*>(lds_base<C>() + (NC_ + 1) * a.NC * a.CS));
+    if (threadIdx.x == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
 }
 
 // =============================================================================
@@ -636,6 +653,232 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
     if (r <= a.tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; return; }
     if (n >= a.max_iter) { st.done = 1; st.status = 1; st.final_buf = n & 1; return; }
     st.iter = n + 1;
+}
+
+// =============================================================================
+// batched solves: persistent workgroups, one (pattern, load) item at a time
+// =============================================================================
+namespace {
+
+// global-memory writes of this workgroup made visible to its later reads
+__device__ __forceinline__ void wg_mem_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T>
+__device__ void wg_fill_state(void* buf, const double* eps_bar, int64_t S, int64_t row, int nfield) {
+    using C = typename CT<T>::t;
+    C* b = reinterpret_cast<C*>(buf);
+    const int64_t n = (int64_t)nfield * S;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int f = (int)(i / S);
+        const int64_t k = i - (int64_t)f * S;
+        b[i] = k < row ? C{(T)eps_bar[f], (T)0} : C{(T)0, (T)0};
+    }
+}
+
+template <typename T>
+__device__ void wg_zero(void* p, int64_t n_complex) {
+    using C = typename CT<T>::t;
+    C* q = reinterpret_cast<C*>(p);
+    for (int64_t i = threadIdx.x; i < n_complex; i += blockDim.x) q[i] = C{(T)0, (T)0};
+}
+
+// Iterate one item (all passes, then the FP64 reduction and loop control of
+// k_reduce) until it stops at tol, max_iter or divergence.  st is the item's
+// state in LDS; sig_base (nullable) is added to the mean stress.
+template <typename T, int DIM>
+__device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisArgs* ax, const SpecArgs& sa,
+                            int64_t t_real, int64_t t_spec, const int64_t* t_axis, LoadState& st,
+                            const double* sig_base, double tol, int max_iter, int resid_period, bool record,
+                            double* red) {
+    constexpr int NC_ = Comp<DIM>::N;
+    const int tid = threadIdx.x;
+    for (;;) {
+        double v[NC_ + 1];
+#pragma unroll
+        for (int c = 0; c <= NC_; ++c) v[c] = 0.0;
+        for (int64_t t = 0; t < t_real; ++t) {
+            real_tile<T, DIM, REAL_TURN>(ra, st, 0, t, v);
+            __syncthreads();
+        }
+        wg_mem_sync();
+        const int par = (st.iter + 1) & 1;
+        for (int a = 1; a <= it.D - 2; ++a) {
+            for (int f = 0; f < NC_; ++f)
+                for (int64_t t = 0; t < t_axis[a]; ++t) {
+                    axis_tile<T, -1>(ax[a], par, 0, f, t);
+                    __syncthreads();
+                }
+            wg_mem_sync();
+        }
+        for (int64_t t = 0; t < t_spec; ++t) {
+            spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_]);
+            __syncthreads();
+        }
+        wg_mem_sync();
+        for (int a = it.D - 2; a >= 1; --a) {
+            for (int f = 0; f < NC_; ++f)
+                for (int64_t t = 0; t < t_axis[a]; ++t) {
+                    axis_tile<T, +1>(ax[a], par, 0, f, t);
+                    __syncthreads();
+                }
+            wg_mem_sync();
+        }
+        block_sum<NC_ + 1>(v, red);
+        if (tid == 0) {
+            const double inv_m = 1.0 / (double)it.m;
+            double fro = 0.0;
+            for (int c = 0; c < NC_; ++c) {
+                const double mc = v[c] * inv_m + (sig_base ? sig_base[c] : 0.0);
+                st.mean[c] = mc;
+                const bool diag = DIM == 3 ? c < 3 : c < 2;
+                fro += (diag ? 1.0 : 2.0) * mc * mc;
+            }
+            const int n = st.iter;
+            if (!ahom_check_iter(n, resid_period, max_iter)) {
+                if (record && n < it.hist_cap) it.hist[n] = -1.0;
+                st.iter = n + 1;
+            } else {
+                const double r = sqrt(v[NC_]) / sqrt(fro);
+                if (record && n < it.hist_cap) it.hist[n] = r;
+                if (n == 0) st.r0 = r;
+                st.resid = r;
+                const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
+                if (bad) { st.done = 1; st.status = 2; st.final_buf = n & 1; }
+                else if (r <= tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; }
+                else if (n >= max_iter) { st.done = 1; st.status = 1; st.final_buf = n & 1; }
+                else st.iter = n + 1;
+            }
+        }
+        __syncthreads();
+        if (st.done) return;
+    }
+}
+
+// Algorithm 1 on one item, with the FP32 defect-correction restarts (the
+// same scheme as the single-pattern solver: FP64 iterate eps_b = F(eps_h),
+// traction step d, then FP32 iteration on eps - eps_b with offset d).
+template <typename T, int DIM>
+__device__ void batch_item(const BatchArgs& b, const BatchItem& it, LoadState& st, LoadState& st64, double* sbase,
+                           double* red) {
+    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    const int tid = threadIdx.x;
+    wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_);
+    wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S);
+    if (tid == 0) st = LoadState{};
+    wg_mem_sync();
+    double stage_tol = b.refine_on ? fmax(b.tol, b.refine) : b.tol;
+    batch_stage<T, DIM>(it, it.ra, it.ax, it.sa, it.t_real, it.t_spec, it.t_axis, st, nullptr, stage_tol, b.max_iter,
+                        b.resid_period, true, red);
+    int nres = 0;
+    if constexpr (sizeof(T) == 4) {
+        while (b.refine_on && st.status == 0 && st.resid > b.tol) {
+            // FP64 iterate eps_h = (FP64 base) + FP32 state
+            {
+                const float2* in = reinterpret_cast<const float2*>(st.final_buf ? it.ra.buf1 : it.ra.buf0);
+                double2* out = reinterpret_cast<double2*>(it.ra64.buf0);
+                const double2* base = nres ? reinterpret_cast<const double2*>(it.ra64.buf1) : nullptr;
+                const int64_t n = (int64_t)NC_ * it.S;
+                for (int64_t i = tid; i < n; i += blockDim.x) {
+                    const float2 x = in[i];
+                    double2 r = double2{(double)x.x, (double)x.y};
+                    if (base) { r.x += base[i].x; r.y += base[i].y; }
+                    out[i] = r;
+                }
+            }
+            wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S);
+            if (tid == 0) st64 = LoadState{};
+            wg_mem_sync();
+            batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64,
+                                     nullptr, -1.0, 1, 1, false, red);
+            ++nres;
+            // correction stage: e(0) = 0, t(e(-1)) = -d (written by the FP64 pass)
+            if (tid == 0) {
+                LoadState ns{};
+                ns.iter = st.iter + 1 < b.max_iter ? st.iter + 1 : b.max_iter;
+                ns.r0 = st.r0;
+                ns.resid = st64.resid;
+                for (int c = 0; c < NC_; ++c) ns.mean[c] = sbase[c] = st64.mean[c];
+                ns.final_buf = ns.iter & 1;
+                const double r = st64.resid;
+                if (!(r == r) || isinf(r)) { ns.done = 1; ns.status = 2; }
+                else if (r <= b.tol) { ns.done = 1; ns.status = 0; }
+                else if (ns.iter >= b.max_iter) { ns.done = 1; ns.status = 1; }
+                if (ns.done && ns.iter < it.hist_cap) it.hist[ns.iter] = r;
+                st = ns;
+            }
+            wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S);
+            wg_zero<T>(it.ra.buf1, (int64_t)NC_ * it.S);
+            wg_mem_sync();
+            if (st.done) break;
+            stage_tol = fmax(b.tol, b.refine * st.resid);
+            batch_stage<T, DIM>(it, it.ra, it.ax, it.sa_corr, it.t_real, it.t_spec, it.t_axis, st, sbase, stage_tol,
+                                b.max_iter, b.resid_period, true, red);
+        }
+    }
+    if (tid == 0) {
+        *it.st = st;
+        *it.restarts = nres;
+    }
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
+    constexpr int NC_ = Comp<DIM>::N;
+    __shared__ double red[(NC_ + 1) * AHOM_WG];
+    __shared__ LoadState st, st64;
+    __shared__ double sbase[NC_];
+    __shared__ int qi;
+    for (;;) {
+        if (threadIdx.x == 0) qi = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int q = qi;
+        __syncthreads();
+        if (q >= b.n_items) return;
+        batch_item<T, DIM>(b, b.items[b.order[q]], st, st64, sbase, red);
+        __syncthreads();
+    }
+}
+
+__global__ void k_batch_reset(int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+}  // namespace
+
+int ahom_launch_batch_reset(int* counter, int n_items, hipStream_t s) {
+    (void)n_items;
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
+    return AHOM_CHECK_LAUNCH();
+}
+
+size_t ahom_batch_static_lds(int dim) {
+    const int nc = dim == 3 ? 6 : 3;
+    return (size_t)(nc + 1) * AHOM_WG * 8 + 2 * sizeof(LoadState) + nc * 8 + 16;
+}
+
+int ahom_batch_occupancy(int prec, int dim, size_t lds) {
+    int n = 0;
+    hipError_t e;
+    if (prec == 0) e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 3>, AHOM_WG, lds)
+                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 2>, AHOM_WG, lds);
+    else e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 3>, AHOM_WG, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 2>, AHOM_WG, lds);
+    return e == hipSuccess ? n : 0;
+}
+
+int ahom_launch_batch(int prec, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s) {
+    if (prec == 0) {
+        if (dim == 3) hipLaunchKernelGGL((k_batch<double, 3>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
+        else hipLaunchKernelGGL((k_batch<double, 2>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
+    } else {
+        if (dim == 3) hipLaunchKernelGGL((k_batch<float, 3>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
+        else hipLaunchKernelGGL((k_batch<float, 2>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
+    }
+    return AHOM_CHECK_LAUNCH();
 }
 
 // =============================================================================
@@ -706,7 +949,6 @@ __global__ void k_reorder(ReorderArgs a) {
 }
 
 // ----------------------------------------------------------------- launchers
-#define AHOM_CHECK_LAUNCH() (hipGetLastError() == hipSuccess ? 0 : -1)
 
 template <typename T>
 static int set_lds(const void* fn, size_t bytes) {

@@ -208,11 +208,12 @@ void ahom_canonical_freqs(const SmithForm& sf, const FreqMap& fm, int64_t* h) {
 
 namespace {
 
-std::vector<int> radix_plan(int L) {
+std::vector<int> radix_plan(int L, int max_radix) {
     std::vector<int> r;
     int v = L;
-    while (v % 8 == 0) { r.push_back(8); v /= 8; }
-    if (v % 4 == 0) { r.push_back(4); v /= 4; }
+    if (max_radix >= 8)
+        while (v % 8 == 0) { r.push_back(8); v /= 8; }
+    while (v % 4 == 0) { r.push_back(4); v /= 4; }
     if (v % 2 == 0) { r.push_back(2); v /= 2; }
     for (int p : {3, 5, 7})
         while (v % p == 0) { r.push_back(p); v /= p; }
@@ -249,6 +250,10 @@ bool factorize(int64_t L, int k, int64_t lmax, std::vector<int64_t>* out) {
 }  // namespace
 
 int ahom_build_plan(const SmithForm& sf, int lmax, Plan* plan, std::string* err) {
+    return ahom_build_plan_ex(sf, lmax, 8, plan, err);
+}
+
+int ahom_build_plan_ex(const SmithForm& sf, int lmax, int max_radix, Plan* plan, std::string* err) {
     Plan p{};
     p.d = sf.d;
     p.m = sf.m;
@@ -306,7 +311,7 @@ int ahom_build_plan(const SmithForm& sf, int lmax, Plan* plan, std::string* err)
             for (size_t u = t; u < f.size(); ++u) tail *= f[u];
             a.tailN = tail;
             a.split = (t + 1 < f.size()) ? 1 : 0;
-            std::vector<int> r = radix_plan(a.len);
+            std::vector<int> r = radix_plan(a.len, max_radix);
             a.nstage = (int)r.size();
             for (size_t u = 0; u < r.size(); ++u) a.radix[u] = r[u];
         }

@@ -18,6 +18,7 @@ Workload recipes (shapes of the paper's examples, Sec. 4-5):
 """
 from __future__ import annotations
 
+import functools
 import math
 
 import numpy as np
@@ -249,7 +250,8 @@ def spheres_phase(points_num, m, centres, radii):
 # 2-D batch members: non-diagonal M with 7-smooth elementary divisors
 # --------------------------------------------------------------------------
 
-def seven_smooth(lo, hi):
+@functools.lru_cache(maxsize=None)
+def _seven_smooth(lo, hi):
     out = []
     for a in range(0, 40):
         for b in range(0, 26):
@@ -258,7 +260,12 @@ def seven_smooth(lo, hi):
                     v = 2 ** a * 3 ** b * 5 ** c * 7 ** e
                     if lo <= v <= hi:
                         out.append(v)
-    return sorted(set(out))
+    return tuple(sorted(set(out)))
+
+
+def seven_smooth(lo, hi):
+    """Sorted integers in [lo, hi] with no prime factor above 7."""
+    return list(_seven_smooth(lo, hi))
 
 
 def batch_2d_member(seed, lo=1024, hi=65536):
