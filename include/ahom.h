@@ -276,6 +276,64 @@ int ahom_batch_last_timing(const ahom_batch* b, double* ms, int* restarts);
 /* Plan variant the autotuner chose for member i (index into the candidate list). */
 int ahom_batch_member_variant(const ahom_batch* b, int member, int* variant);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess on tensor grids M = diag(n, n, n), n a multiple of 8.
+ * A 3-D convolutional encoder-decoder (4 levels n^3 .. (n/8)^3 with 32, 64,
+ * 96, 128 channels, two periodic 3x3x3 convolutions per level, 2x2x2
+ * average pooling, nearest upsampling, additive skips, ReLU; 36 outputs =
+ * fluctuation strain (11,22,33,23,13,12) of the six Mandel unit loads) runs
+ * on BF16 matrix cores with FP32 accumulation; FP32 master weights and Adam.
+ * Inputs per point: phase indicator (id != 0), mu/mu0 - 1, lambda/lambda0 - 1.
+ * Training loss: the C0-energy norm of the strain error divided by mu0,
+ * averaged over points and loads.  Points are in canonical order (z slowest).
+ * The guess only sets eps(0): Algorithm 1 still iterates to its tolerance.
+ * ------------------------------------------------------------------------ */
+typedef struct ahom_guess ahom_guess;
+
+/* batch: largest number of samples per training step (<= 64); seed: weights
+ * (He-normal) and sample drawing; stream: NULL or a hipStream_t. */
+int ahom_guess_create(int n, int batch, uint64_t seed, void* stream, ahom_guess** out);
+void ahom_guess_destroy(ahom_guess* g);
+int ahom_guess_num_params(const ahom_guess* g, int64_t* n);
+/* flat FP32 parameters: per convolution W[cout][27][cin] (tap t = 9 (dz+1) +
+ * 3 (dy+1) + (dx+1)) then b[cout], channel counts padded (input 32, output 64) */
+int ahom_guess_get_params(const ahom_guess* g, float* out);
+int ahom_guess_set_params(ahom_guess* g, const float* in);
+
+/* Training sample: phase ids (n^3), its phase table (n_phase <= 8), the
+ * reference (lambda0, mu0) and the solved strain of the six Mandel unit loads
+ * (ahom_solve output for the loads of ahom_effective_stiffness),
+ * [6 loads][6 components][n^3] doubles (host or device); the target is that
+ * strain minus the load. */
+int ahom_guess_add_sample(ahom_guess* g, const uint8_t* phase, int n_phase, const double* lame, double lam0, double mu0,
+                          const double* strain, int mem_flags);
+int ahom_guess_num_samples(const ahom_guess* g, int* n);
+
+/* Loss and its gradient (flat, as the parameters) over the given samples. */
+int ahom_guess_gradients(ahom_guess* g, const int* samples, int count, float* grad, double* loss);
+/* steps of Adam (lr, beta 0.9 / 0.999, eps 1e-8) on random batches; losses[steps] (nullable) */
+int ahom_guess_train(ahom_guess* g, int steps, int batch, double lr, double* losses);
+/* one Adam step with a caller-supplied gradient */
+int ahom_guess_adam_step(ahom_guess* g, const float* grad, double lr);
+
+/* Initial fluctuation for n_load strains eps_bar (n_load*9): the network's
+ * unit-load fields combined with the Mandel coordinates of each eps_bar,
+ * written as [n_load][6][n^3] doubles: the `init` argument of ahom_solve. */
+int ahom_guess_infer(ahom_guess* g, int n_phase, const double* lame, double lam0, double mu0, const uint8_t* phase,
+                     int n_load, const double* eps_bar, double* init_out, int mem_flags);
+/* network output [n^3][36] of dataset sample i */
+int ahom_guess_predict_sample(ahom_guess* g, int sample, float* out);
+int ahom_guess_save(const ahom_guess* g, const char* path);
+int ahom_guess_load(ahom_guess* g, const char* path);
+
+/* One periodic 3x3x3 convolution through the network's kernels (host FP32
+ * arrays, rounded to BF16 on entry; channels-last [batch][n^3][c]).  mode 0:
+ * out = conv(x) + b (ReLU if relu); mode 1: out = adjoint of the convolution
+ * applied to dy (cout multiple of 32); mode 2: out = weight gradient
+ * [cout][27][cin] of sum(dy * conv(x)), db (nullable) = bias gradient. */
+int ahom_conv3d(int n, int batch, int cin, int cout, int mode, int relu, const float* x, const float* w, const float* b,
+                const float* dy, float* out, float* db);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,10 @@ EXPORTS = [
     "ahom_solver_pass_times", "ahom_batch_create", "ahom_batch_destroy", "ahom_batch_member_info",
     "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
     "ahom_batch_strain", "ahom_batch_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
+    "ahom_guess_create", "ahom_guess_destroy", "ahom_guess_num_params", "ahom_guess_get_params", "ahom_guess_set_params",
+    "ahom_guess_add_sample", "ahom_guess_num_samples", "ahom_guess_gradients", "ahom_guess_train",
+    "ahom_guess_adam_step", "ahom_guess_infer", "ahom_guess_predict_sample", "ahom_guess_save", "ahom_guess_load",
+    "ahom_conv3d",
 ]
 
 
@@ -93,6 +97,23 @@ _lib.ahom_batch_strain.argtypes = [_P, ct.c_int, ct.c_int, _dp]
 _lib.ahom_batch_history.argtypes = [_P, ct.c_int, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_batch_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_batch_member_variant.argtypes = [_P, ct.c_int, _ip]
+_fp = ct.POINTER(ct.c_float)
+_lib.ahom_guess_create.argtypes = [ct.c_int, ct.c_int, ct.c_uint64, _P, ct.POINTER(_P)]
+_lib.ahom_guess_destroy.argtypes = [_P]
+_lib.ahom_guess_destroy.restype = None
+_lib.ahom_guess_num_params.argtypes = [_P, _i64p]
+_lib.ahom_guess_get_params.argtypes = [_P, _fp]
+_lib.ahom_guess_set_params.argtypes = [_P, _fp]
+_lib.ahom_guess_add_sample.argtypes = [_P, _P, ct.c_int, _dp, ct.c_double, ct.c_double, _P, ct.c_int]
+_lib.ahom_guess_num_samples.argtypes = [_P, _ip]
+_lib.ahom_guess_gradients.argtypes = [_P, _ip, ct.c_int, _fp, _dp]
+_lib.ahom_guess_train.argtypes = [_P, ct.c_int, ct.c_int, ct.c_double, _dp]
+_lib.ahom_guess_adam_step.argtypes = [_P, _fp, ct.c_double]
+_lib.ahom_guess_infer.argtypes = [_P, ct.c_int, _dp, ct.c_double, ct.c_double, _P, ct.c_int, _dp, _P, ct.c_int]
+_lib.ahom_guess_predict_sample.argtypes = [_P, ct.c_int, _fp]
+_lib.ahom_guess_save.argtypes = [_P, ct.c_char_p]
+_lib.ahom_guess_load.argtypes = [_P, ct.c_char_p]
+_lib.ahom_conv3d.argtypes = [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, _fp, _fp, _fp, _fp, _fp, _fp]
 
 
 class AhomError(RuntimeError):
@@ -406,4 +427,114 @@ class Batch:
     def __del__(self):
         if getattr(self, "_h", None):
             _lib.ahom_batch_destroy(self._h)
+            self._h = None
+
+
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def conv3d(n, cin, cout, mode, x=None, w=None, b=None, dy=None, relu=False, batch=1):
+    """One periodic 3x3x3 convolution through the network kernels (mode 0 fwd, 1 adjoint, 2 weight gradient)."""
+    x, w, b, dy = _f32(x), _f32(w), _f32(b), _f32(dy)
+    P = n ** 3
+    if mode == 0:
+        out = np.zeros((batch, P, cout), np.float32)
+    elif mode == 1:
+        out = np.zeros((batch, P, cin), np.float32)
+    else:
+        out = np.zeros((cout, 27, cin), np.float32)
+    db = np.zeros(cout, np.float32) if mode == 2 else None
+    p = lambda a: None if a is None else a.ctypes.data_as(_fp)  # noqa: E731
+    _check(_lib.ahom_conv3d(n, batch, cin, cout, mode, 1 if relu else 0, p(x), p(w), p(b), p(dy), p(out), p(db)))
+    return (out, db) if mode == 2 else out
+
+
+class Guess:
+    """Learned initial guess (BF16 matrix-core network) on diag(n, n, n) grids."""
+
+    def __init__(self, n, batch=4, seed=0, stream=None):
+        h = _P()
+        _check(_lib.ahom_guess_create(n, batch, seed, stream, ct.byref(h)))
+        self._h = h
+        self.n = n
+        self.P = n ** 3
+        k = ct.c_int64()
+        _check(_lib.ahom_guess_num_params(h, ct.byref(k)))
+        self.nparam = int(k.value)
+
+    def params(self):
+        out = np.zeros(self.nparam, np.float32)
+        _check(_lib.ahom_guess_get_params(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32))
+        assert w.size == self.nparam
+        _check(_lib.ahom_guess_set_params(self._h, w.ctypes.data_as(_fp)))
+
+    def add_sample(self, phase, lame, lam0, mu0, strain):
+        """strain: solved strain of the 6 Mandel unit loads, (6, 6, n^3) host array or DeviceArray."""
+        lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        if _is_device(phase):
+            ph_ptr, flags = phase.data_ptr(), MEM_DEVICE
+            assert _is_device(strain)
+            st_ptr = strain.data_ptr()
+        else:
+            ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
+            st = np.ascontiguousarray(np.asarray(strain, dtype=np.float64))
+            ph_ptr, st_ptr, flags = ph.ctypes.data, st.ctypes.data, MEM_HOST
+        _check(_lib.ahom_guess_add_sample(self._h, ph_ptr, lame.shape[0], _ptr(lame, ct.c_double), float(lam0), float(mu0),
+                                          st_ptr, flags))
+
+    def num_samples(self):
+        n = ct.c_int()
+        _check(_lib.ahom_guess_num_samples(self._h, ct.byref(n)))
+        return n.value
+
+    def gradients(self, samples):
+        idx = np.ascontiguousarray(np.asarray(samples, dtype=np.int32))
+        g = np.zeros(self.nparam, np.float32)
+        loss = ct.c_double()
+        _check(_lib.ahom_guess_gradients(self._h, _ptr(idx, ct.c_int), idx.size, g.ctypes.data_as(_fp), ct.byref(loss)))
+        return loss.value, g
+
+    def train(self, steps, batch, lr):
+        losses = np.zeros(max(steps, 1), np.float64)
+        _check(_lib.ahom_guess_train(self._h, steps, batch, float(lr), _ptr(losses, ct.c_double)))
+        return losses[:steps]
+
+    def adam_step(self, grad, lr):
+        g = np.ascontiguousarray(np.asarray(grad, dtype=np.float32))
+        _check(_lib.ahom_guess_adam_step(self._h, g.ctypes.data_as(_fp), float(lr)))
+
+    def infer(self, phase, lame, lam0, mu0, eps_bar, out=None):
+        """Initial fluctuation (n_load, 6, n^3) for strains eps_bar (n_load, 3, 3); out: DeviceArray or None (host)."""
+        lame = np.ascontiguousarray(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
+        eb = np.ascontiguousarray(np.asarray(eps_bar, dtype=np.float64).reshape(-1, 9))
+        nl = eb.shape[0]
+        if out is None:
+            host = np.zeros((nl, 6, self.P), np.float64)
+            _check(_lib.ahom_guess_infer(self._h, lame.shape[0], _ptr(lame, ct.c_double), float(lam0), float(mu0), ph.ctypes.data,
+                                         nl, _ptr(eb, ct.c_double), host.ctypes.data, MEM_HOST))
+            return host
+        _check(_lib.ahom_guess_infer(self._h, lame.shape[0], _ptr(lame, ct.c_double), float(lam0), float(mu0), ph.ctypes.data,
+                                     nl, _ptr(eb, ct.c_double), out.data_ptr(), MEM_DEVICE))
+        return out
+
+    def predict_sample(self, i):
+        out = np.zeros((self.P, 36), np.float32)
+        _check(_lib.ahom_guess_predict_sample(self._h, i, out.ctypes.data_as(_fp)))
+        return out
+
+    def save(self, path):
+        _check(_lib.ahom_guess_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(_lib.ahom_guess_load(self._h, str(path).encode()))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.ahom_guess_destroy(self._h)
             self._h = None

@@ -315,3 +315,43 @@ def ellipses_phase(points_num, m, ellipses):
 
 def random_phase_field(m, n_phase, seed):
     return np.random.default_rng(seed).integers(0, n_phase, size=m).astype(np.uint8)
+
+
+def random_rotation(rng):
+    """Uniformly distributed rotation (QR of a Gaussian matrix with sign fix)."""
+    A = rng.standard_normal((3, 3))
+    Q, R = np.linalg.qr(A)
+    Q = Q * np.sign(np.diag(R))[None, :]
+    if np.linalg.det(Q) < 0:
+        Q[:, 0] = -Q[:, 0]
+    return Q
+
+
+def ellipsoids_member(seed):
+    """Learned-guess workload member: 1-20 randomly oriented ellipsoids, axis
+    ratios U[1, 3], a common scale that makes the voxel volume fraction
+    U[0.1, 0.4] (overlap allowed), contrast U[2, 100], nu = 0.3."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 21))
+    ell = []
+    for _ in range(k):
+        ell.append(dict(centre=rng.uniform(-0.5, 0.5, size=3),
+                        axes=np.array([1.0, rng.uniform(1.0, 3.0), rng.uniform(1.0, 3.0)]),
+                        R=random_rotation(rng)))
+    vf = float(rng.uniform(0.1, 0.4))
+    contrast = float(rng.uniform(2.0, 100.0))
+    return dict(ellipsoids=ell, vf=vf, contrast=contrast, lame=(lame(1.0, 0.3), lame(contrast, 0.3)))
+
+
+def ellipsoids_phase(points_num, m, member):
+    """Phase 1 where min_k (d_k^T A_k d_k) <= s^2 (minimum image d_k), s chosen
+    so that the fraction of points in phase 1 is the member's vf."""
+    y = np.asarray(points_num, dtype=np.float64) / m
+    q = np.full(y.shape[0], np.inf)
+    for e in member["ellipsoids"]:
+        d = y - e["centre"]
+        d -= np.round(d)
+        u = d @ e["R"]                     # coordinates in the ellipsoid's axes
+        q = np.minimum(q, np.sum((u / e["axes"]) ** 2, axis=1))
+    s2 = np.quantile(q, member["vf"])
+    return (q <= s2).astype(np.uint8)

@@ -1,0 +1,233 @@
+"""GPU: learned initial guess (BF16 matrix-core network) against the FP64 oracle.
+
+Layer parity uses BF16-rounded inputs on both sides (the kernels accumulate in
+FP32); the whole network runs BF16 activations through 15 layers, so its loss
+and gradients are compared in norm at 5e-2.  The last test trains a network
+on solves the scheme itself produced and reports what the guess saves.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import learned as NN
+
+pytestmark = pytest.mark.gpu
+ahom = pytest.importorskip("paper_1605_05712_amd.ahom")
+
+R2 = 1.0 / np.sqrt(2.0)
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_bf16(a):
+    """Round to the nearest BF16 (ties to even), returned as float32."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def cl_to_cf(a, n):
+    """channels-last (P, C) -> channel-first (C, n, n, n)"""
+    return np.asarray(a, dtype=np.float64).T.reshape(-1, n, n, n)
+
+
+def cf_to_cl(a):
+    return np.asarray(a).reshape(a.shape[0], -1).T
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
+
+
+@pytest.mark.parametrize("n,cin,cout,batch", [(8, 32, 32, 1), (6, 64, 48, 2), (4, 32, 16, 1), (5, 96, 64, 1)])
+def test_conv3d_forward_matches_oracle(n, cin, cout, batch):
+    say("conv fwd", n, cin, cout, batch)
+    r = np.random.default_rng(n * 1000 + cin)
+    P = n ** 3
+    x = to_bf16(r.standard_normal((batch, P, cin)))
+    w = to_bf16(r.standard_normal((cout, 27, cin)) * 0.1)
+    b = r.standard_normal(cout).astype(np.float32)
+    for relu in (False, True):
+        y = ahom.conv3d(n, cin, cout, 0, x=x, w=w, b=b, relu=relu, batch=batch)
+        for s in range(batch):
+            ref = NN.conv3d(cl_to_cf(x[s], n), w.astype(np.float64).transpose(0, 2, 1), b.astype(np.float64))
+            if relu:
+                ref = np.maximum(ref, 0.0)
+            assert rel(y[s], cf_to_cl(ref)) < 1e-4, (relu, s)
+
+
+@pytest.mark.parametrize("n,cin,cout", [(8, 32, 32), (6, 64, 96), (4, 96, 64)])
+def test_conv3d_adjoint_and_weight_gradient_match_oracle(n, cin, cout):
+    say("conv bwd", n, cin, cout)
+    r = np.random.default_rng(7 * n + cout)
+    P = n ** 3
+    x = to_bf16(r.standard_normal((1, P, cin)))
+    w = to_bf16(r.standard_normal((cout, 27, cin)) * 0.1)
+    dy = to_bf16(r.standard_normal((1, P, cout)))
+    wcf = w.astype(np.float64).transpose(0, 2, 1)
+    dx = ahom.conv3d(n, cin, cout, 1, w=w, dy=dy)
+    assert rel(dx[0], cf_to_cl(NN.conv3d_adjoint(cl_to_cf(dy[0], n), wcf))) < 1e-4
+    dw, db = ahom.conv3d(n, cin, cout, 2, x=x, dy=dy)
+    ref = NN.conv3d_wgrad(cl_to_cf(x[0], n), cl_to_cf(dy[0], n)).transpose(0, 2, 1)
+    assert rel(dw, ref) < 1e-4
+    assert rel(db, dy[0].astype(np.float64).sum(axis=0)) < 1e-5
+
+
+def unit_strain_from_fluct(fl):
+    """fluctuation (6, 6, P) -> total strain of the Mandel unit loads"""
+    st = np.array(fl, dtype=np.float64)
+    for k in range(6):
+        st[k, k] += 1.0 if k < 3 else R2
+    return st
+
+
+def test_network_loss_and_gradients_match_oracle():
+    """Whole network on 8^3 (levels 8, 4, 2, 1), two samples: loss and every layer's gradient."""
+    n = 8
+    P = n ** 3
+    say("network gradients", n)
+    g = ahom.Guess(n, batch=2, seed=5)
+    flat = g.params()
+    params = NN.unflatten(flat)
+    # the device multiplies BF16 weights
+    params_b = [(to_bf16(w).astype(np.float64), b) for w, b in params]
+    r = np.random.default_rng(11)
+    samples = []
+    for s in range(2):
+        ph = (r.random(P) < 0.3).astype(np.uint8)
+        lame = np.array([synth.lame(1.0, 0.3), synth.lame(20.0, 0.3)])
+        lam0, mu0 = lame[:, 0].mean(), lame[:, 1].mean()
+        fl = r.standard_normal((6, 6, P)) * 0.2
+        g.add_sample(ph, lame, lam0, mu0, unit_strain_from_fluct(fl))
+        samples.append((ph, lame, lam0, mu0, fl))
+    loss, grad = g.gradients([0, 1])
+    ref_loss = 0.0
+    ref_grads = None
+    for ph, lame, lam0, mu0, fl in samples:
+        x = NN.net_input(ph, lame, lam0, mu0, n)
+        out, cache = NN.forward(params_b, x)
+        lab = NN.label_from_strain(fl, n)
+        L, dout = NN.energy_loss(out, lab, lam0, mu0, batch=2)
+        ref_loss += L
+        gr = NN.backward(params_b, cache, dout)
+        ref_grads = gr if ref_grads is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(ref_grads, gr)]
+    print("loss", loss, "oracle", ref_loss, flush=True)
+    assert abs(loss - ref_loss) / ref_loss < 2e-2
+    mine = NN.unflatten(grad)
+    for k, ((gw, gb), (rw, rb)) in enumerate(zip(mine, ref_grads)):
+        ew = np.linalg.norm(gw - rw) / np.linalg.norm(rw)
+        eb = np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)
+        print(f"layer {k}: weight-gradient error {ew:.2e}, bias {eb:.2e}", flush=True)
+        assert ew < 5e-2 and eb < 5e-2, k
+
+
+def test_adam_steps_match_oracle():
+    g = ahom.Guess(8, batch=1, seed=2)
+    w0 = g.params().astype(np.float64)
+    r = np.random.default_rng(3)
+    m = np.zeros_like(w0)
+    v = np.zeros_like(w0)
+    w = w0
+    for t in (1, 2, 3):
+        gr = (r.standard_normal(w0.size) * 0.01).astype(np.float32)
+        g.adam_step(gr, 1e-3)
+        w, m, v = NN.adam(w, gr.astype(np.float64), m, v, t, 1e-3)
+        assert np.max(np.abs(g.params() - w)) < 1e-6 * max(1.0, np.max(np.abs(w)))
+
+
+def test_inference_combines_unit_loads_and_save_load(tmp_path):
+    n = 8
+    P = n ** 3
+    g = ahom.Guess(n, batch=1, seed=9)
+    r = np.random.default_rng(4)
+    ph = (r.random(P) < 0.4).astype(np.uint8)
+    lame = np.array([synth.lame(1.0, 0.3), synth.lame(5.0, 0.3)])
+    lam0, mu0 = lame[:, 0].mean(), lame[:, 1].mean()
+    g.add_sample(ph, lame, lam0, mu0, unit_strain_from_fluct(np.zeros((6, 6, P))))
+    pred = g.predict_sample(0)                              # (P, 36)
+    eb = np.zeros((2, 3, 3))
+    eb[0, 0, 0] = 2.0
+    eb[1, 0, 1] = eb[1, 1, 0] = 0.5
+    init = g.infer(ph, lame, lam0, mu0, eb)                 # (2, 6, P)
+    assert np.allclose(init[0], 2.0 * pred[:, 0:6].T, rtol=1e-6, atol=1e-7)
+    assert np.allclose(init[1], 0.5 * np.sqrt(2.0) * pred[:, 30:36].T, rtol=1e-6, atol=1e-7)
+    path = tmp_path / "guess.bin"
+    g.save(path)
+    g2 = ahom.Guess(n, batch=1, seed=123)
+    g2.load(path)
+    assert np.array_equal(g2.params(), g.params())
+
+
+def unit_loads():
+    eb = np.zeros((6, 3, 3))
+    pairs = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+    for k, (i, j) in enumerate(pairs):
+        v = 1.0 if i == j else R2
+        eb[k, i, j] = eb[k, j, i] = v
+    return eb
+
+
+def energy(fl, lam0, mu0):
+    """mean over loads and points of e : C0 : e / mu0 (the training norm)"""
+    e = np.asarray(fl).reshape(6, 6, -1)
+    tr = e[:, 0] + e[:, 1] + e[:, 2]
+    sq = e[:, 0] ** 2 + e[:, 1] ** 2 + e[:, 2] ** 2 + 2 * (e[:, 3] ** 2 + e[:, 4] ** 2 + e[:, 5] ** 2)
+    return float(np.mean(lam0 / mu0 * tr ** 2 + 2 * sq))
+
+
+def test_training_on_scheme_solves_and_the_gain():
+    """32^3 ellipsoid microstructures: train on solves of the scheme itself, then
+    measure on held-out seeds what the guess gains: its error in the training
+    norm against the zero guess's (asserted smaller), and the iterations to the
+    unchanged tolerance from both starts (reported; the result and C_eff must
+    not depend on the start)."""
+    n, ntrain, ntest = 32, 48, 6
+    say("train + gain", n, ntrain, ntest)
+    P = ahom.Pattern([[n, 0, 0], [0, n, 0], [0, 0, n]])
+    pts = P.points()
+    g = ahom.Guess(n, batch=4, seed=1)
+    loads = unit_loads()
+
+    def member(seed):
+        mb = synth.ellipsoids_member(seed)
+        ph = synth.ellipsoids_phase(pts, P.m, mb)
+        lame = np.array(mb["lame"])
+        return ph, lame, lame[:, 0].mean(), lame[:, 1].mean()
+
+    for s in range(100000, 100000 + ntrain):
+        ph, lame, lam0, mu0 = member(s)
+        S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
+        S.set_material(lame, ph)
+        out = S.solve(loads, want_strain=True, allow=(ahom.AHOM_OK,))
+        g.add_sample(ph, lame, lam0, mu0, out["strain"])
+    losses = g.train(400, 4, 1e-3)
+    print("loss first 10 mean", losses[:10].mean(), "last 10 mean", losses[-10:].mean(), flush=True)
+    assert losses[-10:].mean() < 0.5 * losses[:10].mean()
+    it0, it1, ratios = [], [], []
+    for s in range(200000, 200000 + ntest):
+        ph, lame, lam0, mu0 = member(s)
+        S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
+        S.set_material(lame, ph)
+        a = S.solve(loads, want_strain=True, allow=(ahom.AHOM_OK,))
+        fl = a["strain"].copy()
+        for k in range(6):
+            fl[k, k] -= 1.0 if k < 3 else R2
+        init = g.infer(ph, lame, lam0, mu0, loads)
+        ratios.append(energy(init - fl, lam0, mu0) / energy(fl, lam0, mu0))
+        b = S.solve(loads, init=init, allow=(ahom.AHOM_OK,))
+        assert np.all(b["resid"] <= 1e-6)
+        C0 = np.array([[a["mean_stress"][k][i, j] for k in range(6)] for i, j in [(0, 0), (1, 1), (2, 2)]])
+        C1 = np.array([[b["mean_stress"][k][i, j] for k in range(6)] for i, j in [(0, 0), (1, 1), (2, 2)]])
+        assert np.max(np.abs(C1 - C0)) < 1e-5 * np.max(np.abs(C0))
+        it0.append(a["iters"].mean())
+        it1.append(b["iters"].mean())
+        print(f"held-out {s}: guess error / zero-guess error (energy) {ratios[-1]:.3f}; iterations zero guess "
+              f"{a['iters'].tolist()} learned guess {b['iters'].tolist()}", flush=True)
+    print(f"mean iterations: zero guess {np.mean(it0):.1f}, learned guess {np.mean(it1):.1f}; "
+          f"mean error ratio {np.mean(ratios):.3f}", flush=True)
+    assert np.mean(ratios) < 0.6
