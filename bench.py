@@ -108,6 +108,93 @@ print(json.dumps(dict(seconds=dt, m=T.m)))
                        f"{rec['seconds']:.1f} s incl. the residual evaluations")
 
 
+def batch_workload(ahom):
+    """512 seeded 2-D members (uneven non-diagonal patterns, 1,024..65,536 points),
+    3 loads, FP32 with FP64 residual, tol 1e-6, one persistent launch from a graph."""
+    import numpy as np
+    import synth
+    seeds = range(4000, 4512)
+    mbs = [synth.batch_2d_member(s) for s in seeds]
+    B = ahom.Batch([mb["M"] for mb in mbs], precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
+    ms_pts = []
+    for i, mb in enumerate(mbs):
+        m, _ = B.info(i)
+        ms_pts.append(m)
+        B.set_material(i, np.array(mb["lame"]), synth.ellipses_phase(B.points(i), m, mb["ellipses"]))
+    eb = np.zeros((3, 3, 3))
+    eb[0, 0, 0] = 1.0
+    eb[1, 1, 1] = 1.0
+    eb[2, 0, 1] = eb[2, 1, 0] = 1.0 / math.sqrt(2.0)
+    print("[bench] batch: tuning plans and building 1536 items", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    B.solve(eb, use_graph=True)            # tuning, allocation, graph capture, first launch
+    t_setup = time.perf_counter() - t0
+    out = B.solve(eb, use_graph=True)      # timed replay
+    ms, restarts = B.last_timing()
+    upd = float(np.sum(np.array(ms_pts)[:, None] * out["iters"]))
+    print(f"[bench] batch: {ms:.1f} ms device, {upd:.3e} point updates", file=sys.stderr, flush=True)
+    return dict(members=len(mbs), loads=3, points=int(sum(ms_pts)), device_ms=round(ms, 2),
+                point_updates=upd, updates_per_s=round(upd / (ms * 1e-3), 1), restarts=int(restarts),
+                iters_min=int(out["iters"].min()), iters_max=int(out["iters"].max()),
+                converged=bool(np.all(out["item_status"] == 0)), setup_s=round(t_setup, 1),
+                precision="fp32 + fp64 residual, tol 1e-6", launch="one persistent kernel replayed from a HIP graph")
+
+
+def learned_workload(ahom, ntrain, steps, n=64, ntest=4):
+    """Learned initial guess on 64^3 ellipsoid microstructures: train on solves of
+    the scheme, then time-to-1e-6 on held-out seeds from the zero guess (FP64 and
+    FP32) and from the learned guess (FP32, inference included)."""
+    import numpy as np
+    import synth
+    P = ahom.Pattern([[n, 0, 0], [0, n, 0], [0, 0, n]])
+    pts = P.points()
+    loads = mandel_loads()
+    g = ahom.Guess(n, batch=4, seed=1)
+
+    def member(seed):
+        mb = synth.ellipsoids_member(seed)
+        ph = synth.ellipsoids_phase(pts, P.m, mb)
+        lame = np.array(mb["lame"])
+        return ph, lame, lame[:, 0].mean(), lame[:, 1].mean()
+
+    t0 = time.perf_counter()
+    for s in range(100000, 100000 + ntrain):
+        ph, lame, lam0, mu0 = member(s)
+        S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
+        S.set_material(lame, ph)
+        out = S.solve(loads, want_strain=True)
+        g.add_sample(ph, lame, lam0, mu0, out["strain"])
+    t_data = time.perf_counter() - t0
+    print(f"[bench] learned: {ntrain} training solves in {t_data:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    losses = g.train(steps, 4, 1e-3)
+    t_train = time.perf_counter() - t0
+    print(f"[bench] learned: {steps} steps in {t_train:.1f} s, loss {losses[:10].mean():.3f} -> {losses[-10:].mean():.3f}",
+          file=sys.stderr, flush=True)
+    rows = []
+    for s in range(200000, 200000 + ntest):
+        ph, lame, lam0, mu0 = member(s)
+        row = {}
+        for name, prec, guess in (("fp64", ahom.FP64, False), ("fp32", ahom.FP32_MIXED, False), ("fp32_guess", ahom.FP32_MIXED, True)):
+            S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4)
+            S.set_material(lame, ph)
+            S.solve(loads[:1])                       # warm (tuning)
+            d_init = ahom.DeviceArray((6, 6, P.m), np.float64) if guess else None
+            t0 = time.perf_counter()
+            if guess:
+                g.infer(ph, lame, lam0, mu0, loads, out=d_init)     # device to device, no host copies
+            o = S.solve_device(loads, init=d_init)
+            row[name] = dict(ms=round((time.perf_counter() - t0) * 1e3, 2), iters=float(o["iters"].mean()))
+        rows.append(row)
+    mean = {k: float(np.mean([r[k]["ms"] for r in rows])) for k in rows[0]}
+    its = {k: float(np.mean([r[k]["iters"] for r in rows])) for k in rows[0]}
+    return dict(n=n, train_solves=ntrain, steps=steps, data_s=round(t_data, 1), train_s=round(t_train, 1),
+                loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean()),
+                held_out=ntest, mean_ms=mean, mean_iters=its,
+                speedup_guess_fp32_vs_fp64=round(mean["fp64"] / mean["fp32_guess"], 3),
+                speedup_fp32_vs_fp64=round(mean["fp64"] / mean["fp32"], 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +203,11 @@ def main():
     ap.add_argument("--size", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-member batched 2-D workload")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
+    ap.add_argument("--learned-train", type=int, default=64, help="training solves for --learned")
+    ap.add_argument("--learned-steps", type=int, default=400, help="Adam steps for --learned")
     ap.add_argument("--fp64-only", action="store_true", help="throughput of the FP64 path only (profiling runs)")
     ap.add_argument("--ttt-resid-period", type=int, default=4,
                     help="residual evaluated every k iterations in the time-to-tolerance solves")
@@ -197,6 +289,12 @@ def main():
         ttt["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["fp32"]["ms"], 3)
 
     cpu = None
+    batch = None
+    if not args.no_batch:
+        batch = batch_workload(ahom)
+    learned = None
+    if args.learned:
+        learned = learned_workload(ahom, args.learned_train, args.learned_steps)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(args.size)
@@ -214,6 +312,8 @@ def main():
         device_ms_per_step=round(main_res["device_ms_per_step"], 4),
         time_to_1e6=ttt,
         time_to_1e6_resid_period=args.ttt_resid_period,
+        batch_2d=batch,
+        learned_guess=learned,
     )
     print(json.dumps(line))
 
