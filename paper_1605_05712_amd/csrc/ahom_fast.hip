@@ -277,6 +277,16 @@ __device__ void block_sum(double* vals, double* scratch) {
         }
 }
 
+// Tile of schedule slot t (of n).  Workgroups are dealt to the 8 XCDs
+// round-robin (slot t runs on XCD t % 8); give each XCD a contiguous range of
+// tiles, so that tiles sharing HBM lines (neighbouring column blocks) meet in
+// the same L2.  A bijection of [0, n).
+__device__ __forceinline__ int64_t xcd_tile(int64_t t, int64_t n) {
+    const int64_t per = n >> 3, rem = n & 7;
+    const int64_t x = t & 7, i = t >> 3;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
 // exact (A kappa) mod emax, centred; double path while products stay below 2^53
 __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_t* kap, int64_t* N, int dim) {
     int half = 0;
@@ -356,11 +366,12 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
     };
 
     int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(t) : false;
+    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
     for (; t < total; t += gridDim.x) {
         const bool cur = have;
-        const int load = (int)(t / nct);
-        const int64_t c0 = (t % nct) * NC;
+        const int64_t tt = xcd_tile(t, total);
+        const int load = (int)(tt / nct);
+        const int64_t c0 = (tt % nct) * NC;
         const int ncol = (int)((I - c0) < NC ? (I - c0) : NC);
         if (cur) {
             // packed full spectra Z_p = A + i B from the half spectra
@@ -386,7 +397,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
         else have = false;
         if (!cur) {
             if constexpr (!G::PERSIST) break;
@@ -458,7 +469,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         __syncthreads();
         block_sum<NCOMP>(sig, reinterpret_cast<double*>(Z));
         if (tid == 0)
-            for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * nct + t % nct) * NCOMP + c] = sig[c];
+            for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * nct + tt % nct) * NCOMP + c] = sig[c];
         __syncthreads();
         if constexpr (!G::PERSIST) break;  // one tile per workgroup
     }
@@ -537,12 +548,12 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
     };
 
     int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(t) : false;
+    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
     for (; t < total; t += gridDim.x) {
         const bool cur = have;
         int load;
         int64_t c0;
-        C* base = tile_base(t, load, c0);
+        C* base = tile_base(xcd_tile(t, total), load, c0);
         const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
         if (cur) {
             sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
@@ -558,7 +569,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
         else have = false;
         if (!cur) {
             if constexpr (!G::PERSIST) break;
@@ -626,11 +637,12 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     };
 
     int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(t) : false;
+    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
     for (; t < total; t += gridDim.x) {
         const bool cur = have;
-        const int load = (int)(t / nct);
-        const int64_t c0 = (t % nct) * NC;
+        const int64_t tt = xcd_tile(t, total);
+        const int load = (int)(tt / nct);
+        const int64_t c0 = (tt % nct) * NC;
         const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
         if (cur) {
             sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
@@ -665,7 +677,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         }
         __syncthreads();
         const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(tn) : false;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
         else have = false;
         if (!cur) {
             if constexpr (!G::PERSIST) break;
@@ -803,7 +815,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         __syncthreads();
         double rv[1] = {res};
         block_sum<1>(rv, reinterpret_cast<double*>(F));
-        if (tid == 0) a.res_part[(int64_t)load * nct + t % nct] = rv[0];
+        if (tid == 0) a.res_part[(int64_t)load * nct + tt % nct] = rv[0];
         __syncthreads();
         if constexpr (!G::PERSIST) break;  // one tile per workgroup
     }
