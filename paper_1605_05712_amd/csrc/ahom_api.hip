@@ -517,10 +517,13 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
         for (int a = 1; a <= P.D - 2; ++a)
             if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, 0, &fg)) s->f_axis[a] = true;
         const char* venv = getenv("AHOM_FAST_VARIANT");
-        if (venv && venv[0] >= '0' && venv[0] <= '3') {
+        if (venv && venv[0] >= '0' && venv[0] <= '4') {
             const int v = venv[0] - '0';
-            s->v_real = s->v_spec = v;
-            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v;
+            FastGeom fg4;
+            const bool rr_ok = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, v, &fg4);
+            s->v_real = rr_ok ? v : 0;          // variant 4 exists for the real-space pass only
+            s->v_spec = v < 4 ? v : 0;
+            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v < 4 ? v : 0;
             s->tuned = true;
         }
         s->apply_variants();

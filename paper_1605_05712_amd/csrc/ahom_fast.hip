@@ -476,6 +476,199 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
 }
 
 // =============================================================================
+// real-space turnaround, register-resident variant: one wave owns a tile of
+// 64 / N1 columns and all packed transforms of it; the columns stay in
+// registers from the gather to the scatter, the local law runs on them in
+// place, and LDS only carries the FFT exchange and the final half-spectrum
+// split, in a region private to the wave (no workgroup barrier per stage).
+// =============================================================================
+template <typename T, int L> struct RR {
+    static constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2, B = N2 / N1;
+    static constexpr int NCW = 64 / N1;      // columns per wave
+    static constexpr int W = 4;              // waves (independent tiles) per workgroup
+    static constexpr int CS = L + 1;
+    static constexpr int REGION = NCW * CS;  // complex elements of one wave's LDS region
+};
+
+// LDS stores of this wave visible to its later loads (no other wave involved)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FFT of one column held by the N1 threads tau of it: v[q] = x[tau + N1 q] in,
+// v[b N1 + kb] = X[tau + N1 b + N2 kb] out; base = the column's LDS region.
+template <int L, int DIR, typename C>
+__device__ __forceinline__ void fft_reg(C* v, C* base, int tau, const C* twl) {
+    constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2, B = N2 / N1;
+    dft<N2, DIR>(v);
+    sfor<1, N2>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int ka = kc;
+        const C w = twl[ka * N1 + tau];
+        v[ka] = DIR < 0 ? cmul(v[ka], w) : cmulc(v[ka], w);
+    });
+    wave_lds_sync();
+    sfor<0, N2>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int ka = kc;
+        base[ka * N1 + (tau ^ (ka & (N1 - 1)))] = v[ka];
+    });
+    wave_lds_sync();
+    sfor<0, B>([&](auto bc) __attribute__((always_inline)) {
+        constexpr int b = bc;
+        sfor<0, N1>([&](auto tc) __attribute__((always_inline)) {
+            constexpr int t = tc;
+            v[b * N1 + t] = base[(tau + N1 * b) * N1 + (t ^ tau)];
+        });
+        dft<N1, DIR>(v + b * N1);
+    });
+}
+
+template <typename T, int DIM, int L>
+__global__ void __launch_bounds__(256) kf_real_rr(RealArgs a) {
+    using C = typename CT<T>::t;
+    using R = RR<T, L>;
+    constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    constexpr int N1 = R::N1, N2 = R::N2, B = R::B, NCW = R::NCW, CS = R::CS, H = L / 2 + 1;
+    constexpr int TW = NCW * R::W;          // columns per workgroup tile
+    const Plan& P = *a.plan;
+    const AxisDesc& ax = P.ax[0];
+    const int64_t I = P.S / H;
+    const int64_t nct = (I + TW - 1) / TW;
+    const int64_t total = nct * a.nload;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tau = lane % N1, jj = lane / N1;
+    C* twl = smem<C>();
+    C* X = twl + L + wave * R::REGION + jj * CS;
+    double* red = reinterpret_cast<double*>(twl + L + R::W * R::REGION);
+    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
+    __syncthreads();
+    const int64_t tt = xcd_tile(blockIdx.x, total);
+    const int load = (int)(tt / nct);
+    const LoadState& st = a.st[load];
+    if (st.done) return;
+    const int64_t col = (tt % nct) * TW + wave * NCW + jj;
+    const bool act = col < I;
+    const int64_t colc = act ? col : 0;
+    const C* src = reinterpret_cast<const C*>((st.iter & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+    C* dst = reinterpret_cast<C*>((st.iter & 1) ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
+
+    // gather the packed full spectra Z_p[k] = A + i B, k = tau + N1 q (rows above
+    // L/2 from the conjugate half-spectrum row L - k)
+    C v[NP][N2];
+    sfor<0, N2>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = qc;
+        const int k = tau + N1 * q;
+        const bool upper = 2 * k > L;
+        const int kr = upper ? L - k : k;
+        C w = C{(T)1, (T)0};
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (colc / ax.qdiv) * (int64_t)kr);
+        sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int p = pc;
+            C A = ldg(src + (int64_t)(2 * p) * P.S + (int64_t)kr * I + colc);
+            C Bv = C{(T)0, (T)0};
+            if constexpr (2 * p + 1 < NCOMP) Bv = ldg(src + (int64_t)(2 * p + 1) * P.S + (int64_t)kr * I + colc);
+            if (ax.split) { A = cmulc(A, w); Bv = cmulc(Bv, w); }
+            if (kr == 0 || 2 * kr == L) { A.y = 0; Bv.y = 0; }
+            v[p][q] = upper ? C{A.x + Bv.y, Bv.x - A.y} : C{A.x - Bv.y, A.y + Bv.x};
+        });
+    });
+    sfor<0, NP>([&](auto pc) __attribute__((always_inline)) { fft_reg<L, +1>(v[decltype(pc)::value], X, tau, twl); });
+
+    // local law at x_n, n = tau + N1 (b + B kb) for v[.][b N1 + kb]; then the
+    // forward transforms take the samples back in the order n = tau + N1 q
+    const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
+    double sig[NCOMP];
+#pragma unroll
+    for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
+    C u[NP][N2];
+    sfor<0, N2>([&](auto ic) __attribute__((always_inline)) {
+        constexpr int i = ic;
+        constexpr int b = i / N1, kb = i % N1;
+        constexpr int qpos = b + B * kb;
+        const int n = tau + N1 * qpos;
+        const int64_t pt_t = colc * (int64_t)L + n;
+        T lam, mu;
+        if (a.lame_pts_t) {
+            lam = (T)a.lame_pts_t[2 * pt_t];
+            mu = (T)a.lame_pts_t[2 * pt_t + 1];
+        } else {
+            const int ph = a.phase_t[pt_t];
+            lam = (T)a.lame_tab[2 * ph];
+            mu = (T)a.lame_tab[2 * ph + 1];
+        }
+        T eps[NCOMP];
+        sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int p = pc;
+            eps[2 * p] = v[p][i].x;
+            if constexpr (2 * p + 1 < NCOMP) eps[2 * p + 1] = v[p][i].y;
+        });
+        const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+        const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+        T tv[NCOMP];
+#pragma unroll
+        for (int c = 0; c < NCOMP; ++c) {
+            const bool diag = DIM == 3 ? c < 3 : c < 2;
+            if (act) sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
+            tv[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+        }
+        sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int p = pc;
+            u[p][qpos] = C{tv[2 * p], 2 * p + 1 < NCOMP ? tv[2 * p + 1] : (T)0};
+        });
+    });
+
+    // forward transforms and the half-spectrum split A_k, B_k (k <= L/2),
+    // rows k = tau + N1 r of this thread's column
+    sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = pc;
+        fft_reg<L, -1>(u[p], X, tau, twl);
+        wave_lds_sync();
+        sfor<0, N2>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = ic;
+            constexpr int b = i / N1, kb = i % N1;
+            X[tau + N1 * b + N2 * kb] = u[p][i];
+        });
+        wave_lds_sync();
+        sfor<0, (H + N1 - 1) / N1>([&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = rc;
+            const int k = tau + N1 * r;
+            if (k < H && act) {
+                const int km = k == 0 ? 0 : L - k;
+                const C zk = X[k], zm = X[km];
+                C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
+                C Bv = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
+                if (ax.split) {
+                    const C w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+                    A = cmul(A, w);
+                    Bv = cmul(Bv, w);
+                }
+                stg(dst + (int64_t)(2 * p) * P.S + (int64_t)k * I + col, A);
+                if constexpr (2 * p + 1 < NCOMP) stg(dst + (int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col, Bv);
+            }
+        });
+    });
+
+    // mean-stress partial sums: wave butterflies, then the waves in order
+#pragma unroll
+    for (int c = 0; c < NCOMP; ++c) {
+        double x = sig[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        sig[c] = x;
+    }
+    if (lane == 0)
+        for (int c = 0; c < NCOMP; ++c) red[wave * NCOMP + c] = sig[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int c = 0; c < NCOMP; ++c) {
+            double acc = 0.0;
+            for (int w2 = 0; w2 < R::W; ++w2) acc += red[w2 * NCOMP + c];
+            a.sig_part[((int64_t)load * nct + tt % nct) * NCOMP + c] = acc;
+        }
+}
+
+// =============================================================================
 // middle axes
 // =============================================================================
 template <typename T, int L, int DIR, int V>
@@ -935,8 +1128,40 @@ int spec_TV(int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream
 }  // namespace ahom_fast_detail
 
 namespace ahom_fast_detail {
+// register-resident real-space variant (tile variant 4)
+constexpr int kRRVariant = 4;
+constexpr bool rr_length(int L) { return L >= 32 && L <= 256; }
+
+template <typename T, int LL>
+FastGeom geom_rr(int dim) {
+    using R = RR<T, LL>;
+    FastGeom g;
+    g.NC = R::NCW * R::W;
+    g.threads = 64 * R::W;
+    g.persistent = false;
+    g.lds = (size_t)(LL + R::W * R::REGION) * 2 * sizeof(T) + (size_t)R::W * 6 * 8;
+    (void)dim;
+    return g;
+}
+
+template <typename T>
+bool geom_rr_T(int dim, int L, FastGeom* g) {
+    switch (L) {
+        case 32: *g = geom_rr<T, 32>(dim); return true;
+        case 64: *g = geom_rr<T, 64>(dim); return true;
+        case 128: *g = geom_rr<T, 128>(dim); return true;
+        case 256: *g = geom_rr<T, 256>(dim); return true;
+        default: return false;
+    }
+}
+
+template <typename T>
+int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
+
 template <typename T>
 bool geom_T(int kind, int dim, int L, int v, FastGeom* g) {
+    if (v == kRRVariant) return kind == FAST_REAL && rr_length(L) && geom_rr_T<T>(dim, L, g);
+    if (v > kRRVariant) return false;
     if (!tuned_length(L)) v = 0;
     switch (v) {
         case 0: return geom_TV<T, 0>(kind, dim, L, g);
@@ -969,10 +1194,28 @@ AHOM_INST_SPEC(double, 0) AHOM_INST_SPEC(double, 1)
 AHOM_INST_SPEC(double, 2) AHOM_INST_SPEC(double, 3)
 #elif AHOM_FAST_PART == 6
 AHOM_INST_SPEC(float, 0) AHOM_INST_SPEC(float, 1) AHOM_INST_SPEC(float, 2) AHOM_INST_SPEC(float, 3)
+#elif AHOM_FAST_PART == 7
+template <typename T>
+int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
+    FastGeom g;
+    if (!geom_rr_T<T>(dim, L, &g)) return -1;
+#define AHOM_FRR(LL)                                                                 \
+    case LL:                                                                         \
+        return dim == 3 ? go(kf_real_rr<T, 3, LL>, g, total, ncu, s, a) : go(kf_real_rr<T, 2, LL>, g, total, ncu, s, a);
+    switch (L) {
+        AHOM_FRR(32) AHOM_FRR(64) AHOM_FRR(128) AHOM_FRR(256)
+        default: return -1;
+    }
+#undef AHOM_FRR
+}
+template int real_RR<double>(int, int, const RealArgs&, int64_t, int, hipStream_t);
+template int real_RR<float>(int, int, const RealArgs&, int64_t, int, hipStream_t);
 #endif
 #else
 AHOM_DECL_TV(double, 0) AHOM_DECL_TV(double, 1) AHOM_DECL_TV(double, 2) AHOM_DECL_TV(double, 3)
 AHOM_DECL_TV(float, 0) AHOM_DECL_TV(float, 1) AHOM_DECL_TV(float, 2) AHOM_DECL_TV(float, 3)
+extern template int real_RR<double>(int, int, const RealArgs&, int64_t, int, hipStream_t);
+extern template int real_RR<float>(int, int, const RealArgs&, int64_t, int, hipStream_t);
 #endif
 
 }  // namespace ahom_fast_detail
@@ -1004,6 +1247,10 @@ bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g
 
 int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     int rc;
+    if (variant == kRRVariant) {
+        rc = prec == 0 ? real_RR<double>(dim, L, a, total, ncu, s) : real_RR<float>(dim, L, a, total, ncu, s);
+        return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     auto run = [&]() -> int { AHOM_VSWITCH(real_TV, dim, L, a, total, ncu, s); };
     rc = run();
     return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;

@@ -187,7 +187,7 @@ struct FastGeom {
     bool persistent = false;
     size_t lds = 0;
 };
-constexpr int AHOM_FAST_VARIANTS = 4;   // tile width x schedule, chosen by the autotuner
+constexpr int AHOM_FAST_VARIANTS = 5;   // tile width x schedule (+ register-resident real pass), chosen by the autotuner
 bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g);
 // total = tiles of the pass (all loads/fields); the grid is sized from the occupancy API
 int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s);

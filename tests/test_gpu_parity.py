@@ -281,7 +281,7 @@ def test_every_tile_variant_matches_generic(name, M, prec, monkeypatch):
     del S
     monkeypatch.setenv("AHOM_GENERIC_ONLY", "0")
     tol = 1e-12 if prec == ahom.FP64 else 2e-5
-    for v in "0123":
+    for v in "01234":
         monkeypatch.setenv("AHOM_FAST_VARIANT", v)
         S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=3)
         S.set_material(LAM3, ph)
