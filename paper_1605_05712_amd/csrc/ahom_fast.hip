@@ -156,7 +156,8 @@ constexpr int pow2floor(int v) {
 template <typename T, int L, int NF, int V = 0> struct Geo {
     static constexpr int es = 2 * (int)sizeof(T);
     static constexpr int N1 = Split<L>::N1;
-    static constexpr int CS = L + 1;  // odd: consecutive columns start in distinct LDS banks
+    static constexpr int GL = 128 / es;  // elements per 128 B LDS line
+    static constexpr int CS = L >= GL ? L : L + 1;  // line-aligned columns (swizzled, see lsw)
     static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
     static constexpr int by_thr = 512 / (NF * N1);
     static constexpr int NCMAX = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
@@ -165,6 +166,24 @@ template <typename T, int L, int NF, int V = 0> struct Geo {
     static constexpr int THREADS = ((NF * NC * N1 + 63) / 64) * 64;
     static constexpr int TILE = NF * NC * CS;  // complex elements of LDS tile
 };
+
+// XOR mask of the element index inside LDS tile column `col`.  Columns are
+// unpadded, so every column starts on a 128 B line and a lane group that
+// sweeps N1 consecutive elements of one column stays inside one line; the
+// mask makes the GL consecutive columns that lanes read row by row (loads,
+// stores, pack/unpack) hit distinct banks, and places the columns that share
+// one GL-lane group in the FFT stages (GL / N1 of them) in disjoint quarters.
+template <int L, typename C> __device__ __forceinline__ int lsw(int col) {
+    constexpr int GL = 128 / (int)sizeof(C);
+    if constexpr (L < GL) {
+        return 0;
+    } else {
+        constexpr int N1 = Split<L>::N1;
+        constexpr int P = N1 >= GL ? 1 : GL / N1;
+        constexpr int Q = GL / P;
+        return ((col % P) * (N1 >= GL ? 1 : N1)) | ((col / P) % Q);
+    }
+}
 
 // FFT of `ncols` columns (stride CS) of an LDS tile in place.  twl holds the
 // inter-stage twiddles as twl[ka * N1 + tau] = W_L^{tau ka}.  The exchange
@@ -177,21 +196,22 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
     const int col = s / N1, tau = s % N1;
     const bool act = col < ncols;
     C* base = lds + col * CS;
+    const int sz = lsw<L, C>(col);
     C v[N2];
     if constexpr (N1 == 1) {
         if (act) {
 #pragma unroll
-            for (int q = 0; q < N2; ++q) v[q] = base[q];
+            for (int q = 0; q < N2; ++q) v[q] = base[q ^ sz];
             dft<N2, DIR>(v);
 #pragma unroll
-            for (int q = 0; q < N2; ++q) base[q] = v[q];
+            for (int q = 0; q < N2; ++q) base[q ^ sz] = v[q];
         }
         __syncthreads();
         return;
     } else {
         if (act) {
 #pragma unroll
-            for (int q = 0; q < N2; ++q) v[q] = base[tau + N1 * q];
+            for (int q = 0; q < N2; ++q) v[q] = base[(tau + N1 * q) ^ sz];
         }
         __syncthreads();
         if (act) {
@@ -202,7 +222,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
                 v[ka] = DIR < 0 ? cmul(v[ka], w) : cmulc(v[ka], w);
             }
 #pragma unroll
-            for (int ka = 0; ka < N2; ++ka) base[ka * N1 + (tau ^ (ka & (N1 - 1)))] = v[ka];
+            for (int ka = 0; ka < N2; ++ka) base[(ka * N1 + (tau ^ (ka & (N1 - 1)))) ^ sz] = v[ka];
         }
         __syncthreads();
         constexpr int B = N2 / N1;
@@ -210,7 +230,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
             for (int b = 0; b < B; ++b)
 #pragma unroll
-                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[(tau + N1 * b) * N1 + (t ^ tau)];
+                for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[((tau + N1 * b) * N1 + (t ^ tau)) ^ sz];
         }
         __syncthreads();
         if (act) {
@@ -218,7 +238,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
             for (int b = 0; b < B; ++b) {
                 dft<N1, DIR>(v + b * N1);
 #pragma unroll
-                for (int kb = 0; kb < N1; ++kb) base[tau + N1 * b + N2 * kb] = v[b * N1 + kb];
+                for (int kb = 0; kb < N1; ++kb) base[(tau + N1 * b + N2 * kb) ^ sz] = v[b * N1 + kb];
             }
         }
         __syncthreads();
@@ -390,8 +410,9 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
                     if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
                     if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
                     C* Zp = Z + (p * NC + j) * CS;
-                    Zp[k] = C{A.x - B.y, A.y + B.x};
-                    if (k > 0 && 2 * k != L) Zp[L - k] = C{A.x + B.y, B.x - A.y};
+                    const int sz = lsw<L, C>(p * NC + j);
+                    Zp[k ^ sz] = C{A.x - B.y, A.y + B.x};
+                    if (k > 0 && 2 * k != L) Zp[(L - k) ^ sz] = C{A.x + B.y, B.x - A.y};
                 });
             });
         }
@@ -428,7 +449,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
             T eps[NCOMP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const C z = Z[(p * NC + j) * CS + n];
+                const C z = Z[(p * NC + j) * CS + (n ^ lsw<L, C>(p * NC + j))];
                 eps[2 * p] = z.x;
                 if (2 * p + 1 < NCOMP) eps[2 * p + 1] = z.y;
             }
@@ -443,7 +464,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
-                Z[(p * NC + j) * CS + n] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
+                Z[(p * NC + j) * CS + (n ^ lsw<L, C>(p * NC + j))] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
         }
         __syncthreads();
         fft_cols<L, -1, CS>(Z, NP * NC, twl);
@@ -458,7 +479,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const C* Zp = Z + (p * NC + j) * CS;
-                const C zk = Zp[k], zm = Zp[km];
+                const int sz = lsw<L, C>(p * NC + j);
+                const C zk = Zp[k ^ sz], zm = Zp[km ^ sz];
                 C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
                 C B = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
                 if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
@@ -757,7 +779,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
                 if (e >= NC * L || j >= ncol) return;
                 C v = pre[q];
                 if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
-                X[j * CS + l] = v;
+                X[j * CS + (l ^ lsw<L, C>(j))] = v;
             });
         }
         __syncthreads();
@@ -774,7 +796,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             int j, l;
             map(e, j, l);
             if (j >= ncol) continue;
-            C v = X[j * CS + l];
+            C v = X[j * CS + (l ^ lsw<L, C>(j))];
             if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
             stg(base + addr(c0, cb, j, l), v);
         }
@@ -845,7 +867,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 if (e >= NC * L || j >= ncol) return;
                 sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
                     constexpr int f = fc;
-                    F[(f * NC + j) * CS + l] = pre[q][f];
+                    F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))] = pre[q][f];
                 });
             });
             if (tid < NC) {
@@ -907,7 +929,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                               kb[j * 4 + 2] + (last_snf == 2 ? add : 0)};
             C* fp[NCOMP];
 #pragma unroll
-            for (int f = 0; f < NCOMP; ++f) fp[f] = F + (f * NC + j) * CS + l;
+            for (int f = 0; f < NCOMP; ++f) fp[f] = F + (f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j));
             if (kap[0] == 0 && kap[1] == 0 && kap[2] == 0) {
 #pragma unroll
                 for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)eb[f], (T)0};
@@ -1003,7 +1025,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
             const int64_t addr = c0 * L + e;
             const int l = e % L;
 #pragma unroll
-            for (int f = 0; f < NCOMP; ++f) stg(base + (int64_t)f * P.S + addr, F[(f * NC + j) * CS + l]);
+            for (int f = 0; f < NCOMP; ++f) stg(base + (int64_t)f * P.S + addr, F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))]);
         }
         __syncthreads();
         double rv[1] = {res};
