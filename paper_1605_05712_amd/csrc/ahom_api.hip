@@ -273,6 +273,7 @@ struct ahom_solver {
         a.lame_pts = d_lame_pts;
         a.phase_t = d_phase_t;
         a.lame_pts_t = d_lame_pts_t;
+        a.n_phase = d_lame_pts_t ? 0 : n_phase;
         a.lam0 = lam0;
         a.mu0 = mu0;
         a.sig_part = d_sig;

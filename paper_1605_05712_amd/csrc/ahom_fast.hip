@@ -185,14 +185,23 @@ template <int L, typename C> __device__ __forceinline__ int lsw(int col) {
     }
 }
 
+// LDS stores of this wave visible to its later loads (no other wave involved)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // FFT of `ncols` columns (stride CS) of an LDS tile in place.  twl holds the
 // inter-stage twiddles as twl[ka * N1 + tau] = W_L^{tau ka}.  The exchange
 // between the stages stores row r, entry c at r * N1 + (c ^ (r % N1)) so that
-// the N1 threads of a column touch distinct LDS banks in both stages.
+// the N1 threads of a column touch distinct LDS banks in both stages.  The N1
+// threads of a column lie in one wavefront (N1 divides 64), so the exchange
+// only needs wave-level ordering; one workgroup barrier at the end hands the
+// transformed tile to the next stage.
 template <int L, int DIR, int CS, typename C>
-__device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
+__device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl, int s = threadIdx.x) {
     constexpr int N1 = Split<L>::N1, N2 = Split<L>::N2;
-    const int s = threadIdx.x;
     const int col = s / N1, tau = s % N1;
     const bool act = col < ncols;
     C* base = lds + col * CS;
@@ -213,7 +222,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
             for (int q = 0; q < N2; ++q) v[q] = base[(tau + N1 * q) ^ sz];
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act) {
             dft<N2, DIR>(v);
 #pragma unroll
@@ -224,7 +233,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
             for (int ka = 0; ka < N2; ++ka) base[(ka * N1 + (tau ^ (ka & (N1 - 1)))) ^ sz] = v[ka];
         }
-        __syncthreads();
+        wave_lds_sync();
         constexpr int B = N2 / N1;
         if (act) {
 #pragma unroll
@@ -232,7 +241,7 @@ __device__ __forceinline__ void fft_cols(C* lds, int ncols, const C* twl) {
 #pragma unroll
                 for (int t = 0; t < N1; ++t) v[b * N1 + t] = base[((tau + N1 * b) * N1 + (t ^ tau)) ^ sz];
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act) {
 #pragma unroll
             for (int b = 0; b < B; ++b) {
@@ -255,6 +264,29 @@ __device__ __forceinline__ void load_twiddles(C* twl, const C* tw) {
     }
 }
 
+// The same table staged in two steps: loads into registers first, the LDS
+// stores once the tile's own loads are in flight, so that the two memory
+// latencies overlap instead of adding up.  Loads are unconditional (clamped
+// index) so later waits stay exact.
+template <int L, int TH, typename C> struct Twiddles {
+    static constexpr int N = (L + TH - 1) / TH;
+    C v[N];
+    __device__ __forceinline__ void load(const C* tw, int tid) {
+        constexpr int N1 = Split<L>::N1;
+        sfor<0, N>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = ic;
+            const int j = tid + i * TH < L ? tid + i * TH : 0;
+            v[i] = ldg(tw + (j / N1) * (j % N1));
+        });
+    }
+    __device__ __forceinline__ void store(C* twl, int tid) const {
+        sfor<0, N>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = ic;
+            if (tid + i * TH < L) twl[tid + i * TH] = v[i];
+        });
+    }
+};
+
 template <typename C>
 __device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
     const double2 a = tw64[ax.sp_off1 + (j % ax.spB)];
@@ -271,30 +303,6 @@ template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
 template <typename T> __device__ __forceinline__ T* smem() {
     extern __shared__ __align__(16) unsigned char ahom_fast_smem[];
     return reinterpret_cast<T*>(ahom_fast_smem);
-}
-
-// fixed-order block sum of NV doubles (result in thread 0): butterfly sums
-// inside each 64-lane wavefront, then the per-wave sums in wave order.
-// scratch: NV * (blockDim / 64) doubles.
-template <int NV>
-__device__ void block_sum(double* vals, double* scratch) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = (blockDim.x + 63) >> 6;
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        double v = vals[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        vals[c] = v;
-    }
-    if (lane == 0)
-        for (int c = 0; c < NV; ++c) scratch[c * nw + wave] = vals[c];
-    __syncthreads();
-    if (tid == 0)
-        for (int c = 0; c < NV; ++c) {
-            double acc = 0.0;
-            for (int w = 0; w < nw; ++w) acc += scratch[c * nw + w];
-            vals[c] = acc;
-        }
 }
 
 // Tile of schedule slot t (of n).  Workgroups are dealt to the 8 XCDs
@@ -343,109 +351,158 @@ __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_
 // LDS work.  Partial sums are written per (load, tile) and reduced in a
 // fixed order.
 
+// Value of a wave-uniform quantity kept in a scalar register, so that the
+// loads it addresses (load states, plan fields) are scalar loads and never
+// enter the vector-memory wait counter.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // =============================================================================
 // real-space turnaround along axis 0
+//
+// Variants 0/1 run one tile per workgroup.  The persistent variants (2/3) run
+// a software pipeline over the workgroup's tiles: while tile t is in its
+// transforms and local law (LDS and registers only), the loads of tile t+1
+// and the stores of tile t-1 are in flight.  A wave's counter of outstanding
+// vector-memory operations covers loads and stores alike, and with both kinds
+// in flight any wait on one of them waits for all; so nothing waits on global
+// memory between the packing of a tile and the next packing: the law reads
+// its Lame pairs from a copy of the phase table in LDS, and the stress sums
+// go through LDS.  (Per-point Lame fields are read in the law directly: a
+// slower path.)
 // =============================================================================
 template <typename T, int DIM, int L, int V>
 __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_real(RealArgs a) {
     using C = typename CT<T>::t;
     constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
     using G = Geo<T, L, NP, V>;
-    constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1, TH = G::THREADS;
+    constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1, TH = G::THREADS, NW = TH / 64;
     constexpr int EPT = (H * NC + TH - 1) / TH;     // half-spectrum rows per thread
+    constexpr int EPL = (L * NC + TH - 1) / TH;     // law points per thread
+    constexpr int TWT = (L + TH - 1) / TH;          // twiddles per thread
+    constexpr int MTT = (2 * 256 + TH - 1) / TH;    // phase-table entries per thread (<= 256 phases)
     const Plan& P = *a.plan;
     const AxisDesc& ax = P.ax[0];
     const int64_t I = P.S / H;
     const int64_t nct = (I + NC - 1) / NC;
     const int64_t total = nct * a.nload;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    const int wave = tid >> 6;
     C* Z = smem<C>();
     C* twl = Z + G::TILE;
-    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
+    double* red = reinterpret_cast<double*>(twl + L);   // [NCOMP][NW] per-wave stress sums
+    T* mat = reinterpret_cast<T*>(red + NCOMP * NW);     // [n_phase][2] Lame pairs
+    const bool table = a.lame_pts_t == nullptr;
     const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
 
+    // twiddles and phase table: loaded into registers, written to LDS once
+    C twv[TWT];
+    T mtv[MTT];
+    auto load_tables = [&]() __attribute__((always_inline)) {
+        const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
+        sfor<0, TWT>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = ic;
+            const int j = tid + i * TH < L ? tid + i * TH : 0;
+            twv[i] = ldg(tw + (j / Split<L>::N1) * (j % Split<L>::N1));
+        });
+        if (table) {
+            sfor<0, MTT>([&](auto ic) __attribute__((always_inline)) {
+                constexpr int i = ic;
+                const int j = tid + i * TH < 2 * a.n_phase ? tid + i * TH : 0;
+                mtv[i] = (T)a.lame_tab[j];
+            });
+        }
+    };
+    auto store_tables = [&]() __attribute__((always_inline)) {
+        sfor<0, TWT>([&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = ic;
+            if (tid + i * TH < L) twl[tid + i * TH] = twv[i];
+        });
+        if (table) {
+            sfor<0, MTT>([&](auto ic) __attribute__((always_inline)) {
+                constexpr int i = ic;
+                if (tid + i * TH < 2 * a.n_phase) mat[tid + i * TH] = mtv[i];
+            });
+        }
+    };
+
+    // A tile: load case, first column, columns, buffer parity of the iterate.
+    struct Tile { int load, ncol, par; int64_t c0, ct; };
+    auto tile_of = [&](int64_t t) __attribute__((always_inline)) -> Tile {
+        Tile x;
+        x.load = uni((int)(t / nct));
+        x.ct = uni(t % nct);
+        x.c0 = x.ct * NC;
+        x.ncol = (int)((I - x.c0) < NC ? (I - x.c0) : NC);
+        x.par = a.st[x.load].iter & 1;
+        return x;
+    };
+
+    // Loads of a tile, phase ids first, then the spectra.  All loads are
+    // issued unconditionally, out-of-tile slots clamped to an in-bounds
+    // address (values unused), so the compiler's waits stay exact.
     C pre[EPT][NCOMP];
-    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
-        const int load = (int)(t / nct);
-        const int64_t c0 = (t % nct) * NC;
-        const LoadState& st = a.st[load];
-        if (st.done) return false;
-        const C* src = reinterpret_cast<const C*>((st.iter & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+    uint8_t phq[EPL];
+    auto fetch_loads = [&](const Tile& x) __attribute__((always_inline)) {
+        if (table) {
+            sfor<0, EPL>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int j = e / L, n = e % L;
+                const bool ok = e < L * NC && j < x.ncol;
+                phq[q] = a.phase_t[ok ? (x.c0 + j) * (int64_t)L + n : x.c0 * (int64_t)L];
+            });
+        }
+        // per field a uniform base and one 32-bit byte offset per slot (the
+        // scalar-base addressing form: no 64-bit address per load)
+        const C* src = reinterpret_cast<const C*>(x.par ? a.buf1 : a.buf0) + (int64_t)x.load * NCOMP * P.S;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const int k = e < H * NC ? e / NC : H - 1;
+            const int j = e % NC < x.ncol ? e % NC : 0;
+            const uint32_t off = (uint32_t)(((int64_t)k * I + x.c0 + j) * (int64_t)sizeof(C));
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                pre[q][f] = ldg(reinterpret_cast<const C*>(reinterpret_cast<const char*>(src + (int64_t)f * P.S) + off));
+            });
+        });
+    };
+
+    // packed full spectra Z_p = A + i B from the half spectra in pre[]
+    auto pack = [&](const Tile& x) __attribute__((always_inline)) {
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
             const int k = e / NC, j = e % NC;
-            if (e < H * NC && c0 + j < I) {
-                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
-                    constexpr int f = fc;
-                    pre[q][f] = ldg(src + (int64_t)f * P.S + (int64_t)k * I + c0 + j);
-                });
-            }
+            if (e >= H * NC || j >= x.ncol) return;
+            C w = C{(T)1, (T)0};
+            if (ax.split) w = split_twiddle<C>(ax, a.tw64, ((x.c0 + j) / ax.qdiv) * (int64_t)k);
+            sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+                constexpr int p = pc;
+                C A = pre[q][2 * p];
+                C B = C{(T)0, (T)0};
+                if constexpr (2 * p + 1 < NCOMP) B = pre[q][2 * p + 1];
+                if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
+                if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
+                C* Zp = Z + (p * NC + j) * CS;
+                const int sz = lsw<L, C>(p * NC + j);
+                Zp[k ^ sz] = C{A.x - B.y, A.y + B.x};
+                if (k > 0 && 2 * k != L) Zp[(L - k) ^ sz] = C{A.x + B.y, B.x - A.y};
+            });
         });
-        return true;
     };
 
-    int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
-    for (; t < total; t += gridDim.x) {
-        const bool cur = have;
-        const int64_t tt = xcd_tile(t, total);
-        const int load = (int)(tt / nct);
-        const int64_t c0 = (tt % nct) * NC;
-        const int ncol = (int)((I - c0) < NC ? (I - c0) : NC);
-        if (cur) {
-            // packed full spectra Z_p = A + i B from the half spectra
-            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
-                constexpr int q = qc;
-                const int e = tid + q * TH;
-                const int k = e / NC, j = e % NC;
-                if (e >= H * NC || j >= ncol) return;
-                C w = C{(T)1, (T)0};
-                if (ax.split) w = split_twiddle<C>(ax, a.tw64, ((c0 + j) / ax.qdiv) * (int64_t)k);
-                sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
-                    constexpr int p = pc;
-                    C A = pre[q][2 * p];
-                    C B = C{(T)0, (T)0};
-                    if constexpr (2 * p + 1 < NCOMP) B = pre[q][2 * p + 1];
-                    if (ax.split) { A = cmulc(A, w); B = cmulc(B, w); }
-                    if (k == 0 || 2 * k == L) { A.y = 0; B.y = 0; }
-                    C* Zp = Z + (p * NC + j) * CS;
-                    const int sz = lsw<L, C>(p * NC + j);
-                    Zp[k ^ sz] = C{A.x - B.y, A.y + B.x};
-                    if (k > 0 && 2 * k != L) Zp[(L - k) ^ sz] = C{A.x + B.y, B.x - A.y};
-                });
-            });
-        }
-        __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
-        else have = false;
-        if (!cur) {
-            if constexpr (!G::PERSIST) break;
-            continue;
-        }
-        const LoadState& st = a.st[load];
-        C* dst = reinterpret_cast<C*>((st.iter & 1) ? a.buf0 : a.buf1) + (int64_t)load * NCOMP * P.S;
-        fft_cols<L, +1, CS>(Z, NP * NC, twl);
-
+    // local law on the tile in LDS; per-wave stress sums into red[]
+    auto law = [&](const Tile& x, const uint8_t (&ph)[EPL]) __attribute__((always_inline)) {
         double sig[NCOMP];
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
-        for (int e = tid; e < L * NC; e += TH) {
-            // material arrays are stored column-major for this pass: one
-            // contiguous block of NC * L entries per tile
-            const int j = e / L, n = e % L;
-            if (j >= ncol) continue;
-            const int64_t pt_t = (c0 + j) * (int64_t)L + n;
-            T lam, mu;
-            if (a.lame_pts_t) {
-                lam = (T)a.lame_pts_t[2 * pt_t];
-                mu = (T)a.lame_pts_t[2 * pt_t + 1];
-            } else {
-                const int ph = a.phase_t[pt_t];
-                lam = (T)a.lame_tab[2 * ph];
-                mu = (T)a.lame_tab[2 * ph + 1];
-            }
+        auto point = [&](int j, int n, T lam, T mu) __attribute__((always_inline)) {
             T eps[NCOMP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -465,35 +522,150 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
 #pragma unroll
             for (int p = 0; p < NP; ++p)
                 Z[(p * NC + j) * CS + (n ^ lsw<L, C>(p * NC + j))] = C{tau[2 * p], 2 * p + 1 < NCOMP ? tau[2 * p + 1] : (T)0};
+        };
+        // material arrays are stored column-major for this pass: one
+        // contiguous block of NC * L entries per tile.  The two material paths
+        // are separate loops, so the global loads of the per-point path are
+        // waited for inside its own branch.
+        if (table) {
+            sfor<0, EPL>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int j = e / L, n = e % L;
+                if (e >= L * NC || j >= x.ncol) return;
+                point(j, n, mat[2 * ph[q]], mat[2 * ph[q] + 1]);
+            });
+        } else {
+            sfor<0, EPL>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int j = e / L, n = e % L;
+                if (e >= L * NC || j >= x.ncol) return;
+                const int64_t pt_t = (x.c0 + j) * (int64_t)L + n;
+                point(j, n, (T)a.lame_pts_t[2 * pt_t], (T)a.lame_pts_t[2 * pt_t + 1]);
+            });
         }
-        __syncthreads();
-        fft_cols<L, -1, CS>(Z, NP * NC, twl);
-
-        for (int e = tid; e < H * NC; e += TH) {
-            const int k = e / NC, j = e % NC;
-            if (j >= ncol) continue;
-            const int64_t col = c0 + j;
-            C w = C{(T)1, (T)0};
-            if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
-            const int km = k == 0 ? 0 : L - k;
+        // fixed-order butterfly sums inside the wave, one entry per wave
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
+        for (int c = 0; c < NCOMP; ++c) {
+            double v = sig[c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            sig[c] = v;
+        }
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) red[c * NW + wave] = sig[c];
+    };
+    // tile's stress partial from the per-wave sums (thread 0, waves in order)
+    auto write_sig = [&](const Tile& x) __attribute__((always_inline)) {
+        if (tid == 0)
+            for (int c = 0; c < NCOMP; ++c) {
+                double acc = 0.0;
+                for (int w = 0; w < NW; ++w) acc += red[c * NW + w];
+                a.sig_part[((int64_t)x.load * nct + x.ct) * NCOMP + c] = acc;
+            }
+    };
+
+    // half spectra of the transformed tile into out[]
+    C out[EPT][NCOMP];
+    auto unpack = [&](const Tile& x) __attribute__((always_inline)) {
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const bool ok = e < H * NC && e % NC < x.ncol;
+            const int k = ok ? e / NC : 0, j = e % NC;
+            C w = C{(T)1, (T)0};
+            if (ax.split && ok) w = split_twiddle<C>(ax, a.tw64, ((x.c0 + j) / ax.qdiv) * (int64_t)k);
+            const int km = k == 0 ? 0 : L - k;
+            sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
+                constexpr int p = pc;
                 const C* Zp = Z + (p * NC + j) * CS;
                 const int sz = lsw<L, C>(p * NC + j);
                 const C zk = Zp[k ^ sz], zm = Zp[km ^ sz];
                 C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
                 C B = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
                 if (ax.split) { A = cmul(A, w); B = cmul(B, w); }
-                stg(dst + (int64_t)(2 * p) * P.S + (int64_t)k * I + col, A);
-                if (2 * p + 1 < NCOMP) stg(dst + (int64_t)(2 * p + 1) * P.S + (int64_t)k * I + col, B);
+                out[q][2 * p] = A;
+                if constexpr (2 * p + 1 < NCOMP) out[q][2 * p + 1] = B;
+            });
+        });
+    };
+    auto store = [&](const Tile& x) __attribute__((always_inline)) {
+        C* dst = reinterpret_cast<C*>(x.par ? a.buf0 : a.buf1) + (int64_t)x.load * NCOMP * P.S;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const int k = e / NC, j = e % NC;
+            if (e >= H * NC || j >= x.ncol) return;
+            const uint32_t off = (uint32_t)(((int64_t)k * I + x.c0 + j) * (int64_t)sizeof(C));
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                stg(reinterpret_cast<C*>(reinterpret_cast<char*>(dst + (int64_t)f * P.S) + off), out[q][f]);
+            });
+        });
+    };
+
+    int64_t t = blockIdx.x;
+    if constexpr (!G::PERSIST) {
+        // one tile per workgroup; a workgroup without work leaves at once
+        if (t >= total) return;
+        const Tile x = tile_of(xcd_tile(t, total));
+        if (a.st[x.load].done) return;
+        load_tables();
+        fetch_loads(x);
+        store_tables();                 // waits for the table loads only
+        pack(x);
+        __syncthreads();
+        fft_cols<L, +1, CS>(Z, NP * NC, twl);
+        law(x, phq);
+        __syncthreads();
+        write_sig(x);
+        fft_cols<L, -1, CS>(Z, NP * NC, twl);
+        unpack(x);
+        store(x);
+    } else {
+        load_tables();
+        store_tables();
+        Tile x = t < total ? tile_of(xcd_tile(t, total)) : Tile{0, 0, 0, 0, 0};
+        bool have = t < total && !a.st[x.load].done;
+        if (have) fetch_loads(x);
+        Tile prev = x;
+        bool pend = false;
+        uint8_t phc[EPL];
+        for (; t < total; t += gridDim.x) {
+            // a fresh (opaque) copy of the thread index per tile: keeps the
+            // per-thread LDS offsets from being hoisted out of the loop and
+            // held in registers across all stages
+            asm volatile("" : "=v"(tid) : "0"(tid));
+            const bool cur = have;
+            if (cur) {
+                pack(x);
+                sfor<0, EPL>([&](auto qc) __attribute__((always_inline)) { phc[qc] = phq[qc]; });
             }
+            __syncthreads();
+            if (pend) store(prev);      // tile t-1, in flight during this tile's work
+            pend = false;
+            const Tile xc = x;
+            const int64_t tn = t + gridDim.x;
+            have = false;
+            if (tn < total) {
+                x = tile_of(xcd_tile(tn, total));
+                have = !a.st[x.load].done;
+                if (have) fetch_loads(x);   // tile t+1, in flight during this tile's work
+            }
+            if (!cur) continue;
+            fft_cols<L, +1, CS>(Z, NP * NC, twl, tid);
+            law(xc, phc);
+            __syncthreads();
+            write_sig(xc);
+            fft_cols<L, -1, CS>(Z, NP * NC, twl, tid);
+            unpack(xc);
+            __syncthreads();            // the tile is read out: LDS free for the next packing
+            prev = xc;
+            pend = true;
         }
-        __syncthreads();
-        block_sum<NCOMP>(sig, reinterpret_cast<double*>(Z));
-        if (tid == 0)
-            for (int c = 0; c < NCOMP; ++c) a.sig_part[((int64_t)load * nct + tt % nct) * NCOMP + c] = sig[c];
-        __syncthreads();
-        if constexpr (!G::PERSIST) break;  // one tile per workgroup
+        if (pend) store(prev);
     }
 }
 
@@ -511,13 +683,6 @@ template <typename T, int L> struct RR {
     static constexpr int CS = L + 1;
     static constexpr int REGION = NCW * CS;  // complex elements of one wave's LDS region
 };
-
-// LDS stores of this wave visible to its later loads (no other wave involved)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // FFT of one column held by the N1 threads tau of it: v[q] = x[tau + N1 q] in,
 // v[b N1 + kb] = X[tau + N1 b + N2 kb] out; base = the column's LDS region.
@@ -712,7 +877,8 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
     const int tid = threadIdx.x;
     C* X = smem<C>();
     C* twl = X + G::TILE;
-    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + ax.tw_off);
+    Twiddles<L, TH, C> twr;
+    twr.load(reinterpret_cast<const C*>(a.tw) + ax.tw_off, tid);
 
     // element e of a tile -> (column j, position l)
     auto map = [&](int e, int& j, int& l) __attribute__((always_inline)) {
@@ -745,9 +911,11 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             const int j = tid % NC, l0 = tid / NC;
             const C* p0 = base + (c0 / I) * (int64_t)L * I + (c0 % I) + j + (int64_t)l0 * I;
             const int64_t step = (int64_t)(TH / NC) * I;
+            // unconditional loads, out-of-tile slots clamped to the first
+            // position (values unused): keeps later waits on older loads exact
             sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
                 constexpr int q = qc;
-                if (tid + q * TH < NC * L) pre[q] = ldg(p0 + q * step);
+                pre[q] = ldg(tid + q * TH < NC * L ? p0 + q * step : p0);
             });
             return true;
         }
@@ -757,13 +925,24 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             const int e = tid + q * TH;
             int j, l;
             map(e, j, l);
-            if (e < NC * L && c0 + j < ncols) pre[q] = ldg(base + addr(c0, cb, j, l));
+            if (!(e < NC * L && c0 + j < ncols)) { j = 0; l = 0; }
+            pre[q] = ldg(base + addr(c0, cb, j, l));
         });
         return true;
     };
 
     int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
+    bool have;
+    if constexpr (!G::PERSIST) {
+        // one tile per workgroup: a workgroup without work leaves here, so the
+        // tile's loads lie on the only path below (exact load waits)
+        if (t >= total || !fetch(xcd_tile(t, total))) return;
+        have = true;
+        twr.store(twl, tid);
+    } else {
+        twr.store(twl, tid);
+        have = t < total ? fetch(xcd_tile(t, total)) : false;
+    }
     for (; t < total; t += gridDim.x) {
         const bool cur = have;
         int load;
@@ -821,10 +1000,13 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     const int64_t nct = (ncols + NC - 1) / NC;
     const int64_t total = nct * a.nload;
     const int tid = threadIdx.x;
+    constexpr int NW = TH / 64;
     C* F = smem<C>();
     C* twl = F + G::TILE;
     int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
-    load_twiddles<L>(twl, reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off);
+    double* red = reinterpret_cast<double*>(kb + NC * 4); // [NW] per-wave residual sums
+    Twiddles<L, TH, C> twr;
+    twr.load(reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, tid);
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
     const int last_snf = P.ax[D - 1].snf;
@@ -837,22 +1019,32 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         const LoadState& st = a.st[load];
         if (st.done) return false;
         const C* base = reinterpret_cast<const C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        // unconditional loads, out-of-tile slots clamped to the tile's first
+        // element (values unused): keeps later waits on older loads exact
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
-            if (e < NC * L && c0 + e / L < ncols) {
-                const int64_t addr = c0 * L + e;
-                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
-                    constexpr int f = fc;
-                    pre[q][f] = ldg(base + (int64_t)f * P.S + addr);
-                });
-            }
+            const int64_t addr = c0 * L + ((e < NC * L && c0 + e / L < ncols) ? e : 0);
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                pre[q][f] = ldg(base + (int64_t)f * P.S + addr);
+            });
         });
         return true;
     };
 
     int64_t t = blockIdx.x;
-    bool have = t < total ? fetch(xcd_tile(t, total)) : false;
+    bool have;
+    if constexpr (!G::PERSIST) {
+        // one tile per workgroup: a workgroup without work leaves here, so the
+        // tile's loads lie on the only path below (exact load waits)
+        if (t >= total || !fetch(xcd_tile(t, total))) return;
+        have = true;
+        twr.store(twl, tid);
+    } else {
+        twr.store(twl, tid);
+        have = t < total ? fetch(xcd_tile(t, total)) : false;
+    }
     for (; t < total; t += gridDim.x) {
         const bool cur = have;
         const int64_t tt = xcd_tile(t, total);
@@ -903,18 +1095,36 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
         const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
         const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
-        // previous traction of this tile: in flight during the forward transform
+        // previous traction of this tile (and, in FP32, the restart's traction
+        // offset): in flight during the forward transform
+        constexpr bool HOIST_OFF = sizeof(T) == 4;
         C oldv[EPT][NT];
-        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
-            constexpr int q = qc;
-            const int e = tid + q * TH;
-            if (chk && e < NC * L && c0 + e / L < ncols) {
+        C offv[HOIST_OFF ? EPT : 1][NT];
+        const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
+        if (chk) {
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int64_t addr = c0 * L + ((e < NC * L && c0 + e / L < ncols) ? e : 0);
                 sfor<0, NT>([&](auto cc) __attribute__((always_inline)) {
                     constexpr int c = cc;
-                    oldv[q][c] = ldg(tb + (int64_t)c * P.S + c0 * L + e);
+                    oldv[q][c] = ldg(tb + (int64_t)c * P.S + addr);
+                });
+            });
+        }
+        if constexpr (HOIST_OFF) {
+            if (a.toff) {
+                sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                    constexpr int q = qc;
+                    const int e = tid + q * TH;
+                    const int64_t addr = c0 * L + ((e < NC * L && c0 + e / L < ncols) ? e : 0);
+                    sfor<0, NT>([&](auto cc) __attribute__((always_inline)) {
+                        constexpr int c = cc;
+                        offv[q][c] = ldg(to + (int64_t)c * P.S + addr);
+                    });
                 });
             }
-        });
+        }
         fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
 
         const double* eb = a.eps_bar + (int64_t)load * NCOMP;
@@ -990,10 +1200,11 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 for (int c = 0; c < NT; ++c) stg(tb + (int64_t)c * P.S + spos, tt[c]);
             }
             if (a.toff) {
-                const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
-                    const C o = ldg(to + (int64_t)c * P.S + spos);
+                    C o;
+                    if constexpr (HOIST_OFF) o = offv[q][c];
+                    else o = ldg(to + (int64_t)c * P.S + spos);
                     tt[c] = C{tt[c].x + o.x, tt[c].y + o.y};
                 }
             }
@@ -1017,7 +1228,16 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
             }
         });
+        // fixed-order residual sum: butterfly inside the wave, waves in order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) res += __shfl_xor(res, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = res;
         __syncthreads();
+        if (tid == 0) {
+            double acc = 0.0;
+            for (int w = 0; w < NW; ++w) acc += red[w];
+            a.res_part[(int64_t)load * nct + tt % nct] = acc;
+        }
         fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
         for (int e = tid; e < L * NC; e += TH) {
             const int j = e / L;
@@ -1027,12 +1247,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
 #pragma unroll
             for (int f = 0; f < NCOMP; ++f) stg(base + (int64_t)f * P.S + addr, F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))]);
         }
-        __syncthreads();
-        double rv[1] = {res};
-        block_sum<1>(rv, reinterpret_cast<double*>(F));
-        if (tid == 0) a.res_part[(int64_t)load * nct + tt % nct] = rv[0];
-        __syncthreads();
         if constexpr (!G::PERSIST) break;  // one tile per workgroup
+        __syncthreads();                   // LDS free for the next tile
     }
 }
 
@@ -1050,11 +1266,13 @@ FastGeom geom_of(int kind) {
     g.NC = G::NC;
     g.threads = G::THREADS;
     g.persistent = G::PERSIST;
-    // tile + twiddles + per-column integers (spec: kappa + weight)
-    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * 32 : 0;
+    // tile + twiddles + per-column integers (spec: kappa + weight) or
+    // per-wave stress sums (real; the phase table is added at launch)
+    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * 32 + (size_t)(G::THREADS / 64) * 8
+                                     : (kind == FAST_REAL ? (size_t)6 * (G::THREADS / 64) * 8 : 0);
     size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
-    // block reduction reuses the tile: NV doubles per thread
-    const size_t red = (size_t)G::THREADS * 8 * (kind == FAST_REAL ? 6 : 1);
+    // block reduction of the other passes reuses the tile: one double per thread
+    const size_t red = (size_t)G::THREADS * 8;
     g.lds = lds > red ? lds : red;
     return g;
 }
@@ -1106,6 +1324,9 @@ template <typename T, int V>
 int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
     if (!geom_TV<T, V>(FAST_REAL, dim, L, &g)) return -1;
+    // the phase table (Lame pairs in the working precision) follows in LDS
+    if (!a.lame_pts_t && (a.n_phase < 1 || a.n_phase > 256 || !a.lame_tab)) return -1;
+    if (!a.lame_pts_t) g.lds += (size_t)a.n_phase * 2 * sizeof(T);
 #define AHOM_FR(LL)                                                                    \
     case LL:                                                                           \
         return dim == 3 ? go(kf_real<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \

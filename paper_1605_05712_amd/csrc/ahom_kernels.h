@@ -40,6 +40,7 @@ struct RealArgs {
     int NC, CS;
     int nload;                // fast path: load cases covered by the persistent grid
     int accumulate;           // TO_REAL: add to real_io instead of overwriting it
+    int n_phase;              // entries of lame_tab (fast path stages them in LDS)
 };
 
 struct AxisArgs {
