@@ -1012,96 +1012,16 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     const int last_snf = P.ax[D - 1].snf;
     const int64_t last_mult = P.ax[D - 1].mult;
 
-    C pre[EPT][NCOMP];
-    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
-        const int load = (int)(t / nct);
-        const int64_t c0 = (t % nct) * NC;
-        const LoadState& st = a.st[load];
-        if (st.done) return false;
-        const C* base = reinterpret_cast<const C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
-        // unconditional loads, out-of-tile slots clamped to the tile's first
-        // element (values unused): keeps later waits on older loads exact
-        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
-            constexpr int q = qc;
-            const int e = tid + q * TH;
-            const int64_t addr = c0 * L + ((e < NC * L && c0 + e / L < ncols) ? e : 0);
-            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
-                constexpr int f = fc;
-                pre[q][f] = ldg(base + (int64_t)f * P.S + addr);
-            });
-        });
-        return true;
-    };
-
-    int64_t t = blockIdx.x;
-    bool have;
-    if constexpr (!G::PERSIST) {
-        // one tile per workgroup: a workgroup without work leaves here, so the
-        // tile's loads lie on the only path below (exact load waits)
-        if (t >= total || !fetch(xcd_tile(t, total))) return;
-        have = true;
-        twr.store(twl, tid);
-    } else {
-        twr.store(twl, tid);
-        have = t < total ? fetch(xcd_tile(t, total)) : false;
-    }
-    for (; t < total; t += gridDim.x) {
-        const bool cur = have;
-        const int64_t tt = xcd_tile(t, total);
-        const int load = (int)(tt / nct);
-        const int64_t c0 = (tt % nct) * NC;
-        const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
-        if (cur) {
-            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
-                constexpr int q = qc;
-                const int e = tid + q * TH;
-                const int j = e / L, l = e % L;
-                if (e >= NC * L || j >= ncol) return;
-                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
-                    constexpr int f = fc;
-                    F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))] = pre[q][f];
-                });
-            });
-            if (tid < NC) {
-                int64_t o = c0 + tid;
-                int64_t k0 = 0, kq0 = 0, kq1 = 0, kq2 = 0;
-                for (int b = D - 2; b >= 0; --b) {
-                    const int64_t sl = P.ax[b].slen;
-                    const int64_t kk = o % sl;
-                    o /= sl;
-                    const int64_t v = P.ax[b].mult * kk;
-                    const int sn = P.ax[b].snf;
-                    kq0 += sn == 0 ? v : 0;
-                    kq1 += sn == 1 ? v : 0;
-                    kq2 += sn == 2 ? v : 0;
-                    if (b == 0) k0 = kk;
-                }
-                kb[tid * 4 + 0] = kq0;
-                kb[tid * 4 + 1] = kq1;
-                kb[tid * 4 + 2] = kq2;
-                kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
-            }
-        }
-        __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
-        else have = false;
-        if (!cur) {
-            if constexpr (!G::PERSIST) break;
-            continue;
-        }
-        const LoadState& st = a.st[load];
-        C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
-        C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
-        const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
-        const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
-        // previous traction of this tile (and, in FP32, the restart's traction
-        // offset): in flight during the forward transform
-        constexpr bool HOIST_OFF = sizeof(T) == 4;
-        C oldv[EPT][NT];
-        C offv[HOIST_OFF ? EPT : 1][NT];
+    // previous traction of a tile (and, in FP32, the restart's traction
+    // offset): the one-tile variants fetch them with the tile's spectra, the
+    // persistent ones after packing (in flight during the forward transform)
+    constexpr bool HOIST_OFF = sizeof(T) == 4;
+    C oldv[EPT][NT];
+    C offv[HOIST_OFF ? EPT : 1][NT];
+    auto load_old = [&](int load, int64_t c0, int iter) __attribute__((always_inline)) {
+        const C* tb = reinterpret_cast<const C*>(a.tbuf) + (int64_t)load * NT * P.S;
         const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
-        if (chk) {
+        if (ahom_check_iter(iter, a.resid_period, a.max_iter)) {
             sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
                 constexpr int q = qc;
                 const int e = tid + q * TH;
@@ -1125,6 +1045,107 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 });
             }
         }
+    };
+
+    C pre[EPT][NCOMP];
+    auto fetch = [&](int64_t t) __attribute__((always_inline)) -> bool {
+        const int load = (int)(t / nct);
+        const int64_t c0 = (t % nct) * NC;
+        const LoadState& st = a.st[load];
+        if (st.done) return false;
+        const C* base = reinterpret_cast<const C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        // unconditional loads, out-of-tile slots clamped to the tile's first
+        // element (values unused): keeps later waits on older loads exact
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const int64_t addr = c0 * L + ((e < NC * L && c0 + e / L < ncols) ? e : 0);
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                pre[q][f] = ldg(base + (int64_t)f * P.S + addr);
+            });
+        });
+        if constexpr (!G::PERSIST) load_old(load, c0, st.iter);
+        return true;
+    };
+
+    int64_t t = blockIdx.x;
+    bool have;
+    if constexpr (!G::PERSIST) {
+        // one tile per workgroup: a workgroup without work leaves here, so the
+        // tile's loads lie on the only path below (exact load waits)
+        if (t >= total || !fetch(xcd_tile(t, total))) return;
+        have = true;
+        twr.store(twl, tid);
+    } else {
+        twr.store(twl, tid);
+        have = t < total ? fetch(xcd_tile(t, total)) : false;
+    }
+    for (; t < total; t += gridDim.x) {
+        const bool cur = have;
+        const int64_t tt = xcd_tile(t, total);
+        const int load = (int)(tt / nct);
+        const int64_t c0 = (tt % nct) * NC;
+        const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+        if (cur) {
+            // per-column Smith indices of the other axes (while the tile's
+            // loads are in flight); 32-bit division where the column count fits
+            if (tid < NC) {
+                int64_t k0 = 0, kq0 = 0, kq1 = 0, kq2 = 0;
+                auto acc = [&](int b, int64_t kk) __attribute__((always_inline)) {
+                    const int64_t v = P.ax[b].mult * kk;
+                    const int sn = P.ax[b].snf;
+                    kq0 += sn == 0 ? v : 0;
+                    kq1 += sn == 1 ? v : 0;
+                    kq2 += sn == 2 ? v : 0;
+                    if (b == 0) k0 = kk;
+                };
+                if (ncols < (int64_t(1) << 31)) {
+                    uint32_t o = (uint32_t)(c0 + tid);
+                    for (int b = D - 2; b >= 0; --b) {
+                        const uint32_t sl = (uint32_t)P.ax[b].slen;
+                        acc(b, (int64_t)(o % sl));
+                        o /= sl;
+                    }
+                } else {
+                    int64_t o = c0 + tid;
+                    for (int b = D - 2; b >= 0; --b) {
+                        const int64_t sl = P.ax[b].slen;
+                        acc(b, o % sl);
+                        o /= sl;
+                    }
+                }
+                kb[tid * 4 + 0] = kq0;
+                kb[tid * 4 + 1] = kq1;
+                kb[tid * 4 + 2] = kq2;
+                kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
+            }
+            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+                constexpr int q = qc;
+                const int e = tid + q * TH;
+                const int j = e / L, l = e % L;
+                if (e >= NC * L || j >= ncol) return;
+                sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                    constexpr int f = fc;
+                    F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))] = pre[q][f];
+                });
+            });
+        }
+        __syncthreads();
+        const int64_t tn = t + gridDim.x;
+        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
+        else have = false;
+        if (!cur) {
+            if constexpr (!G::PERSIST) break;
+            continue;
+        }
+        const LoadState& st = a.st[load];
+        C* base = reinterpret_cast<C*>(((st.iter + 1) & 1) ? a.buf1 : a.buf0) + (int64_t)load * NCOMP * P.S;
+        C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
+        const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
+        const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
+        const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
+        if constexpr (G::PERSIST) load_old(load, c0, st.iter);
         fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
 
         const double* eb = a.eps_bar + (int64_t)load * NCOMP;
