@@ -315,6 +315,19 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t t, int64_t n) {
     return x * per + (x < rem ? x : rem) + i;
 }
 
+// Self-conjugate class test 2 kappa = 0 (mod e) per Smith axis.  The pass
+// kernels enumerate reduced indices 0 <= kappa_s < e_s, for which the test is
+// 2 kappa_s in {0, e_s}: no 64-bit division (kept as a fallback otherwise).
+__device__ __forceinline__ bool self_conjugate(const FreqMap& f, const int64_t* kap, int dim) {
+    bool ok = true;
+    for (int s = 0; s < dim; ++s) {
+        const int64_t k2 = 2 * kap[s], e = f.e[s];
+        if (kap[s] >= 0 && kap[s] < e) ok = ok && (k2 == 0 || k2 == e);
+        else ok = ok && (k2 % e == 0);
+    }
+    return ok;
+}
+
 // exact (A kappa) mod emax, centred; double path while products stay below 2^53
 __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_t* kap, int64_t* N, int dim) {
     int half = 0;
@@ -1004,13 +1017,44 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     C* F = smem<C>();
     C* twl = F + G::TILE;
     int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
-    double* red = reinterpret_cast<double*>(kb + NC * 4); // [NW] per-wave residual sums
+    double* nbd = reinterpret_cast<double*>(kb + NC * 4); // [NC][3]: base numerators (exact doubles)
+    double* red = nbd + NC * 3;                           // [NW] per-wave residual sums
     Twiddles<L, TH, C> twr;
     twr.load(reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, tid);
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
     const int last_snf = P.ax[D - 1].snf;
     const int64_t last_mult = P.ax[D - 1].mult;
+    // Along a column only the last axis moves: kappa = kappa_b + l mult u_snf,
+    // so the centred numerators are (A kappa_b + l A u mult) mod emax.  With
+    // emax <= 2^24 every term is an integer below 2^53 and the reduction in
+    // doubles is exact (the same integers as the plain 64-bit formula).
+    // (A has entries in [0, emax) and mult < e_s <= emax, so every product
+    // below is an integer < 2^48 and sums of three stay < 2^53.)
+    const int64_t emax = P.fm.emax;
+    const bool nfast = emax <= (int64_t(1) << 24);
+    const double emax_d = (double)emax, inv_e = 1.0 / emax_d;
+    auto dmod = [&](double x) __attribute__((always_inline)) -> double {   // x mod emax, x integer >= 0
+        double r = x - floor(x * inv_e) * emax_d;
+        if (r < 0) r += emax_d;
+        if (r >= emax_d) r -= emax_d;
+        return r;
+    };
+    double Ad[3][3], MTd[3][3], stepd[3];
+#pragma unroll
+    for (int i2 = 0; i2 < 3; ++i2)
+#pragma unroll
+        for (int r2 = 0; r2 < 3; ++r2) {
+            Ad[i2][r2] = (i2 < DIM && r2 < DIM) ? (double)P.fm.A[i2][r2] : 0.0;
+            MTd[i2][r2] = (i2 < DIM && r2 < DIM) ? (double)P.fm.MT[i2][r2] : 0.0;
+        }
+#pragma unroll
+    for (int i2 = 0; i2 < 3; ++i2) {
+        double a_s = 0.0;
+#pragma unroll
+        for (int r2 = 0; r2 < 3; ++r2) a_s = r2 == last_snf ? Ad[i2][r2] : a_s;
+        stepd[i2] = nfast ? dmod(a_s * (double)last_mult) : 0.0;
+    }
 
     // previous traction of a tile (and, in FP32, the restart's traction
     // offset): the one-tile variants fetch them with the tile's spectra, the
@@ -1119,6 +1163,16 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 kb[tid * 4 + 1] = kq1;
                 kb[tid * 4 + 2] = kq2;
                 kb[tid * 4 + 3] = (k0 == 0 || 2 * k0 == P.ax[0].len) ? 1 : 2;
+                if (nfast) {
+                    const double kq[3] = {(double)kq0, (double)kq1, (double)kq2};
+#pragma unroll
+                    for (int i2 = 0; i2 < DIM; ++i2) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int s2 = 0; s2 < DIM; ++s2) acc += Ad[i2][s2] * kq[s2];
+                        nbd[tid * 3 + i2] = dmod(acc);
+                    }
+                }
             }
             sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
                 constexpr int q = qc;
@@ -1166,9 +1220,23 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)eb[f], (T)0};
                 return;
             }
-            int64_t N[3];
-            const int half = centred_numerators(P.fm, kap, N, DIM);
-            if (half && !ahom_self_conjugate(P.fm, kap)) {
+            double Nd[3];
+            int half = 0;
+            if (nfast) {
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    double r = dmod(nbd[j * 3 + i] + (double)l * stepd[i]);
+                    if (2 * r >= emax_d) r -= emax_d;
+                    if (2 * r == -emax_d) half = 1;
+                    Nd[i] = r;
+                }
+            } else {
+                int64_t N[3];
+                half = centred_numerators(P.fm, kap, N, DIM);
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) Nd[i] = (double)N[i];
+            }
+            if (half && !self_conjugate(P.fm, kap, DIM)) {
 #pragma unroll
                 for (int f = 0; f < NCOMP; ++f) *fp[f] = C{(T)0, (T)0};
                 return;
@@ -1178,7 +1246,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
             for (int i = 0; i < DIM; ++i) {
                 hd[i] = 0.0;
 #pragma unroll
-                for (int r = 0; r < DIM; ++r) hd[i] += (double)P.fm.MT[i][r] * (double)N[r];
+                for (int r = 0; r < DIM; ++r) hd[i] += MTd[i][r] * Nd[r];
             }
             double hn = 0.0;
 #pragma unroll
@@ -1289,7 +1357,7 @@ FastGeom geom_of(int kind) {
     g.persistent = G::PERSIST;
     // tile + twiddles + per-column integers (spec: kappa + weight) or
     // per-wave stress sums (real; the phase table is added at launch)
-    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * 32 + (size_t)(G::THREADS / 64) * 8
+    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * (32 + 24) + (size_t)(G::THREADS / 64) * 8
                                      : (kind == FAST_REAL ? (size_t)6 * (G::THREADS / 64) * 8 : 0);
     size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
     // block reduction of the other passes reuses the tile: one double per thread
