@@ -305,6 +305,27 @@ template <typename T> __device__ __forceinline__ T* smem() {
     return reinterpret_cast<T*>(ahom_fast_smem);
 }
 
+// Fixed-order sum of a double over the 64 lanes of a wavefront with DPP lane
+// moves (VALU only, no LDS round trip): pairs, quads, half rows and rows by
+// mirrors, then rows 0+1 and 2+3 by the row-15 broadcast and all four by the
+// lane-31 broadcast.  The total is in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_step(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return v + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_lane63(double v) {
+    v = dpp_step<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v = dpp_step<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v = dpp_step<0x141, 0xf>(v);   // row_half_mirror
+    v = dpp_step<0x140, 0xf>(v);   // row_mirror
+    v = dpp_step<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_step<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Tile of schedule slot t (of n).  Workgroups are dealt to the 8 XCDs
 // round-robin (slot t runs on XCD t % 8); give each XCD a contiguous range of
 // tiles, so that tiles sharing HBM lines (neighbouring column blocks) meet in
@@ -558,15 +579,10 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
                 point(j, n, (T)a.lame_pts_t[2 * pt_t], (T)a.lame_pts_t[2 * pt_t + 1]);
             });
         }
-        // fixed-order butterfly sums inside the wave, one entry per wave
+        // fixed-order sums inside the wave, one entry per wave
 #pragma unroll
-        for (int c = 0; c < NCOMP; ++c) {
-            double v = sig[c];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            sig[c] = v;
-        }
-        if ((tid & 63) == 0)
+        for (int c = 0; c < NCOMP; ++c) sig[c] = wave_sum_lane63(sig[c]);
+        if ((tid & 63) == 63)
 #pragma unroll
             for (int c = 0; c < NCOMP; ++c) red[c * NW + wave] = sig[c];
     };
@@ -627,8 +643,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         if (a.st[x.load].done) return;
         load_tables();
         fetch_loads(x);
-        store_tables();                 // waits for the table loads only
         pack(x);
+        store_tables();                 // older than the tile's loads: no further wait
         __syncthreads();
         fft_cols<L, +1, CS>(Z, NP * NC, twl);
         law(x, phq);
@@ -951,7 +967,6 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
         // tile's loads lie on the only path below (exact load waits)
         if (t >= total || !fetch(xcd_tile(t, total))) return;
         have = true;
-        twr.store(twl, tid);
     } else {
         twr.store(twl, tid);
         have = t < total ? fetch(xcd_tile(t, total)) : false;
@@ -974,6 +989,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
                 X[j * CS + (l ^ lsw<L, C>(j))] = v;
             });
         }
+        if constexpr (!G::PERSIST) twr.store(twl, tid);   // older than the tile's loads
         __syncthreads();
         const int64_t tn = t + gridDim.x;
         if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
@@ -1120,7 +1136,6 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         // tile's loads lie on the only path below (exact load waits)
         if (t >= total || !fetch(xcd_tile(t, total))) return;
         have = true;
-        twr.store(twl, tid);
     } else {
         twr.store(twl, tid);
         have = t < total ? fetch(xcd_tile(t, total)) : false;
@@ -1185,6 +1200,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 });
             });
         }
+        if constexpr (!G::PERSIST) twr.store(twl, tid);   // older than the tile's loads
         __syncthreads();
         const int64_t tn = t + gridDim.x;
         if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
@@ -1317,10 +1333,9 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
             }
         });
-        // fixed-order residual sum: butterfly inside the wave, waves in order
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) res += __shfl_xor(res, off, 64);
-        if ((tid & 63) == 0) red[tid >> 6] = res;
+        // fixed-order residual sum: inside the wave, then waves in order
+        res = wave_sum_lane63(res);
+        if ((tid & 63) == 63) red[tid >> 6] = res;
         __syncthreads();
         if (tid == 0) {
             double acc = 0.0;
