@@ -903,7 +903,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
     const int64_t total = nct * a.nfield * a.nload;
     const bool rowmajor = I >= NC;
     const bool aligned = rowmajor && (I % NC) == 0;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
     C* X = smem<C>();
     C* twl = X + G::TILE;
     Twiddles<L, TH, C> twr;
@@ -960,56 +960,97 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
         return true;
     };
 
+    // transformed tile (LDS) -> out[] -> HBM; the persistent variants defer
+    // the stores of tile t until tile t+1 is packed (software pipeline: the
+    // loads of t+1 and the stores of t-1 are in flight during the transform
+    // of t, and the wait for the next tile's loads never waits for stores
+    // issued just before it)
+    C out[EPT];
+    auto unpack = [&](int64_t c0, int ncol) __attribute__((always_inline)) {
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            int j, l;
+            map(e, j, l);
+            const bool ok = e < NC * L && j < ncol;
+            if (!ok) { j = 0; l = 0; }
+            C v = X[j * CS + (l ^ lsw<L, C>(j))];
+            if (DIR < 0 && ax.split && ok) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+            out[q] = v;
+        });
+    };
+    auto store_out = [&](C* base, int64_t c0, int ncol) __attribute__((always_inline)) {
+        const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            int j, l;
+            map(e, j, l);
+            if (e >= NC * L || j >= ncol) return;
+            stg(base + addr(c0, cb, j, l), out[q]);
+        });
+    };
+    auto pack = [&](int64_t c0, int ncol) __attribute__((always_inline)) {
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            int j, l;
+            map(e, j, l);
+            if (e >= NC * L || j >= ncol) return;
+            C v = pre[q];
+            if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+            X[j * CS + (l ^ lsw<L, C>(j))] = v;
+        });
+    };
+
     int64_t t = blockIdx.x;
-    bool have;
     if constexpr (!G::PERSIST) {
         // one tile per workgroup: a workgroup without work leaves here, so the
         // tile's loads lie on the only path below (exact load waits)
         if (t >= total || !fetch(xcd_tile(t, total))) return;
-        have = true;
-    } else {
-        twr.store(twl, tid);
-        have = t < total ? fetch(xcd_tile(t, total)) : false;
-    }
-    for (; t < total; t += gridDim.x) {
-        const bool cur = have;
         int load;
         int64_t c0;
         C* base = tile_base(xcd_tile(t, total), load, c0);
         const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
-        if (cur) {
-            sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
-                constexpr int q = qc;
-                const int e = tid + q * TH;
-                int j, l;
-                map(e, j, l);
-                if (e >= NC * L || j >= ncol) return;
-                C v = pre[q];
-                if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
-                X[j * CS + (l ^ lsw<L, C>(j))] = v;
-            });
-        }
-        if constexpr (!G::PERSIST) twr.store(twl, tid);   // older than the tile's loads
+        pack(c0, ncol);
+        twr.store(twl, tid);   // older than the tile's loads
         __syncthreads();
-        const int64_t tn = t + gridDim.x;
-        if constexpr (G::PERSIST) have = tn < total ? fetch(xcd_tile(tn, total)) : false;
-        else have = false;
-        if (!cur) {
-            if constexpr (!G::PERSIST) break;
-            continue;
-        }
         fft_cols<L, DIR, CS>(X, NC, twl);
-        const int64_t cb = aligned ? (c0 / I) * (int64_t)L * I + (c0 % I) : 0;
-        for (int e = tid; e < L * NC; e += TH) {
-            int j, l;
-            map(e, j, l);
-            if (j >= ncol) continue;
-            C v = X[j * CS + (l ^ lsw<L, C>(j))];
-            if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
-            stg(base + addr(c0, cb, j, l), v);
+        unpack(c0, ncol);
+        store_out(base, c0, ncol);
+    } else {
+        twr.store(twl, tid);
+        bool have = t < total ? fetch(xcd_tile(t, total)) : false;
+        bool pend = false;
+        C* pbase = nullptr;
+        int64_t pc0 = 0;
+        int pncol = 0;
+        for (; t < total; t += gridDim.x) {
+            // a fresh (opaque) copy of the thread index per tile: keeps the
+            // per-thread offsets from being hoisted out of the loop and held
+            // in registers across all stages
+            asm volatile("" : "=v"(tid) : "0"(tid));
+            const bool cur = have;
+            int load;
+            int64_t c0;
+            C* base = tile_base(xcd_tile(t, total), load, c0);
+            const int ncol = (int)((ncols - c0) < NC ? (ncols - c0) : NC);
+            if (cur) pack(c0, ncol);
+            __syncthreads();
+            if (pend) store_out(pbase, pc0, pncol);   // tile t-1
+            pend = false;
+            const int64_t tn = t + gridDim.x;
+            have = tn < total ? fetch(xcd_tile(tn, total)) : false;   // tile t+1
+            if (!cur) continue;
+            fft_cols<L, DIR, CS>(X, NC, twl, tid);
+            unpack(c0, ncol);
+            __syncthreads();   // the tile is read out: LDS free for the next packing
+            pend = true;
+            pbase = base;
+            pc0 = c0;
+            pncol = ncol;
         }
-        __syncthreads();
-        if constexpr (!G::PERSIST) break;  // one tile per workgroup
+        if (pend) store_out(pbase, pc0, pncol);
     }
 }
 
