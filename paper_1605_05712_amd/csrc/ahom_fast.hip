@@ -1384,14 +1384,29 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
             a.res_part[(int64_t)load * nct + tt % nct] = acc;
         }
         fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
-        for (int e = tid; e < L * NC; e += TH) {
-            const int j = e / L;
-            if (j >= ncol) continue;
+        // read the tile out into registers, then store (the LDS reads go out
+        // back to back instead of alternating with the stores)
+        C out[EPT][NCOMP];
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            const bool ok = e < NC * L && e / L < ncol;
+            const int j = ok ? e / L : 0, l = e % L;
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                out[q][f] = F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))];
+            });
+        });
+        sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = qc;
+            const int e = tid + q * TH;
+            if (e >= NC * L || e / L >= ncol) return;
             const int64_t addr = c0 * L + e;
-            const int l = e % L;
-#pragma unroll
-            for (int f = 0; f < NCOMP; ++f) stg(base + (int64_t)f * P.S + addr, F[(f * NC + j) * CS + (l ^ lsw<L, C>(f * NC + j))]);
-        }
+            sfor<0, NCOMP>([&](auto fc) __attribute__((always_inline)) {
+                constexpr int f = fc;
+                stg(base + (int64_t)f * P.S + addr, out[q][f]);
+            });
+        });
         if constexpr (!G::PERSIST) break;  // one tile per workgroup
         __syncthreads();                   // LDS free for the next tile
     }
