@@ -660,11 +660,14 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
 // =============================================================================
 namespace {
 
-// global-memory writes of this workgroup made visible to its later reads
+// Global-memory writes of this workgroup made visible to its later reads.
+// An item's buffers are written and read by the one workgroup that owns the
+// item, so workgroup scope suffices; agent scope would write back and
+// invalidate the whole L2 of the XCD at every pass.
 __device__ __forceinline__ void wg_mem_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 template <typename T>
