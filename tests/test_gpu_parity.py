@@ -267,6 +267,53 @@ VARIANT_CASES = [
 ]
 
 
+STAGGER_CASES = [
+    ("3-D 64x64x128", [[64, 0, 0], [0, 64, 0], [0, 0, 128]], ahom.FP64),
+    ("3-D 64x64x128 fp32", [[64, 0, 0], [0, 64, 0], [0, 0, 128]], ahom.FP32_MIXED),
+    ("2-D 256x128", [[256, 0], [0, 128]], ahom.FP64),
+]
+
+
+@pytest.mark.parametrize("name,M,prec", STAGGER_CASES, ids=[c[0] for c in STAGGER_CASES])
+def test_every_tile_variant_with_loads_stopping_at_different_iterations(name, M, prec, monkeypatch):
+    """Load cases that converge at different iterations: every tile variant
+    (including the persistent schedules, which skip the tiles of finished
+    loads while prefetching the next tile) stops each load where the generic
+    path does, with the same residuals and fields."""
+    say("stagger", name, M, prec)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(23, 3)(P.points(), P.m)
+    eb = np.stack([np.eye(3) * 0.01, np.diag([0.01, 0.0, 0.0]), np.array([[0, 1, 0], [1, 0, 0], [0, 0, 0]]) * 0.005])
+    if len(M) == 2:
+        eb[:, 2, :] = 0.0
+        eb[:, :, 2] = 0.0
+    tol_stop = 1e-7 if prec == ahom.FP64 else 1e-6
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "1")
+    S = ahom.Solver(P, precision=prec, tol=tol_stop, max_iter=400)
+    S.set_material(LAM3, ph)
+    ref = S.solve(eb, want_strain=True)
+    del S
+    assert len(set(ref["iters"].tolist())) > 1, ref["iters"]   # the loads stop at different iterations
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "0")
+    for v in "01234":
+        monkeypatch.setenv("AHOM_FAST_VARIANT", v)
+        S = ahom.Solver(P, precision=prec, tol=tol_stop, max_iter=400)
+        S.set_material(LAM3, ph)
+        out = S.solve(eb, want_strain=True)
+        del S
+        if prec == ahom.FP64:
+            assert np.array_equal(out["iters"], ref["iters"]), (v, out["iters"], ref["iters"])
+            assert np.allclose(out["resid"], ref["resid"], rtol=1e-9), v
+            assert rel_err(out["strain"], ref["strain"]) < 1e-10, v
+        else:
+            # FP32 rounding differs between the two kernel families: the
+            # stop may move by an iteration, the fields agree to FP32 level
+            assert np.all(np.abs(out["iters"] - ref["iters"]) <= 2), (v, out["iters"], ref["iters"])
+            assert np.all(out["resid"] <= tol_stop), v
+            assert rel_err(out["strain"], ref["strain"]) < 1e-5, v
+    monkeypatch.delenv("AHOM_FAST_VARIANT")
+
+
 @pytest.mark.parametrize("name,M,prec", VARIANT_CASES, ids=[c[0] for c in VARIANT_CASES])
 def test_every_tile_variant_matches_generic(name, M, prec, monkeypatch):
     """Each compiled tile variant (width x schedule) gives the generic-path result."""
