@@ -287,10 +287,35 @@ template <int L, int TH, typename C> struct Twiddles {
     }
 };
 
+// x / d and x % d for x >= 0, d > 0: 32-bit unsigned division while both
+// fit (a 64-bit division is a long instruction sequence on this GPU)
+__device__ __forceinline__ void divmod_fast(int64_t x, int64_t d, int64_t& q, int64_t& r) {
+    if (((uint64_t)x | (uint64_t)d) < (uint64_t(1) << 32)) {
+        const uint32_t qq = (uint32_t)x / (uint32_t)d;
+        q = qq;
+        r = (int64_t)((uint32_t)x - qq * (uint32_t)d);
+    } else {
+        q = x / d;
+        r = x % d;
+    }
+}
+__device__ __forceinline__ int64_t div_fast(int64_t x, int64_t d) {
+    int64_t q, r;
+    divmod_fast(x, d, q, r);
+    return q;
+}
+__device__ __forceinline__ int64_t mod_fast(int64_t x, int64_t d) {
+    int64_t q, r;
+    divmod_fast(x, d, q, r);
+    return r;
+}
+
 template <typename C>
 __device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
-    const double2 a = tw64[ax.sp_off1 + (j % ax.spB)];
-    const double2 b = tw64[ax.sp_off2 + (j / ax.spB)];
+    int64_t hi, lo;
+    divmod_fast(j, ax.spB, hi, lo);
+    const double2 a = tw64[ax.sp_off1 + lo];
+    const double2 b = tw64[ax.sp_off2 + hi];
     const double2 w = cmul(a, b);
     using T = decltype(C{}.x);
     return C{(T)w.x, (T)w.y};
@@ -515,7 +540,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
             const int k = e / NC, j = e % NC;
             if (e >= H * NC || j >= x.ncol) return;
             C w = C{(T)1, (T)0};
-            if (ax.split) w = split_twiddle<C>(ax, a.tw64, ((x.c0 + j) / ax.qdiv) * (int64_t)k);
+            if (ax.split) w = split_twiddle<C>(ax, a.tw64, div_fast(x.c0 + j, ax.qdiv) * (int64_t)k);
             sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
                 constexpr int p = pc;
                 C A = pre[q][2 * p];
@@ -605,7 +630,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
             const bool ok = e < H * NC && e % NC < x.ncol;
             const int k = ok ? e / NC : 0, j = e % NC;
             C w = C{(T)1, (T)0};
-            if (ax.split && ok) w = split_twiddle<C>(ax, a.tw64, ((x.c0 + j) / ax.qdiv) * (int64_t)k);
+            if (ax.split && ok) w = split_twiddle<C>(ax, a.tw64, div_fast(x.c0 + j, ax.qdiv) * (int64_t)k);
             const int km = k == 0 ? 0 : L - k;
             sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
                 constexpr int p = pc;
@@ -778,7 +803,7 @@ __global__ void __launch_bounds__(256) kf_real_rr(RealArgs a) {
         const bool upper = 2 * k > L;
         const int kr = upper ? L - k : k;
         C w = C{(T)1, (T)0};
-        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (colc / ax.qdiv) * (int64_t)kr);
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, div_fast(colc, ax.qdiv) * (int64_t)kr);
         sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
             constexpr int p = pc;
             C A = ldg(src + (int64_t)(2 * p) * P.S + (int64_t)kr * I + colc);
@@ -855,7 +880,7 @@ __global__ void __launch_bounds__(256) kf_real_rr(RealArgs a) {
                 C A = C{(T)0.5 * (zk.x + zm.x), (T)0.5 * (zk.y - zm.y)};
                 C Bv = C{(T)0.5 * (zk.y + zm.y), (T)0.5 * (zm.x - zk.x)};
                 if (ax.split) {
-                    const C w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+                    const C w = split_twiddle<C>(ax, a.tw64, div_fast(col, ax.qdiv) * (int64_t)k);
                     A = cmul(A, w);
                     Bv = cmul(Bv, w);
                 }
@@ -915,8 +940,9 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
     };
     auto addr = [&](int64_t c0, int64_t cbase_aligned, int j, int l) __attribute__((always_inline)) -> int64_t {
         if (aligned) return cbase_aligned + j + (int64_t)l * I;
-        const int64_t col = c0 + j;
-        return (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+        int64_t cq, cr;
+        divmod_fast(c0 + j, I, cq, cr);
+        return cq * (int64_t)L * I + cr + (int64_t)l * I;
     };
     auto tile_base = [&](int64_t t, int& load, int64_t& c0) __attribute__((always_inline)) -> C* {
         const int64_t ct = t % nct;
@@ -975,7 +1001,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             const bool ok = e < NC * L && j < ncol;
             if (!ok) { j = 0; l = 0; }
             C v = X[j * CS + (l ^ lsw<L, C>(j))];
-            if (DIR < 0 && ax.split && ok) v = cmul(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+            if (DIR < 0 && ax.split && ok) v = cmul(v, split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
             out[q] = v;
         });
     };
@@ -998,7 +1024,7 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
             map(e, j, l);
             if (e >= NC * L || j >= ncol) return;
             C v = pre[q];
-            if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, (((c0 + j) % I) / ax.qdiv) * (int64_t)l));
+            if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
             X[j * CS + (l ^ lsw<L, C>(j))] = v;
         });
     };

@@ -161,10 +161,35 @@ __device__ void lds_fft(C* buf, C* tmp, int ncol, int CS, const AxisDesc& ax, co
 }
 
 // Four-step twiddle W_N^{j} from the two-level FP64 table, rounded to C.
+// x / d and x % d for x >= 0, d > 0: 32-bit unsigned division while both
+// fit (a 64-bit division is a long instruction sequence on this GPU)
+__device__ __forceinline__ void divmod_fast(int64_t x, int64_t d, int64_t& q, int64_t& r) {
+    if (((uint64_t)x | (uint64_t)d) < (uint64_t(1) << 32)) {
+        const uint32_t qq = (uint32_t)x / (uint32_t)d;
+        q = qq;
+        r = (int64_t)((uint32_t)x - qq * (uint32_t)d);
+    } else {
+        q = x / d;
+        r = x % d;
+    }
+}
+__device__ __forceinline__ int64_t div_fast(int64_t x, int64_t d) {
+    int64_t q, r;
+    divmod_fast(x, d, q, r);
+    return q;
+}
+__device__ __forceinline__ int64_t mod_fast(int64_t x, int64_t d) {
+    int64_t q, r;
+    divmod_fast(x, d, q, r);
+    return r;
+}
+
 template <typename C>
 __device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
-    const double2 a = tw64[ax.sp_off1 + (j % ax.spB)];
-    const double2 b = tw64[ax.sp_off2 + (j / ax.spB)];
+    int64_t hi, lo;
+    divmod_fast(j, ax.spB, hi, lo);
+    const double2 a = tw64[ax.sp_off1 + lo];
+    const double2 b = tw64[ax.sp_off2 + hi];
     const double2 w = cmul(a, b);
     using T = decltype(C{}.x);
     return C{(T)w.x, (T)w.y};
@@ -225,6 +250,37 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     C* dst = reinterpret_cast<C*>((MODE == REAL_TURN ? (src_buf ^ 1) : 0) ? a.buf1 : a.buf0) + (int64_t)load * NC_ * P.S;
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
 
+    // Lame pairs of the law points e = tid + q blockDim (q < GEPL): phase ids
+    // and table entries are loaded up front, all independent, so the law does
+    // not wait for two dependent global loads per point.  Tiles with more law
+    // points than GEPL per thread use the per-point loads below.
+    constexpr int GEPL = 8;
+    const bool pre_law = MODE == REAL_TURN && L * a.NC <= GEPL * (int)blockDim.x;
+    T lamq[GEPL], muq[GEPL];
+    if (pre_law) {
+        int phq[GEPL];
+#pragma unroll
+        for (int q = 0; q < GEPL; ++q) {
+            const int e = tid + q * (int)blockDim.x;
+            const int n = e / a.NC, j = e - n * a.NC;
+            const bool ok = e < L * a.NC && j < ncol;
+            const int64_t pt = ok ? (int64_t)n * I + c0 + j : c0;
+            if (a.lame_pts) {
+                lamq[q] = (T)a.lame_pts[2 * pt];
+                muq[q] = (T)a.lame_pts[2 * pt + 1];
+            } else {
+                phq[q] = a.phase[pt];
+            }
+        }
+        if (!a.lame_pts) {
+#pragma unroll
+            for (int q = 0; q < GEPL; ++q) {
+                lamq[q] = (T)a.lame_tab[2 * phq[q]];
+                muq[q] = (T)a.lame_tab[2 * phq[q] + 1];
+            }
+        }
+    }
+
     if (MODE != REAL_FROM_REAL) {
         // ---- gather the half spectra and form packed full spectra Z_p = A + i B
         for (int e = tid; e < H * a.NC; e += blockDim.x) {
@@ -232,7 +288,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
             if (j >= ncol) continue;
             const int64_t col = c0 + j;
             C w = C{(T)1, (T)0};
-            if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+            if (ax.split) w = split_twiddle<C>(ax, a.tw64, div_fast(col, ax.qdiv) * (int64_t)k);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const int fa = 2 * p, fb = 2 * p + 1;
@@ -269,19 +325,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
 
     if (MODE == REAL_TURN) {
         const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
-        for (int e = tid; e < L * a.NC; e += blockDim.x) {
-            const int n = e / a.NC, j = e - n * a.NC;
-            if (j >= ncol) continue;
-            const int64_t pt = (int64_t)n * I + c0 + j;
-            T lam, mu;
-            if (a.lame_pts) {
-                lam = (T)a.lame_pts[2 * pt];
-                mu = (T)a.lame_pts[2 * pt + 1];
-            } else {
-                const int ph = a.phase[pt];
-                lam = (T)a.lame_tab[2 * ph];
-                mu = (T)a.lame_tab[2 * ph + 1];
-            }
+        auto point = [&](int n, int j, T lam, T mu) __attribute__((always_inline)) {
             T eps[NC_];
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
@@ -302,6 +346,26 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
 #pragma unroll
             for (int p = 0; p < NP; ++p)
                 Z[p * a.NC * CS + j * CS + n] = C{tau[2 * p], 2 * p + 1 < NC_ ? tau[2 * p + 1] : (T)0};
+        };
+        if (pre_law) {
+#pragma unroll
+            for (int q = 0; q < GEPL; ++q) {
+                const int e = tid + q * (int)blockDim.x;
+                const int n = e / a.NC, j = e - n * a.NC;
+                if (e < L * a.NC && j < ncol) point(n, j, lamq[q], muq[q]);
+            }
+        } else {
+            for (int e = tid; e < L * a.NC; e += blockDim.x) {
+                const int n = e / a.NC, j = e - n * a.NC;
+                if (j >= ncol) continue;
+                const int64_t pt = (int64_t)n * I + c0 + j;
+                if (a.lame_pts) {
+                    point(n, j, (T)a.lame_pts[2 * pt], (T)a.lame_pts[2 * pt + 1]);
+                } else {
+                    const int ph = a.phase[pt];
+                    point(n, j, (T)a.lame_tab[2 * ph], (T)a.lame_tab[2 * ph + 1]);
+                }
+            }
         }
     } else {  // REAL_FROM_REAL: eps = eps_bar + init
         const double* in = a.real_io + (int64_t)load * NC_ * P.m;
@@ -329,7 +393,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
         C w = C{(T)1, (T)0};
-        if (ax.split) w = split_twiddle<C>(ax, a.tw64, (col / ax.qdiv) * (int64_t)k);
+        if (ax.split) w = split_twiddle<C>(ax, a.tw64, div_fast(col, ax.qdiv) * (int64_t)k);
         const int km = k == 0 ? 0 : L - k;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -393,9 +457,11 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
         if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
-        const int64_t addr = (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+        int64_t cq, cr;
+        divmod_fast(col, I, cq, cr);
+        const int64_t addr = cq * (int64_t)L * I + cr + (int64_t)l * I;
         C v = base[addr];
-        if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, ((col % I) / ax.qdiv) * (int64_t)l));
+        if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, div_fast(cr, ax.qdiv) * (int64_t)l));
         X[j * CS + l] = v;
     }
     __syncthreads();
@@ -405,9 +471,11 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
         if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
-        const int64_t addr = (col / I) * (int64_t)L * I + (col % I) + (int64_t)l * I;
+        int64_t cq, cr;
+        divmod_fast(col, I, cq, cr);
+        const int64_t addr = cq * (int64_t)L * I + cr + (int64_t)l * I;
         C v = X[j * CS + l];
-        if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, ((col % I) / ax.qdiv) * (int64_t)l));
+        if (DIR < 0 && ax.split) v = cmul(v, split_twiddle<C>(ax, a.tw64, div_fast(cr, ax.qdiv) * (int64_t)l));
         base[addr] = v;
     }
 }
@@ -457,24 +525,64 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
     const int L0 = P.ax[0].len;
+    // Centred numerators in exact doubles while emax <= 2^24 (A in [0, emax),
+    // 0 <= kappa_s < e_s <= emax: products < 2^48, sums of three < 2^53), the
+    // same integers as the 64-bit formula without a 64-bit division per point.
+    const int64_t emax = P.fm.emax;
+    const bool nfast = emax <= (int64_t(1) << 24);
+    const double emax_d = (double)emax, inv_e = 1.0 / emax_d;
+    double Ad[3][3];
+    for (int i2 = 0; i2 < 3; ++i2)
+        for (int s2 = 0; s2 < 3; ++s2) Ad[i2][s2] = (i2 < DIM && s2 < DIM) ? (double)P.fm.A[i2][s2] : 0.0;
+    const bool small_cols = ncols < (int64_t(1) << 31);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         const int j = e / L, l = e - j * L;
         if (j >= ncol) continue;
-        // position -> kappa
+        // position -> kappa (32-bit division while the column count fits)
         int64_t kpos[AHOM_MAX_AXES];
-        int64_t o = c0 + j;
-        for (int b = D - 2; b >= 0; --b) {
-            const int64_t sl = P.ax[b].slen;
-            kpos[b] = o % sl;
-            o /= sl;
+        if (small_cols) {
+            uint32_t o = (uint32_t)(c0 + j);
+            for (int b = D - 2; b >= 0; --b) {
+                const uint32_t sl = (uint32_t)P.ax[b].slen;
+                kpos[b] = o % sl;
+                o /= sl;
+            }
+        } else {
+            int64_t o = c0 + j;
+            for (int b = D - 2; b >= 0; --b) {
+                const int64_t sl = P.ax[b].slen;
+                kpos[b] = o % sl;
+                o /= sl;
+            }
         }
         kpos[D - 1] = l;
         int64_t kap[3] = {0, 0, 0};
         for (int b = 0; b < D; ++b) kap[P.ax[b].snf] += P.ax[b].mult * kpos[b];
         const bool is_zero = kap[0] == 0 && kap[1] == 0 && kap[2] == 0;
         int64_t N[3];
-        const int half = ahom_centred_numerators(P.fm, kap, N);
-        const bool active = !half || ahom_self_conjugate(P.fm, kap);
+        int half = 0;
+        if (nfast) {
+            for (int i2 = 0; i2 < DIM; ++i2) {
+                double x = 0.0;
+                for (int s2 = 0; s2 < DIM; ++s2) x += Ad[i2][s2] * (double)kap[s2];
+                double r = x - floor(x * inv_e) * emax_d;
+                if (r < 0) r += emax_d;
+                if (r >= emax_d) r -= emax_d;
+                if (2 * r >= emax_d) r -= emax_d;
+                if (2 * r == -emax_d) half = 1;
+                N[i2] = (int64_t)r;
+            }
+        } else {
+            half = ahom_centred_numerators(P.fm, kap, N);
+        }
+        // self-conjugate test 2 kappa = 0 (mod e): for 0 <= kappa_s < e_s a comparison
+        bool sc = true;
+        if (half)
+            for (int s2 = 0; s2 < DIM; ++s2) {
+                const int64_t k2 = 2 * kap[s2], es = P.fm.e[s2];
+                sc = sc && ((kap[s2] >= 0 && kap[s2] < es) ? (k2 == 0 || k2 == es) : (k2 % es == 0));
+            }
+        const bool active = !half || sc;
         const int64_t spos = (c0 + j) * L + l;
         C* fp[NC_];
 #pragma unroll
