@@ -100,6 +100,7 @@ int choose_geom(int L, int64_t ncols, int nbuf, size_t extra, size_t es, int pre
     int NC = std::max(1, target / L);
     if (ncols < NC) NC = (int)std::max<int64_t>(1, ncols);
     const int CS = L + 1;
+    extra += (size_t)L * es;   // LDS copy of the axis's twiddle table
     while (NC > 1 && (size_t)nbuf * NC * CS * es + extra > kLdsCap) NC /= 2;
     size_t lds = (size_t)nbuf * NC * CS * es + extra;
     if (lds > 160 * 1024) return fail(AHOM_E_UNSUPPORTED_SIZE, "transform length too long for one LDS tile");

@@ -52,11 +52,12 @@ struct PassGeo {
 PassGeo pass_geo(int L, int64_t ncols, int nbuf, size_t es, size_t budget) {
     PassGeo g;
     g.CS = L + 1;
-    int64_t nc = (int64_t)(budget / ((size_t)nbuf * g.CS * es));
+    const size_t twl = (size_t)L * es;   // LDS copy of the axis's twiddle table
+    int64_t nc = (int64_t)((budget > twl ? budget - twl : 0) / ((size_t)nbuf * g.CS * es));
     nc = std::max<int64_t>(1, std::min<int64_t>({nc, ncols, (int64_t)kMaxNC}));
     g.NC = (int)nc;
     g.tiles = (ncols + nc - 1) / nc;
-    g.lds = (size_t)nbuf * g.NC * g.CS * es;
+    g.lds = (size_t)nbuf * g.NC * g.CS * es + twl;
     return g;
 }
 

@@ -200,6 +200,16 @@ template <typename T> __device__ __forceinline__ T* lds_base() {
     return reinterpret_cast<T*>(ahom_smem);
 }
 
+// Copy of an axis's twiddle table (L entries) in LDS after the tile buffers;
+// the Stockham stages read it there instead of from global memory in every
+// butterfly.  Visible to the first transform through the barrier that follows
+// the tile's gather.  (The block reductions after a tile may reuse the space.)
+template <typename C>
+__device__ __forceinline__ C* stage_twiddles(C* twl, const C* __restrict__ tw, int L) {
+    for (int i = threadIdx.x; i < L; i += blockDim.x) twl[i] = tw[i];
+    return twl;
+}
+
 // block-wide sum of NV doubles per thread (fixed order); result valid in thread 0
 template <int NV>
 __device__ void block_sum(double* vals, double* scratch) {
@@ -242,6 +252,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
 
     C* Z = lds_base<C>();
     C* tmp = Z + NP * a.NC * CS;
+    C* twl = stage_twiddles(tmp + a.NC * CS, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
 
     int src_buf = 0;
     if (MODE == REAL_TURN) src_buf = st.iter & 1;
@@ -302,7 +313,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
             }
         }
         __syncthreads();
-        for (int p = 0; p < NP; ++p) lds_fft<+1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, tw);
+        for (int p = 0; p < NP; ++p) lds_fft<+1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, twl);
     }
 
     if (MODE == REAL_TO_REAL) {
@@ -384,7 +395,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
         }
     }
     __syncthreads();
-    for (int p = 0; p < NP; ++p) lds_fft<-1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, tw);
+    for (int p = 0; p < NP; ++p) lds_fft<-1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, twl);
 
     // ---- split the packed spectra and store the half spectra
     const T scale = MODE == REAL_FROM_REAL ? (T)(1.0 / L) : (T)1;
@@ -449,6 +460,7 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
     C* X = lds_base<C>();
     C* tmp = X + a.NC * CS;
+    C* twl = stage_twiddles(tmp + a.NC * CS, tw, L);
     const bool rowmajor = I >= a.NC;
     const int tid = threadIdx.x;
 
@@ -465,7 +477,7 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
         X[j * CS + l] = v;
     }
     __syncthreads();
-    lds_fft<DIR>(X, tmp, ncol, CS, ax, tw);
+    lds_fft<DIR>(X, tmp, ncol, CS, ax, twl);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         int j, l;
         if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
@@ -510,6 +522,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
     C* F = lds_base<C>();
     C* tmp = F + NC_ * a.NC * CS;
+    C* twl = stage_twiddles(tmp + a.NC * CS, tw, L);
 
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         const int j = e / L, l = e - j * L;
@@ -519,7 +532,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         for (int f = 0; f < NC_; ++f) F[f * a.NC * CS + j * CS + l] = base[(int64_t)f * P.S + addr];
     }
     __syncthreads();
-    for (int f = 0; f < NC_; ++f) lds_fft<-1>(F + f * a.NC * CS, tmp, ncol, CS, ax, tw);
+    for (int f = 0; f < NC_; ++f) lds_fft<-1>(F + f * a.NC * CS, tmp, ncol, CS, ax, twl);
 
     const double* eb = a.eps_bar + (int64_t)load * NC_;
     const T inv_m = (T)(1.0 / (double)P.m);
@@ -694,7 +707,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     }
     if (MODE == SPEC_INIT) return;
     __syncthreads();
-    for (int f = 0; f < NC_; ++f) lds_fft<+1>(F + f * a.NC * CS, tmp, ncol, CS, ax, tw);
+    for (int f = 0; f < NC_; ++f) lds_fft<+1>(F + f * a.NC * CS, tmp, ncol, CS, ax, twl);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         const int j = e / L, l = e - j * L;
         if (j >= ncol) continue;
