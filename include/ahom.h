@@ -257,9 +257,11 @@ int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double m
 /*
  * The same n_load macroscopic strains (n_load*9) for every member.  Outputs
  * are indexed [member * n_load + load]: iters, resid, status (0 converged,
- * 1 not converged, 2 diverged), mean_stress (9 doubles each); any may be NULL.
- * use_graph != 0 replays the launch from a HIP graph captured on the first
- * call (on a stream of the batch's own).  Returns as ahom_solve.
+ * 1 not converged, 2 diverged, 3 invalid: a large item iterated by a group of
+ * workgroups lost a member at a pass barrier), mean_stress (9 doubles each);
+ * any may be NULL.  use_graph != 0 replays the launch from a HIP graph
+ * captured on the first call (on a stream of the batch's own).  Returns as
+ * ahom_solve.
  */
 int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iters, double* resid, double* mean_stress,
                      int* status, int use_graph);

@@ -42,6 +42,8 @@ const Variant kVariants[] = {{8, 1}, {4, 1}, {8, 2}, {4, 2}};
 constexpr int kNumVariants = 4;
 constexpr size_t kBudget = 48 * 1024;   // dynamic LDS per workgroup for the largest tiles
 constexpr int kMaxNC = 512;
+constexpr int kGroupMax = 8;            // workgroups per item at most
+constexpr int kGroupPart = 2 * kGroupMax * 8;   // doubles of an item's group partial sums
 
 struct PassGeo {
     int NC = 1, CS = 1;
@@ -109,6 +111,10 @@ struct ahom_batch {
     char* arena = nullptr;            // every item buffer
     BatchItem* d_items = nullptr;
     int* d_order = nullptr;
+    int* d_qslot = nullptr;
+    int* d_gcount = nullptr;
+    double* d_gpart = nullptr;
+    int n_queue = 0;
     int* d_counter = nullptr;
     LoadState* d_st = nullptr;
     LoadState* d_st_base = nullptr;   // final_buf = 1: where the FP64 base iterate is
@@ -137,7 +143,8 @@ struct ahom_batch {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
-        dfree(arena); dfree(d_items); dfree(d_order); dfree(d_counter); dfree(d_st); dfree(d_st_base);
+        dfree(arena); dfree(d_items); dfree(d_order); dfree(d_qslot); dfree(d_gcount); dfree(d_gpart);
+        dfree(d_counter); dfree(d_st); dfree(d_st_base);
         dfree(d_restarts); dfree(d_hist); dfree(d_epsbar); dfree(d_zero);
         nload = 0;
     }
@@ -215,8 +222,9 @@ int ahom_batch::build_items(int n_load) {
     }
     BCHK(hipMalloc((void**)&arena, std::max<size_t>(off[n_items], 256)));
     BCHK(hipMalloc((void**)&d_items, n_items * sizeof(BatchItem)));
-    BCHK(hipMalloc((void**)&d_order, n_items * sizeof(int)));
     BCHK(hipMalloc((void**)&d_counter, 256));
+    BCHK(hipMalloc((void**)&d_gcount, n_items * sizeof(int)));
+    BCHK(hipMalloc((void**)&d_gpart, (size_t)n_items * kGroupPart * sizeof(double)));
     BCHK(hipMalloc((void**)&d_st, n_items * sizeof(LoadState)));
     BCHK(hipMalloc((void**)&d_st_base, sizeof(LoadState)));
     BCHK(hipMalloc((void**)&d_restarts, n_items * sizeof(int)));
@@ -259,6 +267,9 @@ int ahom_batch::build_items(int n_load) {
         it.hist_cap = hist_cap;
         it.st = d_st + q;
         it.restarts = d_restarts + q;
+        it.k = 1;
+        it.gcount = d_gcount + q;
+        it.gpart = d_gpart + (size_t)q * kGroupPart;
         const double beta = (mb.lam0 + mb.mu0) / (mb.lam0 + 2.0 * mb.mu0);
         auto fill_args = [&](int pr, void* b0, void* b1, void* tb, RealArgs* ra, AxisArgs* ax, SpecArgs* sa,
                              int64_t* t_real, int64_t* t_spec, int64_t* t_axis) {
@@ -302,12 +313,6 @@ int ahom_batch::build_items(int n_load) {
             it.sa64.dneg = tbuf;
         }
     }
-    BCHK(hipMemcpy(d_items, h_items.data(), n_items * sizeof(BatchItem), hipMemcpyHostToDevice));
-    // largest members first (the queue hands them out in this order)
-    std::vector<int> order(n_items);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Sv[a / n_load] > Sv[b / n_load]; });
-    BCHK(hipMemcpy(d_order, order.data(), n_items * sizeof(int), hipMemcpyHostToDevice));
     lds = lds_max;
     const size_t lds_total = lds + ahom_batch_static_lds(d);
     if (lds_total > 160 * 1024) return bfail(AHOM_E_UNSUPPORTED_SIZE, "batch tiles exceed the LDS");
@@ -317,7 +322,36 @@ int ahom_batch::build_items(int n_load) {
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) ncu = n;
     }
     const int occ = std::max(1, ahom_batch_occupancy(prec, d, lds));
-    nwg = std::max(1, std::min(n_items, occ * ncu));
+    const int cap = std::max(1, occ * ncu);   // workgroups resident at once
+    // Items much larger than a workgroup's fair share are iterated by a group
+    // of k workgroups (tiles of every pass dealt round-robin, a group barrier
+    // between passes).  k <= nwg keeps the queue deadlock-free: a group's queue
+    // positions are consecutive, so at most the group at the queue head is
+    // incomplete and the workgroups of the complete ones join it when done.
+    {
+        double total = 0.0;
+        for (int q = 0; q < n_items; ++q) total += (double)Sv[q / n_load];
+        const int kmax = std::min(kGroupMax, cap);
+        for (int q = 0; q < n_items; ++q) {
+            const double share = 3.0 * (double)Sv[q / n_load] * cap / std::max(total, 1.0);
+            h_items[q].k = std::max(1, std::min(kmax, (int)std::ceil(share)));
+        }
+    }
+    BCHK(hipMemcpy(d_items, h_items.data(), n_items * sizeof(BatchItem), hipMemcpyHostToDevice));
+    // largest members first (the queue hands them out in this order), one
+    // queue position per workgroup of an item's group
+    std::vector<int> order(n_items);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Sv[a / n_load] > Sv[b / n_load]; });
+    std::vector<int> qitem, qslot;
+    for (int q : order)
+        for (int sl = 0; sl < h_items[q].k; ++sl) { qitem.push_back(q); qslot.push_back(sl); }
+    n_queue = (int)qitem.size();
+    nwg = std::min(n_queue, cap);   // >= every item's k
+    BCHK(hipMalloc((void**)&d_order, n_queue * sizeof(int)));
+    BCHK(hipMalloc((void**)&d_qslot, n_queue * sizeof(int)));
+    BCHK(hipMemcpy(d_order, qitem.data(), n_queue * sizeof(int), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(d_qslot, qslot.data(), n_queue * sizeof(int), hipMemcpyHostToDevice));
     h_st.assign(n_items, LoadState{});
     h_restarts.assign(n_items, 0);
     nload = n_load;
@@ -328,7 +362,8 @@ int ahom_batch::run(bool use_graph) {
     BatchArgs a{};
     a.items = d_items;
     a.order = d_order;
-    a.n_items = (int)h_items.size();
+    a.qslot = d_qslot;
+    a.n_queue = n_queue;
     a.counter = d_counter;
     a.tol = cfg.tol;
     a.refine = cfg.refine;
@@ -338,7 +373,7 @@ int ahom_batch::run(bool use_graph) {
     hipStream_t s = use_graph ? gstream : stream;
     if (use_graph && !gexec) {
         BCHK(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal));
-        const int r1 = ahom_launch_batch_reset(d_counter, a.n_items, gstream);
+        const int r1 = ahom_launch_batch_reset(d_counter, d_gcount, (int)h_items.size(), gstream);
         const int r2 = ahom_launch_batch(prec, d, a, nwg, lds, gstream);
         hipGraph_t g = nullptr;
         BCHK(hipStreamEndCapture(gstream, &g));
@@ -350,7 +385,7 @@ int ahom_batch::run(bool use_graph) {
     if (use_graph) {
         BCHK(hipGraphLaunch(gexec, s));
     } else {
-        if (ahom_launch_batch_reset(d_counter, a.n_items, s)) return bfail(AHOM_E_DEVICE, "launch batch reset");
+        if (ahom_launch_batch_reset(d_counter, d_gcount, (int)h_items.size(), s)) return bfail(AHOM_E_DEVICE, "launch batch reset");
         if (ahom_launch_batch(prec, d, a, nwg, lds, s)) return bfail(AHOM_E_DEVICE, "launch batch kernel");
     }
     BCHK(hipEventRecord(ev1, s));

@@ -150,7 +150,7 @@ constexpr int pow2floor(int v) {
 }
 
 // columns per workgroup: NF fields x NC columns x N1 threads <= 512 threads,
-// NF x NC x (L + 1) elements <= 50 KB of LDS
+// NF x NC x CS elements <= 50 KB of LDS (CS: column stride, see below)
 // Tile variants V (chosen per pass by the autotuner): bit 0 halves the
 // columns per tile, bit 1 selects the persistent prefetching schedule.
 template <typename T, int L, int NF, int V = 0> struct Geo {
@@ -403,12 +403,12 @@ __device__ __forceinline__ int centred_numerators(const FreqMap& f, const int64_
 }  // namespace
 
 
-// Work distribution of the pass kernels below: a persistent grid walks the
-// tiles t = blockIdx.x, blockIdx.x + gridDim.x, ...; while tile t is being
-// transformed, the global loads of the next tile are already in flight into
-// registers (pre[]), so every workgroup overlaps HBM latency with its own
-// LDS work.  Partial sums are written per (load, tile) and reduced in a
-// fixed order.
+// Work distribution of the pass kernels below: one tile per workgroup
+// (variants 0/1), or a persistent grid that walks the tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ... with the next tile's loads in flight into
+// registers (pre[]) while tile t is transformed (variants 2/3).  Tiles of
+// load cases that have stopped are skipped.  Partial sums are written per
+// (load, tile) and reduced in a fixed order.
 
 // Value of a wave-uniform quantity kept in a scalar register, so that the
 // loads it addresses (load states, plan fields) are scalar loads and never

@@ -161,20 +161,24 @@ struct BatchItem {
     int hist_cap;
     LoadState* st;                     // result state of the item
     int* restarts;
+    int k;                             // workgroups that iterate the item together (>= 1)
+    int* gcount;                       // group barrier arrivals (zeroed before each launch)
+    double* gpart;                     // [2][k][8] partial sums of the group's workgroups
 };
 
 struct BatchArgs {
     const BatchItem* items;
     const int* order;                  // queue position -> item
-    int n_items;
+    const int* qslot;                  // queue position -> slot of the item's group
+    int n_queue;                       // queue positions (sum of the items' k)
     int* counter;                      // queue head (zeroed before each launch)
     double tol, refine;
     int max_iter, resid_period;
     int refine_on;                     // FP32 items: defect-correction restarts
 };
 
-// queue head and item states to zero (plain kernels: safe inside a captured graph)
-int ahom_launch_batch_reset(int* counter, int n_items, hipStream_t s);
+// queue head and group barrier counters to zero (plain kernel: safe inside a captured graph)
+int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t s);
 int ahom_launch_batch(int prec, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s);
 // static LDS bytes of the batch kernel (reduction scratch and item state)
 size_t ahom_batch_static_lds(int dim);

@@ -791,12 +791,49 @@ __device__ __forceinline__ void wg_mem_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Pass boundary of an item: workgroup-level for k = 1; for a group of k
+// workgroups (any CUs and XCDs) an agent-scope release, an arrival on the
+// item's counter and a wait for the k arrivals of this phase, then an
+// agent-scope acquire.  Every workgroup of the group calls it the same number
+// of times (phase counts them).  The wait is bounded: after ~4 s without the
+// group's arrivals it marks the counter (bit 30) and this and all later
+// barriers of the item stop waiting, so a lost workgroup cannot hang the
+// launch (the item's result is then wrong and its status says so).
+constexpr int kGroupAbort = 1 << 30;
+__device__ __forceinline__ void group_sync(const BatchItem& it, int& phase) {
+    if (it.k == 1) {
+        wg_mem_sync();
+        return;
+    }
+    ++phase;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(it.gcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int target = it.k * phase;
+        const long long t0 = wall_clock64();
+        for (;;) {
+            const int c = __hip_atomic_load(it.gcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((c & kGroupAbort) || c >= target) break;
+            if (wall_clock64() - t0 > 400000000LL) {   // 100 MHz clock: 4 s
+                __hip_atomic_fetch_or(it.gcount, kGroupAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// element loops below: the group's k workgroups share them (slot = this
+// workgroup's position in the group)
 template <typename T>
-__device__ void wg_fill_state(void* buf, const double* eps_bar, int64_t S, int64_t row, int nfield) {
+__device__ void wg_fill_state(void* buf, const double* eps_bar, int64_t S, int64_t row, int nfield, int slot, int k) {
     using C = typename CT<T>::t;
     C* b = reinterpret_cast<C*>(buf);
     const int64_t n = (int64_t)nfield * S;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int64_t i = (int64_t)slot * blockDim.x + threadIdx.x; i < n; i += (int64_t)k * blockDim.x) {
         const int f = (int)(i / S);
         const int64_t k = i - (int64_t)f * S;
         b[i] = k < row ? C{(T)eps_bar[f], (T)0} : C{(T)0, (T)0};
@@ -804,10 +841,10 @@ __device__ void wg_fill_state(void* buf, const double* eps_bar, int64_t S, int64
 }
 
 template <typename T>
-__device__ void wg_zero(void* p, int64_t n_complex) {
+__device__ void wg_zero(void* p, int64_t n_complex, int slot, int k) {
     using C = typename CT<T>::t;
     C* q = reinterpret_cast<C*>(p);
-    for (int64_t i = threadIdx.x; i < n_complex; i += blockDim.x) q[i] = C{(T)0, (T)0};
+    for (int64_t i = (int64_t)slot * blockDim.x + threadIdx.x; i < n_complex; i += (int64_t)k * blockDim.x) q[i] = C{(T)0, (T)0};
 }
 
 // Iterate one item (all passes, then the FP64 reduction and loop control of
@@ -817,41 +854,57 @@ template <typename T, int DIM>
 __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisArgs* ax, const SpecArgs& sa,
                             int64_t t_real, int64_t t_spec, const int64_t* t_axis, LoadState& st,
                             const double* sig_base, double tol, int max_iter, int resid_period, bool record,
-                            double* red) {
+                            double* red, int slot, int& phase, int& rround) {
     constexpr int NC_ = Comp<DIM>::N;
     const int tid = threadIdx.x;
+    const int k = it.k;
     for (;;) {
         double v[NC_ + 1];
 #pragma unroll
         for (int c = 0; c <= NC_; ++c) v[c] = 0.0;
-        for (int64_t t = 0; t < t_real; ++t) {
+        // the tiles of every pass are dealt round-robin to the group's workgroups
+        for (int64_t t = slot; t < t_real; t += k) {
             real_tile<T, DIM, REAL_TURN>(ra, st, 0, t, v);
             __syncthreads();
         }
-        wg_mem_sync();
+        group_sync(it, phase);
         const int par = (st.iter + 1) & 1;
         for (int a = 1; a <= it.D - 2; ++a) {
-            for (int f = 0; f < NC_; ++f)
-                for (int64_t t = 0; t < t_axis[a]; ++t) {
-                    axis_tile<T, -1>(ax[a], par, 0, f, t);
-                    __syncthreads();
-                }
-            wg_mem_sync();
+            const int64_t nt = (int64_t)NC_ * t_axis[a];
+            for (int64_t u = slot; u < nt; u += k) {
+                axis_tile<T, -1>(ax[a], par, 0, (int)(u / t_axis[a]), u % t_axis[a]);
+                __syncthreads();
+            }
+            group_sync(it, phase);
         }
-        for (int64_t t = 0; t < t_spec; ++t) {
+        for (int64_t t = slot; t < t_spec; t += k) {
             spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_]);
             __syncthreads();
         }
-        wg_mem_sync();
+        group_sync(it, phase);
         for (int a = it.D - 2; a >= 1; --a) {
-            for (int f = 0; f < NC_; ++f)
-                for (int64_t t = 0; t < t_axis[a]; ++t) {
-                    axis_tile<T, +1>(ax[a], par, 0, f, t);
-                    __syncthreads();
-                }
-            wg_mem_sync();
+            const int64_t nt = (int64_t)NC_ * t_axis[a];
+            for (int64_t u = slot; u < nt; u += k) {
+                axis_tile<T, +1>(ax[a], par, 0, (int)(u / t_axis[a]), u % t_axis[a]);
+                __syncthreads();
+            }
+            group_sync(it, phase);
         }
         block_sum<NC_ + 1>(v, red);
+        if (k > 1) {
+            // the group's partial sums, combined in slot order by every member
+            double* gp = it.gpart + (rround & 1) * (k * 8);
+            if (tid == 0)
+                for (int c = 0; c <= NC_; ++c) gp[slot * 8 + c] = v[c];
+            group_sync(it, phase);
+            if (tid == 0)
+                for (int c = 0; c <= NC_; ++c) {
+                    double acc = 0.0;
+                    for (int s2 = 0; s2 < k; ++s2) acc += gp[s2 * 8 + c];
+                    v[c] = acc;
+                }
+            ++rround;
+        }
         if (tid == 0) {
             const double inv_m = 1.0 / (double)it.m;
             double fro = 0.0;
@@ -862,12 +915,13 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
                 fro += (diag ? 1.0 : 2.0) * mc * mc;
             }
             const int n = st.iter;
+            const bool rec = record && slot == 0;
             if (!ahom_check_iter(n, resid_period, max_iter)) {
-                if (record && n < it.hist_cap) it.hist[n] = -1.0;
+                if (rec && n < it.hist_cap) it.hist[n] = -1.0;
                 st.iter = n + 1;
             } else {
                 const double r = sqrt(v[NC_]) / sqrt(fro);
-                if (record && n < it.hist_cap) it.hist[n] = r;
+                if (rec && n < it.hist_cap) it.hist[n] = r;
                 if (n == 0) st.r0 = r;
                 st.resid = r;
                 const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
@@ -875,6 +929,10 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
                 else if (r <= tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; }
                 else if (n >= max_iter) { st.done = 1; st.status = 1; st.final_buf = n & 1; }
                 else st.iter = n + 1;
+            }
+            if (k > 1 && (__hip_atomic_load(it.gcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kGroupAbort)) {
+                st.done = 1;
+                st.status = 3;   // group barrier timed out: result invalid
             }
         }
         __syncthreads();
@@ -886,17 +944,19 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
 // same scheme as the single-pattern solver: FP64 iterate eps_b = F(eps_h),
 // traction step d, then FP32 iteration on eps - eps_b with offset d).
 template <typename T, int DIM>
-__device__ void batch_item(const BatchArgs& b, const BatchItem& it, LoadState& st, LoadState& st64, double* sbase,
-                           double* red) {
+__device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, LoadState& st64,
+                           double* sbase, double* red) {
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
     const int tid = threadIdx.x;
-    wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_);
-    wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S);
+    const int k = it.k;
+    int phase = 0, rround = 0;
+    wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_, slot, k);
+    wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S, slot, k);
     if (tid == 0) st = LoadState{};
-    wg_mem_sync();
+    group_sync(it, phase);
     double stage_tol = b.refine_on ? fmax(b.tol, b.refine) : b.tol;
     batch_stage<T, DIM>(it, it.ra, it.ax, it.sa, it.t_real, it.t_spec, it.t_axis, st, nullptr, stage_tol, b.max_iter,
-                        b.resid_period, true, red);
+                        b.resid_period, true, red, slot, phase, rround);
     int nres = 0;
     if constexpr (sizeof(T) == 4) {
         while (b.refine_on && st.status == 0 && st.resid > b.tol) {
@@ -906,18 +966,18 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, LoadState& s
                 double2* out = reinterpret_cast<double2*>(it.ra64.buf0);
                 const double2* base = nres ? reinterpret_cast<const double2*>(it.ra64.buf1) : nullptr;
                 const int64_t n = (int64_t)NC_ * it.S;
-                for (int64_t i = tid; i < n; i += blockDim.x) {
+                for (int64_t i = (int64_t)slot * blockDim.x + tid; i < n; i += (int64_t)k * blockDim.x) {
                     const float2 x = in[i];
                     double2 r = double2{(double)x.x, (double)x.y};
                     if (base) { r.x += base[i].x; r.y += base[i].y; }
                     out[i] = r;
                 }
             }
-            wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S);
+            wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S, slot, k);
             if (tid == 0) st64 = LoadState{};
-            wg_mem_sync();
+            group_sync(it, phase);
             batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64,
-                                     nullptr, -1.0, 1, 1, false, red);
+                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround);
             ++nres;
             // correction stage: e(0) = 0, t(e(-1)) = -d (written by the FP64 pass)
             if (tid == 0) {
@@ -931,19 +991,19 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, LoadState& s
                 if (!(r == r) || isinf(r)) { ns.done = 1; ns.status = 2; }
                 else if (r <= b.tol) { ns.done = 1; ns.status = 0; }
                 else if (ns.iter >= b.max_iter) { ns.done = 1; ns.status = 1; }
-                if (ns.done && ns.iter < it.hist_cap) it.hist[ns.iter] = r;
+                if (slot == 0 && ns.done && ns.iter < it.hist_cap) it.hist[ns.iter] = r;
                 st = ns;
             }
-            wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S);
-            wg_zero<T>(it.ra.buf1, (int64_t)NC_ * it.S);
-            wg_mem_sync();
+            wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S, slot, k);
+            wg_zero<T>(it.ra.buf1, (int64_t)NC_ * it.S, slot, k);
+            group_sync(it, phase);
             if (st.done) break;
             stage_tol = fmax(b.tol, b.refine * st.resid);
             batch_stage<T, DIM>(it, it.ra, it.ax, it.sa_corr, it.t_real, it.t_spec, it.t_axis, st, sbase, stage_tol,
-                                b.max_iter, b.resid_period, true, red);
+                                b.max_iter, b.resid_period, true, red, slot, phase, rround);
         }
     }
-    if (tid == 0) {
+    if (tid == 0 && slot == 0) {
         *it.st = st;
         *it.restarts = nres;
     }
@@ -961,21 +1021,23 @@ __global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
         __syncthreads();
         const int q = qi;
         __syncthreads();
-        if (q >= b.n_items) return;
-        batch_item<T, DIM>(b, b.items[b.order[q]], st, st64, sbase, red);
+        if (q >= b.n_queue) return;
+        batch_item<T, DIM>(b, b.items[b.order[q]], b.qslot[q], st, st64, sbase, red);
         __syncthreads();
     }
 }
 
-__global__ void k_batch_reset(int* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+__global__ void k_batch_reset(int* counter, int* gcount, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *counter = 0;
+    if (i < n) gcount[i] = 0;
 }
 
 }  // namespace
 
-int ahom_launch_batch_reset(int* counter, int n_items, hipStream_t s) {
-    (void)n_items;
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
+int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t s) {
+    const int nb = n_items > 0 ? (n_items + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_batch_reset, dim3(nb), dim3(256), 0, s, counter, gcount, n_items);
     return AHOM_CHECK_LAUNCH();
 }
 
