@@ -140,6 +140,38 @@ def batch_workload(ahom):
                 precision="fp32 + fp64 residual, tol 1e-6", launch="one persistent kernel replayed from a HIP graph")
 
 
+def precision_workload(ahom, n=256):
+    """The precision workload: spheres on diag(n,n,n) (RSA, radii 0.03-0.08,
+    volume fraction 0.3), contrast E 100 : 1, nu 0.25, 6 Mandel loads, stop at
+    r <= 1e-6 (residual every 4th iteration).  Time to tolerance of the plain
+    FP64 scheme and of FP32 with FP64 restarts (device time, inputs resident),
+    and the per-entry C_eff difference between the two."""
+    import numpy as np
+    import synth
+    M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
+    c, r = synth.spheres_rsa(seed=3)
+    P = ahom.Pattern(M)
+    ph = synth.spheres_phase(P.points(), P.m, c, r)
+    lame = np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
+    out = {}
+    Cs = {}
+    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
+        S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, check_period=16, resid_period=4)
+        S.set_material(lame, ph)
+        C, it = S.effective_stiffness()
+        dev_ms, _ = S.last_timing()
+        out[name] = dict(ms=round(dev_ms, 1), iters=[int(v) for v in it])
+        if name == "fp32":
+            out[name]["restarts"] = int(S.last_restarts())
+        Cs[name] = C
+        print(f"[bench] precision {n}^3 {name}: {dev_ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
+        del S
+    err = np.abs(Cs["fp32"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
+    return dict(workload=f"spheres diag({n},{n},{n}), vf 0.3, contrast 100, 6 loads, tol 1e-6",
+                fp64=out["fp64"], fp32=out["fp32"], speedup_fp32_vs_fp64=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
+                ceff_max_entry_err_fp32_vs_fp64=float(err.max()), volume_fraction=float(ph.mean()))
+
+
 def learned_workload(ahom, ntrain, steps, n=64, ntest=4):
     """Learned initial guess on 64^3 ellipsoid microstructures: train on solves of
     the scheme, then time-to-1e-6 on held-out seeds from the zero guess (FP64 and
@@ -204,6 +236,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-member batched 2-D workload")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 FP32-vs-FP64 time to tolerance")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
     ap.add_argument("--learned-train", type=int, default=64, help="training solves for --learned")
@@ -290,6 +323,9 @@ def main():
 
     cpu = None
     batch = None
+    precision = None
+    if not args.no_ttt and not args.no_precision:
+        precision = precision_workload(ahom)
     if not args.no_batch:
         batch = batch_workload(ahom)
     learned = None
@@ -312,6 +348,7 @@ def main():
         device_ms_per_step=round(main_res["device_ms_per_step"], 4),
         time_to_1e6=ttt,
         time_to_1e6_resid_period=args.ttt_resid_period,
+        precision_256=precision,
         batch_2d=batch,
         learned_guess=learned,
     )
