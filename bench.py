@@ -140,6 +140,37 @@ def batch_workload(ahom):
                 precision="fp32 + fp64 residual, tol 1e-6", launch="one persistent kernel replayed from a HIP graph")
 
 
+def rank1_workload(ahom, steps=20):
+    """The Hashin structure on the rank-1 lattice of det M = 2^21 (generating
+    vector from the seeded search stored with the tests' goldens): FP64
+    throughput with the same 6 loads; the single Smith axis runs as split
+    (four-step) sub-axes with FP64-generated twiddles between them."""
+    import numpy as np
+    import synth
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "hashin_c2.json")))
+    M = np.array(json.load(open(os.path.join(ROOT, "tests", "golden", "rank1_c2.json")))["M"], dtype=np.int64)
+    P = ahom.Pattern(M)
+    geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
+    ph = synth.hashin_phase(P.points(), P.m, geom)
+    lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+    loads = mandel_loads()
+    out = {}
+    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
+        Sw = ahom.Solver(P, precision=prec, tol=0.0, max_iter=2, check_period=3)
+        Sw.set_material(lame, ph)
+        Sw.solve(loads)
+        del Sw
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=steps - 1, check_period=steps)
+        S.set_material(lame, ph)
+        t0 = time.perf_counter()
+        S.solve(loads)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out[name] = dict(value=round(P.m * loads.shape[0] / (ms * 1e-3), 1), ms_per_step=round(ms, 4))
+        print(f"[bench] rank-1 2^21 {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        del S
+    return dict(workload="Hashin structure on the rank-1 lattice det M = 2^21, 6 loads", M=M.tolist(), **out)
+
+
 def precision_workload(ahom, n=256):
     """The precision workload: spheres on diag(n,n,n) (RSA, radii 0.03-0.08,
     volume fraction 0.3), contrast E 100 : 1, nu 0.25, 6 Mandel loads, stop at
@@ -237,6 +268,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-member batched 2-D workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 FP32-vs-FP64 time to tolerance")
+    ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 lattice throughput")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
     ap.add_argument("--learned-train", type=int, default=64, help="training solves for --learned")
@@ -326,6 +358,9 @@ def main():
     precision = None
     if not args.no_ttt and not args.no_precision:
         precision = precision_workload(ahom)
+    rank1 = None
+    if not args.no_rank1 and not args.fp64_only:
+        rank1 = rank1_workload(ahom)
     if not args.no_batch:
         batch = batch_workload(ahom)
     learned = None
@@ -349,6 +384,7 @@ def main():
         time_to_1e6=ttt,
         time_to_1e6_resid_period=args.ttt_resid_period,
         precision_256=precision,
+        rank1_2e21=rank1,
         batch_2d=batch,
         learned_guess=learned,
     )
