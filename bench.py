@@ -368,7 +368,7 @@ def main():
         learned = learned_workload(ahom, args.learned_train, args.learned_steps)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.size)
+        cpu = cpu_baseline(args.size, n_iter=3)
 
     line = dict(
         metric=METRIC, value=round(main_res["value"], 1), unit="lattice-point updates/s", n_gpus=1,
