@@ -261,7 +261,7 @@ int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double m
  * workgroups lost a member at a pass barrier), mean_stress (9 doubles each);
  * any may be NULL.  use_graph != 0 replays the launch from a HIP graph
  * captured on the first call (on a stream of the batch's own).  Returns as
- * ahom_solve.
+ * ahom_solve; AHOM_E_DEVICE if an item has status 3.
  */
 int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iters, double* resid, double* mean_stress,
                      int* status, int use_graph);

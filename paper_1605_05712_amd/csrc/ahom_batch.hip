@@ -370,6 +370,10 @@ int ahom_batch::run(bool use_graph) {
     a.max_iter = cfg.max_iter;
     a.resid_period = cfg.resid_period;
     a.refine_on = refine_on() ? 1 : 0;
+    // group barrier wait limit: 4 s; AHOM_BATCH_GROUP_WAIT (ticks of the
+    // 100 MHz clock) lets a test force the time-out path from the host
+    a.group_wait = 400000000LL;
+    if (const char* w = getenv("AHOM_BATCH_GROUP_WAIT")) a.group_wait = std::max(0LL, atoll(w));
     hipStream_t s = use_graph ? gstream : stream;
     if (use_graph && !gexec) {
         BCHK(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal));
@@ -610,9 +614,11 @@ int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iter
                 ms9[(pos % 3) * 3 + pos / 3] = ls.mean[c];
             }
         }
-        if (ls.status == 2) ret = AHOM_E_DIVERGED;
+        if (ls.status == 3) ret = AHOM_E_DEVICE;
+        else if (ls.status == 2 && ret != AHOM_E_DEVICE) ret = AHOM_E_DIVERGED;
         else if ((ls.status == 1 || ls.resid > b->cfg.tol) && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
     }
+    if (ret == AHOM_E_DEVICE) ahom_set_error("a workgroup group of some batch item timed out at a pass barrier (status 3)");
     if (ret == AHOM_E_DIVERGED) ahom_set_error("residual diverged (some batch item)");
     return ret;
 }

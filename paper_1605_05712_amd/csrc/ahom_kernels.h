@@ -175,6 +175,7 @@ struct BatchArgs {
     double tol, refine;
     int max_iter, resid_period;
     int refine_on;                     // FP32 items: defect-correction restarts
+    long long group_wait;              // group barrier wait limit (100 MHz ticks)
 };
 
 // queue head and group barrier counters to zero (plain kernel: safe inside a captured graph)

@@ -795,12 +795,13 @@ __device__ __forceinline__ void wg_mem_sync() {
 // workgroups (any CUs and XCDs) an agent-scope release, an arrival on the
 // item's counter and a wait for the k arrivals of this phase, then an
 // agent-scope acquire.  Every workgroup of the group calls it the same number
-// of times (phase counts them).  The wait is bounded: after ~4 s without the
-// group's arrivals it marks the counter (bit 30) and this and all later
-// barriers of the item stop waiting, so a lost workgroup cannot hang the
-// launch (the item's result is then wrong and its status says so).
+// of times (phase counts them).  The wait is bounded (wait ticks of the
+// 100 MHz clock, 4 s by default): without the group's arrivals by then it
+// marks the counter (bit 30) and this and all later barriers of the item stop
+// waiting, so a lost workgroup cannot hang the launch (the item's result is
+// then wrong and its status says so).
 constexpr int kGroupAbort = 1 << 30;
-__device__ __forceinline__ void group_sync(const BatchItem& it, int& phase) {
+__device__ __forceinline__ void group_sync(const BatchItem& it, int& phase, long long wait) {
     if (it.k == 1) {
         wg_mem_sync();
         return;
@@ -815,7 +816,7 @@ __device__ __forceinline__ void group_sync(const BatchItem& it, int& phase) {
         for (;;) {
             const int c = __hip_atomic_load(it.gcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((c & kGroupAbort) || c >= target) break;
-            if (wall_clock64() - t0 > 400000000LL) {   // 100 MHz clock: 4 s
+            if (wall_clock64() - t0 > wait) {
                 __hip_atomic_fetch_or(it.gcount, kGroupAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -854,7 +855,7 @@ template <typename T, int DIM>
 __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisArgs* ax, const SpecArgs& sa,
                             int64_t t_real, int64_t t_spec, const int64_t* t_axis, LoadState& st,
                             const double* sig_base, double tol, int max_iter, int resid_period, bool record,
-                            double* red, int slot, int& phase, int& rround) {
+                            double* red, int slot, int& phase, int& rround, long long wait) {
     constexpr int NC_ = Comp<DIM>::N;
     const int tid = threadIdx.x;
     const int k = it.k;
@@ -867,7 +868,7 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             real_tile<T, DIM, REAL_TURN>(ra, st, 0, t, v);
             __syncthreads();
         }
-        group_sync(it, phase);
+        group_sync(it, phase, wait);
         const int par = (st.iter + 1) & 1;
         for (int a = 1; a <= it.D - 2; ++a) {
             const int64_t nt = (int64_t)NC_ * t_axis[a];
@@ -875,20 +876,20 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
                 axis_tile<T, -1>(ax[a], par, 0, (int)(u / t_axis[a]), u % t_axis[a]);
                 __syncthreads();
             }
-            group_sync(it, phase);
+            group_sync(it, phase, wait);
         }
         for (int64_t t = slot; t < t_spec; t += k) {
             spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_]);
             __syncthreads();
         }
-        group_sync(it, phase);
+        group_sync(it, phase, wait);
         for (int a = it.D - 2; a >= 1; --a) {
             const int64_t nt = (int64_t)NC_ * t_axis[a];
             for (int64_t u = slot; u < nt; u += k) {
                 axis_tile<T, +1>(ax[a], par, 0, (int)(u / t_axis[a]), u % t_axis[a]);
                 __syncthreads();
             }
-            group_sync(it, phase);
+            group_sync(it, phase, wait);
         }
         block_sum<NC_ + 1>(v, red);
         if (k > 1) {
@@ -896,7 +897,7 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             double* gp = it.gpart + (rround & 1) * (k * 8);
             if (tid == 0)
                 for (int c = 0; c <= NC_; ++c) gp[slot * 8 + c] = v[c];
-            group_sync(it, phase);
+            group_sync(it, phase, wait);
             if (tid == 0)
                 for (int c = 0; c <= NC_; ++c) {
                     double acc = 0.0;
@@ -949,14 +950,15 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
     const int tid = threadIdx.x;
     const int k = it.k;
+    const long long wait = b.group_wait;
     int phase = 0, rround = 0;
     wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_, slot, k);
     wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S, slot, k);
     if (tid == 0) st = LoadState{};
-    group_sync(it, phase);
+    group_sync(it, phase, wait);
     double stage_tol = b.refine_on ? fmax(b.tol, b.refine) : b.tol;
     batch_stage<T, DIM>(it, it.ra, it.ax, it.sa, it.t_real, it.t_spec, it.t_axis, st, nullptr, stage_tol, b.max_iter,
-                        b.resid_period, true, red, slot, phase, rround);
+                        b.resid_period, true, red, slot, phase, rround, b.group_wait);
     int nres = 0;
     if constexpr (sizeof(T) == 4) {
         while (b.refine_on && st.status == 0 && st.resid > b.tol) {
@@ -975,9 +977,9 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
             }
             wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S, slot, k);
             if (tid == 0) st64 = LoadState{};
-            group_sync(it, phase);
+            group_sync(it, phase, wait);
             batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64,
-                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround);
+                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait);
             ++nres;
             // correction stage: e(0) = 0, t(e(-1)) = -d (written by the FP64 pass)
             if (tid == 0) {
@@ -996,11 +998,11 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
             }
             wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S, slot, k);
             wg_zero<T>(it.ra.buf1, (int64_t)NC_ * it.S, slot, k);
-            group_sync(it, phase);
+            group_sync(it, phase, wait);
             if (st.done) break;
             stage_tol = fmax(b.tol, b.refine * st.resid);
             batch_stage<T, DIM>(it, it.ra, it.ax, it.sa_corr, it.t_real, it.t_spec, it.t_axis, st, sbase, stage_tol,
-                                b.max_iter, b.resid_period, true, red, slot, phase, rround);
+                                b.max_iter, b.resid_period, true, red, slot, phase, rround, b.group_wait);
         }
     }
     if (tid == 0 && slot == 0) {
