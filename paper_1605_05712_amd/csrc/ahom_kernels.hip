@@ -99,6 +99,22 @@ template <int R, int DIR, typename C> __device__ __forceinline__ void bfly_odd(C
     for (int k = 0; k < R; ++k) v[k] = out[k];
 }
 
+// Division by a divisor that is fixed for a whole tile: floor(n / d) as one
+// high-half product with m = floor((2^32 - 1) / d) + 1 = 2^32 / d + e,
+// 0 <= e < 1.  Then n m / 2^32 = n / d + n e / 2^32, and the floor is exact
+// when n d < 2^32 (the fraction of n / d is at most 1 - 1/d).  Used only for
+// positions inside an LDS tile and divisors that are tile extents (both below
+// 2^16, as a tile holds fewer than 2^16 elements); d = 1 wraps m to 0.
+struct UDiv {
+    uint32_t d, m;
+    __device__ __forceinline__ explicit UDiv(int dd) : d((uint32_t)dd), m(0xFFFFFFFFu / (uint32_t)dd + 1u) {}
+    __device__ __forceinline__ int div(int n) const { return m ? (int)__umulhi((uint32_t)n, m) : n; }
+    __device__ __forceinline__ void divmod(int n, int& q, int& r) const {
+        q = div(n);
+        r = n - q * (int)d;
+    }
+};
+
 // One radix-R Stockham stage over `total` butterflies of all columns.
 template <int R, int DIR, typename C>
 __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__ dst, int ncol, int L, int CS, int Ns,
@@ -106,10 +122,11 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
     const int nb = L / R;
     const int total = ncol * nb;
     const int tstep = L / (Ns * R);
+    const UDiv by_nb(nb), by_ns(Ns);
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int j = t / nb;
-        const int b = t - j * nb;
-        const int k = b % Ns;
+        int j, b, bq, k;
+        by_nb.divmod(t, j, b);
+        by_ns.divmod(b, bq, k);
         C v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = src[j * CS + b + r * nb];
@@ -124,7 +141,7 @@ __device__ __forceinline__ void stage(const C* __restrict__ src, C* __restrict__
         else if constexpr (R == 4) bfly4<DIR>(v);
         else if constexpr (R == 8) bfly8<DIR>(v);
         else bfly_odd<R, DIR>(v);
-        const int o = (b / Ns) * Ns * R + k;
+        const int o = bq * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) dst[j * CS + o + r * Ns] = v[r];
     }
@@ -152,8 +169,10 @@ __device__ void lds_fft(C* buf, C* tmp, int ncol, int CS, const AxisDesc& ax, co
         Ns *= R;
     }
     if (src != buf) {
+        const UDiv by_l(L);
         for (int e = threadIdx.x; e < ncol * L; e += blockDim.x) {
-            const int j = e / L, l = e - j * L;
+            int j, l;
+            by_l.divmod(e, j, l);
             buf[j * CS + l] = src[j * CS + l];
         }
         __syncthreads();
@@ -249,6 +268,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     const int ncol = (int)((I - c0) < a.NC ? (I - c0) : a.NC);
     const int CS = a.CS;
     const int tid = threadIdx.x;
+    const UDiv by_nc(a.NC);
 
     C* Z = lds_base<C>();
     C* tmp = Z + NP * a.NC * CS;
@@ -273,7 +293,8 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
 #pragma unroll
         for (int q = 0; q < GEPL; ++q) {
             const int e = tid + q * (int)blockDim.x;
-            const int n = e / a.NC, j = e - n * a.NC;
+            int n, j;
+            by_nc.divmod(e, n, j);
             const bool ok = e < L * a.NC && j < ncol;
             const int64_t pt = ok ? (int64_t)n * I + c0 + j : c0;
             if (a.lame_pts) {
@@ -295,7 +316,8 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     if (MODE != REAL_FROM_REAL) {
         // ---- gather the half spectra and form packed full spectra Z_p = A + i B
         for (int e = tid; e < H * a.NC; e += blockDim.x) {
-            const int k = e / a.NC, j = e - k * a.NC;
+            int k, j;
+            by_nc.divmod(e, k, j);
             if (j >= ncol) continue;
             const int64_t col = c0 + j;
             C w = C{(T)1, (T)0};
@@ -319,7 +341,8 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     if (MODE == REAL_TO_REAL) {
         double* out = a.real_io + (int64_t)load * NC_ * P.m;
         for (int e = tid; e < L * a.NC; e += blockDim.x) {
-            const int n = e / a.NC, j = e - n * a.NC;
+            int n, j;
+            by_nc.divmod(e, n, j);
             if (j >= ncol) continue;
             const int64_t pt = (int64_t)n * I + c0 + j;
 #pragma unroll
@@ -362,12 +385,14 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
 #pragma unroll
             for (int q = 0; q < GEPL; ++q) {
                 const int e = tid + q * (int)blockDim.x;
-                const int n = e / a.NC, j = e - n * a.NC;
+                int n, j;
+                by_nc.divmod(e, n, j);
                 if (e < L * a.NC && j < ncol) point(n, j, lamq[q], muq[q]);
             }
         } else {
             for (int e = tid; e < L * a.NC; e += blockDim.x) {
-                const int n = e / a.NC, j = e - n * a.NC;
+                int n, j;
+                by_nc.divmod(e, n, j);
                 if (j >= ncol) continue;
                 const int64_t pt = (int64_t)n * I + c0 + j;
                 if (a.lame_pts) {
@@ -382,7 +407,8 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
         const double* in = a.real_io + (int64_t)load * NC_ * P.m;
         const double* eb = a.eps_bar + (int64_t)load * NC_;
         for (int e = tid; e < L * a.NC; e += blockDim.x) {
-            const int n = e / a.NC, j = e - n * a.NC;
+            int n, j;
+            by_nc.divmod(e, n, j);
             if (j >= ncol) continue;
             const int64_t pt = (int64_t)n * I + c0 + j;
 #pragma unroll
@@ -400,7 +426,8 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     // ---- split the packed spectra and store the half spectra
     const T scale = MODE == REAL_FROM_REAL ? (T)(1.0 / L) : (T)1;
     for (int e = tid; e < H * a.NC; e += blockDim.x) {
-        const int k = e / a.NC, j = e - k * a.NC;
+        int k, j;
+        by_nc.divmod(e, k, j);
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
         C w = C{(T)1, (T)0};
@@ -463,10 +490,11 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
     C* twl = stage_twiddles(tmp + a.NC * CS, tw, L);
     const bool rowmajor = I >= a.NC;
     const int tid = threadIdx.x;
+    const UDiv by_nc(a.NC), by_l(L);
 
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         int j, l;
-        if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
+        if (rowmajor) by_nc.divmod(e, l, j); else by_l.divmod(e, j, l);
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
         int64_t cq, cr;
@@ -480,7 +508,7 @@ __device__ void axis_tile(const AxisArgs& a, int par, int load, int field, int64
     lds_fft<DIR>(X, tmp, ncol, CS, ax, twl);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         int j, l;
-        if (rowmajor) { l = e / a.NC; j = e - l * a.NC; } else { j = e / L; l = e - j * L; }
+        if (rowmajor) by_nc.divmod(e, l, j); else by_l.divmod(e, j, l);
         if (j >= ncol) continue;
         const int64_t col = c0 + j;
         int64_t cq, cr;
@@ -523,9 +551,11 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     C* F = lds_base<C>();
     C* tmp = F + NC_ * a.NC * CS;
     C* twl = stage_twiddles(tmp + a.NC * CS, tw, L);
+    const UDiv by_l(L);
 
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
-        const int j = e / L, l = e - j * L;
+        int j, l;
+        by_l.divmod(e, j, l);
         if (j >= ncol) continue;
         const int64_t addr = (c0 + j) * L + l;
 #pragma unroll
@@ -549,7 +579,8 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         for (int s2 = 0; s2 < 3; ++s2) Ad[i2][s2] = (i2 < DIM && s2 < DIM) ? (double)P.fm.A[i2][s2] : 0.0;
     const bool small_cols = ncols < (int64_t(1) << 31);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
-        const int j = e / L, l = e - j * L;
+        int j, l;
+        by_l.divmod(e, j, l);
         if (j >= ncol) continue;
         // position -> kappa (32-bit division while the column count fits)
         int64_t kpos[AHOM_MAX_AXES];
@@ -709,7 +740,8 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     __syncthreads();
     for (int f = 0; f < NC_; ++f) lds_fft<+1>(F + f * a.NC * CS, tmp, ncol, CS, ax, twl);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
-        const int j = e / L, l = e - j * L;
+        int j, l;
+        by_l.divmod(e, j, l);
         if (j >= ncol) continue;
         const int64_t addr = (c0 + j) * L + l;
 #pragma unroll
