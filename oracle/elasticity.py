@@ -35,6 +35,11 @@ Readings of the paper applied here
   |eps(n+1) - eps(n)| / |eps(0)|, is reported beside it.
 * Plane strain in 2-D: d = 2 tensors with the in-plane part of the 3-D
   isotropic law.
+* Transformed patterns P_L(M) (Def. 3.3): the cell is L[-1/2,1/2)^d and the
+  point y of P(M) sits at x = L y.  A function periodic on that cell is a
+  sum of exp(2 pi i h^T L^{-1} x), so the wave vector of class h is L^{-T} h;
+  Gamma0 and the residual's xi use it.  Everything else (transform, phases
+  per point, means) is that of P(M).
 """
 from __future__ import annotations
 
@@ -164,9 +169,17 @@ class SchemeResult:
     cauchy: list = field(default_factory=list)
 
 
+def wave_vectors(H, cell=None):
+    """Rows L^{-T} h of the integer frequencies H (Def. 3.3); H itself for P(M)."""
+    Hf = np.asarray(H, dtype=np.float64)
+    if cell is None:
+        return Hf
+    return Hf @ np.linalg.inv(np.asarray(cell, dtype=np.float64))
+
+
 def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=None,
-                 transform=None, rule="hermitian", fixed_iters=None):
-    """Algorithm 1 on P(M) with the equilibrium-residual stop.
+                 transform=None, rule="hermitian", fixed_iters=None, cell=None):
+    """Algorithm 1 on P(M) (or on P_L(M) with cell = L) with the equilibrium-residual stop.
 
     phase: (m,) ints in the transform's point order; lame: (n_phase, 2) rows
     (lambda, mu); lame0 = (lambda0, mu0); eps_bar: (d, d) macroscopic strain;
@@ -177,6 +190,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
     d = len(as_int_matrix(M))
     m = T.m
     H = np.asarray(T.freqs, dtype=np.int64)
+    K = wave_vectors(H, cell)
     zero = np.flatnonzero(np.all(H == 0, axis=1))[0]
     active = active_classes(M, H, rule)
     upd = active.copy()
@@ -195,7 +209,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
     while True:
         sigma = apply_phases(tensors, phase, eps)
         sig_hat = T.forward(sigma)
-        r = equilibrium_residual(sig_hat, H, active, zero)
+        r = equilibrium_residual(sig_hat, K, active, zero)
         hist.append(r)
         r0 = r if r0 is None else r0
         mean = np.sum(sigma, axis=2) / m
@@ -209,7 +223,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
         tau = sigma - contract(C0, eps)
         tau_hat = T.forward(tau)
         eps_hat = np.zeros_like(tau_hat)
-        eps_hat[:, :, upd] = gamma0_apply(C0, H[upd], tau_hat[:, :, upd])
+        eps_hat[:, :, upd] = gamma0_apply(C0, K[upd], tau_hat[:, :, upd])
         eps_hat[:, :, zero] = eps_bar
         new = T.inverse(eps_hat)
         if rule == "hermitian":
@@ -226,13 +240,13 @@ def unit_loads(d):
     return [from_mandel(np.eye(k)[i], d) for i in range(k)]
 
 
-def effective_stiffness(M, phase, lame, lame0, tol=1e-10, max_iter=5000, transform=None, rule="hermitian"):
+def effective_stiffness(M, phase, lame, lame0, tol=1e-10, max_iter=5000, transform=None, rule="hermitian", cell=None):
     """C_eff in Mandel form: column k is Mandel(<sigma>) for unit load k (Def. 3.1)."""
     T = transform or make_transform(M)
     d = len(as_int_matrix(M))
     cols, runs = [], []
     for E in unit_loads(d):
-        res = basic_scheme(M, phase, lame, lame0, E, tol=tol, max_iter=max_iter, transform=T, rule=rule)
+        res = basic_scheme(M, phase, lame, lame0, E, tol=tol, max_iter=max_iter, transform=T, rule=rule, cell=cell)
         cols.append(to_mandel(res.mean_stress))
         runs.append(res)
     return np.array(cols).T, runs
