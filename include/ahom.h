@@ -99,6 +99,20 @@ const char* ahom_last_error(void);
  * AHOM_E_UNSUPPORTED_SIZE.  Host-only: needs no GPU.
  */
 int ahom_pattern_create(int d, const int64_t* M, ahom_pattern** out);
+
+/*
+ * Transformed pattern P_L(M) = L Lambda(M) within the cell L [-1/2,1/2)^d
+ * (Def. 3.3): the periodic cell is spanned by the columns of the real regular
+ * matrix L (d*d, row-major, host memory, copied).  Point i sits at L y_i with
+ * y_i as ahom_pattern_points gives it; the frequency of class h is L^{-T} h,
+ * so Gamma0 and the equilibrium residual use xi parallel to L^{-T} h.  The
+ * Smith form, the point and frequency orders, the transforms and all solver
+ * calls are those of P(M); strains, stresses and C_eff are in the physical
+ * (x = L y) frame.  L = I gives P(M) bit for bit.
+ * Errors: those of ahom_pattern_create, AHOM_E_ARG (null, non-finite entry),
+ * AHOM_E_SINGULAR (|det L| <= 1e-12 max|L_ij|^d).  Host-only.
+ */
+int ahom_pattern_create_transformed(int d, const int64_t* M, const double* L, ahom_pattern** out);
 void ahom_pattern_destroy(ahom_pattern* p);
 
 /*

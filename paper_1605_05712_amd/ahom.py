@@ -39,7 +39,8 @@ MEM_DEVICE = 1
 NYQUIST_HERMITIAN = 0
 
 EXPORTS = [
-    "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_destroy", "ahom_pattern_info",
+    "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_create_transformed", "ahom_pattern_destroy",
+    "ahom_pattern_info",
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
@@ -67,6 +68,7 @@ _ip = ct.POINTER(ct.c_int)
 _lib.ahom_version.restype = ct.c_int
 _lib.ahom_last_error.restype = ct.c_char_p
 _lib.ahom_pattern_create.argtypes = [ct.c_int, _i64p, ct.POINTER(_P)]
+_lib.ahom_pattern_create_transformed.argtypes = [ct.c_int, _i64p, _dp, ct.POINTER(_P)]
 _lib.ahom_pattern_destroy.argtypes = [_P]
 _lib.ahom_pattern_destroy.restype = None
 _lib.ahom_pattern_info.argtypes = [_P, _i64p, _ip, _i64p, _i64p, _i64p]
@@ -199,16 +201,28 @@ class DeviceArray:
 
 
 class Pattern:
-    """P(M) with the library's Smith-normal-form addressing (host only)."""
+    """P(M) with the library's Smith-normal-form addressing (host only).
 
-    def __init__(self, M):
+    L: optional real d x d cell matrix of the transformed pattern P_L(M)
+    (Def. 3.3); points sit at L y, frequencies at L^{-T} h.
+    """
+
+    def __init__(self, M, L=None):
         M = np.ascontiguousarray(np.asarray(M, dtype=np.int64))
         if M.ndim != 2 or M.shape[0] != M.shape[1]:
             raise ValueError("M must be square")
         self.d = M.shape[0]
         self.M = M
         h = _P()
-        _check(_lib.ahom_pattern_create(self.d, _ptr(M, ct.c_int64), ct.byref(h)))
+        if L is None:
+            self.L = None
+            _check(_lib.ahom_pattern_create(self.d, _ptr(M, ct.c_int64), ct.byref(h)))
+        else:
+            Lm = np.ascontiguousarray(np.asarray(L, dtype=np.float64))
+            if Lm.shape != (self.d, self.d):
+                raise ValueError("L must be d x d")
+            self.L = Lm
+            _check(_lib.ahom_pattern_create_transformed(self.d, _ptr(M, ct.c_int64), _ptr(Lm, ct.c_double), ct.byref(h)))
         self._h = h
         m = ct.c_int64()
         dM = ct.c_int()

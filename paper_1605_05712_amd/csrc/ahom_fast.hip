@@ -1123,13 +1123,13 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         if (r >= emax_d) r -= emax_d;
         return r;
     };
-    double Ad[3][3], MTd[3][3], stepd[3];
+    double Ad[3][3], Gd[3][3], stepd[3];
 #pragma unroll
     for (int i2 = 0; i2 < 3; ++i2)
 #pragma unroll
         for (int r2 = 0; r2 < 3; ++r2) {
             Ad[i2][r2] = (i2 < DIM && r2 < DIM) ? (double)P.fm.A[i2][r2] : 0.0;
-            MTd[i2][r2] = (i2 < DIM && r2 < DIM) ? (double)P.fm.MT[i2][r2] : 0.0;
+            Gd[i2][r2] = (i2 < DIM && r2 < DIM) ? P.fm.G[i2][r2] : 0.0;
         }
 #pragma unroll
     for (int i2 = 0; i2 < 3; ++i2) {
@@ -1329,7 +1329,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
             for (int i = 0; i < DIM; ++i) {
                 hd[i] = 0.0;
 #pragma unroll
-                for (int r = 0; r < DIM; ++r) hd[i] += MTd[i][r] * Nd[r];
+                for (int r = 0; r < DIM; ++r) hd[i] += Gd[i][r] * Nd[r];
             }
             double hn = 0.0;
 #pragma unroll

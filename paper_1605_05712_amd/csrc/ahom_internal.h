@@ -41,6 +41,10 @@ struct FreqMap {
     int64_t A[3][3];                // A[i][s] = (Q^{-T})_{is} (emax / e_s) mod emax
     int64_t MT[3][3];               // M^T
     int64_t e[3];                   // elementary divisors
+    // Direction map of Gamma0 and of the residual: xi is parallel to G N.
+    // G = M^T (exact integers) on P(M); G = L^{-T} M^T on the transformed
+    // pattern P_L(M) of Def. 3.3, whose frequencies are L^{-T} h.
+    double G[3][3];
 };
 
 struct Plan {

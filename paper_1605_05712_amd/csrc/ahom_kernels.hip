@@ -643,7 +643,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         }
         double hd[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < DIM; ++i)
-            for (int q = 0; q < DIM; ++q) hd[i] += (double)P.fm.MT[i][q] * (double)N[q];
+            for (int q = 0; q < DIM; ++q) hd[i] += P.fm.G[i][q] * (double)N[q];
         double hn = 0.0;
         for (int i = 0; i < DIM; ++i) hn += hd[i] * hd[i];
         hn = 1.0 / sqrt(hn);

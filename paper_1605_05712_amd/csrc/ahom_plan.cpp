@@ -271,6 +271,7 @@ int ahom_build_plan_ex(const SmithForm& sf, int lmax, int max_radix, Plan* plan,
             if (r < 0) r += fm.emax;
             fm.A[i][s] = r;
             fm.MT[i][s] = sf.M[s][i];
+            fm.G[i][s] = (double)sf.M[s][i];
         }
     // canonical strides
     int64_t stride = 1;

@@ -112,3 +112,20 @@ def test_errors():
     with pytest.raises(ahom.AhomError) as ex:
         ahom.Pattern(np.eye(4, dtype=np.int64))
     assert ex.value.code == ahom.AHOM_E_ARG
+
+
+def test_transformed_pattern_host_side():
+    """P_L(M) keeps the Smith form and the canonical orders of P(M); bad cells are errors."""
+    M = [[12, 0, 0], [0, 6, 0], [3, 0, 4]]
+    P = ahom.Pattern(M)
+    PL = ahom.Pattern(M, L=[[1.0, 0.2, 0.0], [0.0, 0.9, -0.1], [0.3, 0.0, 1.1]])
+    assert PL.m == P.m and np.array_equal(PL.e, P.e)
+    assert np.array_equal(PL.points(), P.points()) and np.array_equal(PL.freqs(), P.freqs())
+    for bad, code in (([[1.0, 2.0], [0.5, 1.0]], ahom.AHOM_E_SINGULAR),
+                      ([[1.0, np.nan], [0.0, 1.0]], ahom.AHOM_E_ARG),
+                      ([[0.0, 0.0], [0.0, 0.0]], ahom.AHOM_E_SINGULAR)):
+        with pytest.raises(ahom.AhomError) as ex:
+            ahom.Pattern([[8, 0], [0, 8]], L=bad)
+        assert ex.value.code == code
+    with pytest.raises(ValueError):
+        ahom.Pattern([[8, 0], [0, 8]], L=np.eye(3))
