@@ -140,6 +140,59 @@ def batch_workload(ahom):
                 precision="fp32 + fp64 residual, tol 1e-6", launch="one persistent kernel replayed from a HIP graph")
 
 
+def sweep_workload(ahom):
+    """The shear sweep of Sec. 5.1 (eq. M-shear): M_{j,k,alpha} for j in {7,8,9},
+    alpha in {0,1}, k in 16 {-32..32}, plus the rotated grids M~_j (393 members,
+    2^14 / 2^13 points, one point along x3) on the coated ellipse of Example
+    4.1 under its Hashin load eps0, FP64 to tol 1e-9, all in one persistent
+    launch.  e_eff(M) against the stored closed form (written by the oracle)."""
+    import numpy as np
+    import synth
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "sweep_example_4_1.json")))
+    geom = dict(c=np.array(g["c12"] + [math.inf]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
+    lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+    eps0 = np.array(g["eps0"])
+    ref = np.array(g["ceff_eps0"])
+    names, Ms = [], []
+    for j in (7, 8, 9):
+        for alpha in (0, 1):
+            for k in range(-512, 513, 16):
+                names.append((j, alpha, k))
+                Ms.append([[2 ** j, alpha * k, 0], [(1 - alpha) * k, 2 ** (14 - j), 0], [0, 0, 1]])
+    for j in (7, 8, 9):
+        names.append((j, "rot", 0))
+        Ms.append([[2 ** (j - 1), 2 ** (13 - j), 0], [-2 ** (j - 1), 2 ** (13 - j), 0], [0, 0, 1]])
+    B = ahom.Batch(Ms, precision=ahom.FP64, tol=1e-9, max_iter=5000)
+    pts = 0
+    for i in range(len(Ms)):
+        m, _ = B.info(i)
+        pts += m
+        B.set_material(i, lame, synth.hashin_phase(B.points(i), m, geom))
+    print("[bench] sweep: tuning plans for 393 members", file=sys.stderr, flush=True)
+    B.solve(eps0[None], use_graph=True)
+    out = B.solve(eps0[None], use_graph=True)
+    ms, _ = B.last_timing()
+    ms_pts = np.array([B.info(i)[0] for i in range(len(Ms))])
+    upd = float(np.sum(ms_pts * out["iters"][:, 0]))
+    ceff = out["mean_stress"][:, 0]
+    e = np.linalg.norm(ceff - ref[None], axis=(1, 2)) / np.linalg.norm(ref)
+    idx = {n: i for i, n in enumerate(names)}
+    curves = {}
+    for j in (7, 8, 9):
+        for alpha in (0, 1):
+            ks = np.arange(-512, 513, 16)
+            ev = np.array([e[idx[(j, alpha, int(k))]] for k in ks])
+            curves[f"j{j}_a{alpha}"] = dict(k0=float(ev[ks == 0][0]), min=float(ev.min()), k_min=int(ks[ev.argmin()]),
+                                             max=float(ev.max()), k_max=int(ks[ev.argmax()]))
+        curves[f"rot_j{j}"] = float(e[idx[(j, "rot", 0)]])
+    print(f"[bench] sweep: {ms:.1f} ms device, {upd:.3e} point updates", file=sys.stderr, flush=True)
+    return dict(workload="Sec. 5.1 shear sweep, Example 4.1 ellipse, 393 members x 1 load, FP64 tol 1e-9",
+                members=len(Ms), points=int(pts), device_ms=round(ms, 2), point_updates=upd,
+                updates_per_s=round(upd / (ms * 1e-3), 1), iters_min=int(out["iters"].min()),
+                iters_max=int(out["iters"].max()), converged=bool(np.all(out["item_status"] == 0)),
+                e_eff=curves, launch="one persistent kernel replayed from a HIP graph")
+
+
 def rank1_workload(ahom, steps=20):
     """The Hashin structure on the rank-1 lattice of det M = 2^21 (generating
     vector from the seeded search stored with the tests' goldens): FP64
@@ -269,6 +322,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-member batched 2-D workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 FP32-vs-FP64 time to tolerance")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 lattice throughput")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. 5.1 shear sweep (one batched launch)")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
     ap.add_argument("--learned-train", type=int, default=64, help="training solves for --learned")
@@ -363,6 +417,9 @@ def main():
         rank1 = rank1_workload(ahom)
     if not args.no_batch:
         batch = batch_workload(ahom)
+    sweep = None
+    if not args.no_sweep and not args.no_batch:
+        sweep = sweep_workload(ahom)
     learned = None
     if args.learned:
         learned = learned_workload(ahom, args.learned_train, args.learned_steps)
@@ -386,6 +443,7 @@ def main():
         precision_256=precision,
         rank1_2e21=rank1,
         batch_2d=batch,
+        shear_sweep=sweep,
         learned_guess=learned,
     )
     print(json.dumps(line))
