@@ -24,7 +24,7 @@ import synth
 from oracle import closed_forms as CF
 from oracle import elasticity as E
 from oracle.dft import make_transform
-from tests.gpu_util import perm_between, tensors_to_fields, rel_err
+from tests.gpu_util import perm_between, fields_to_tensors, tensors_to_fields, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -138,3 +138,41 @@ def test_shear_sweep_in_one_batched_launch():
         r = E.basic_scheme(Ms[i], ph, lame, E.default_reference(lame), h["eps0"], tol=1e-9, max_iter=5000, transform=T)
         assert r.status == 0
         assert rel_err(ceff[i], r.mean_stress) < 1e-7, key
+
+
+def test_subsampling_sec_5_2():
+    """Sec. 5.2: the laminate with normal (1, 1/2) (integer form (2, 1)) on the full
+    grid M_a = diag(64, 64), the directional rank-1 subpattern M_b = [[64, 32], [0, 1]]
+    and the pixel subgrid M_c = diag(8, 8) (64 points each for b and c), FP64 to
+    1e-9 under eps0 = e_11.  GPU = oracle (iterations, fields); e_l2 against the
+    piecewise-constant closed-form strain at the points, e_eff against Milton's
+    formula.  On M_b every frequency is parallel to the normal: exact."""
+    q = (2, 1)
+    n = np.array(q, dtype=np.float64)
+    LAM = np.array(synth.LAMINATE_LAME)
+    eps0 = E.unit_loads(2)[0]
+    e1, e2, _ = CF.laminate_jump(*LAM, 0.5, n, eps0)
+    ref_eff = E.from_mandel(CF.laminate_milton(*LAM, 0.5, n) @ E.to_mandel(eps0), 2)
+    res = {}
+    for name, M in (("a", [[64, 0], [0, 64]]), ("b", [[64, 32], [0, 1]]), ("c", [[8, 0], [0, 8]])):
+        say("subsampling", name, M)
+        P = ahom.Pattern(M)
+        pts = P.points()
+        ph = synth.laminate_phase(pts, P.m, q=q)
+        S = ahom.Solver(P, tol=1e-9, max_iter=3000)
+        S.set_material(LAM, ph)
+        out = S.solve(np.pad(eps0, ((0, 1), (0, 1)))[None], want_strain=True)
+        T = make_transform(M)
+        pho = synth.laminate_phase(T.points, T.m, q=q)
+        r = E.basic_scheme(M, pho, LAM, E.default_reference(LAM), eps0, tol=1e-9, max_iter=3000, transform=T)
+        assert out["iters"][0] == r.iters
+        ip = perm_between(T.points, pts)
+        assert rel_err(out["strain"][0], tensors_to_fields(r.eps[:, :, ip])) < 1e-9
+        exact = np.where(ph[None, None, :] == 0, e1[:, :, None], e2[:, :, None])
+        e_l2 = E.error_l2(fields_to_tensors(out["strain"][0], 2), exact)
+        e_eff = E.error_eff(out["mean_stress"][0][:2, :2], ref_eff)
+        res[name] = (int(out["iters"][0]), e_l2, e_eff)
+        print("[subsampling] M_%s: m %d, iterations %d, e_l2 %.4f, e_eff %.4f" % (name, P.m, *res[name]), flush=True)
+    assert res["b"][1] < 1e-12 and res["b"][2] < 1e-12
+    assert res["c"][1] > res["a"][1] and res["c"][2] > res["a"][2]
+    assert res["b"][0] < res["a"][0]
