@@ -206,6 +206,12 @@ def rank1_workload(ahom, steps=20):
     geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
     ph = synth.hashin_phase(P.points(), P.m, geom)
     lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+    out = _throughput(ahom, P, lame, ph, steps, "rank-1 2^21")
+    return dict(workload="Hashin structure on the rank-1 lattice det M = 2^21, 6 loads", M=M.tolist(), **out)
+
+
+def _throughput(ahom, P, lame, ph, steps, label):
+    """FP64 and FP32 updates/s of `steps` fixed iterations with the 6 Mandel loads."""
     loads = mandel_loads()
     out = {}
     for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
@@ -219,9 +225,28 @@ def rank1_workload(ahom, steps=20):
         S.solve(loads)
         ms = (time.perf_counter() - t0) * 1e3 / steps
         out[name] = dict(value=round(P.m * loads.shape[0] / (ms * 1e-3), 1), ms_per_step=round(ms, 4))
-        print(f"[bench] rank-1 2^21 {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+        print(f"[bench] {label} {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
         del S
-    return dict(workload="Hashin structure on the rank-1 lattice det M = 2^21, 6 loads", M=M.tolist(), **out)
+    return out
+
+
+# cell matrix of the transformed-pattern workload (sheared and stretched)
+CELL = [[1.0, 0.3, 0.0], [0.0, 1.1, 0.2], [0.1, 0.0, 0.9]]
+
+
+def transformed_workload(ahom, n=128, steps=20):
+    """The Hashin workload on the transformed pattern P_L(diag(n,n,n)) (Def. 3.3)
+    in the cell CELL: FP64 and FP32 throughput with the same 6 loads (Gamma0
+    at L^{-T} h; the same kernels as the plain pattern)."""
+    import numpy as np
+    import synth
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "hashin_c2.json")))
+    P = ahom.Pattern([[n, 0, 0], [0, n, 0], [0, 0, n]], L=CELL)
+    geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
+    ph = synth.hashin_phase(P.points(), P.m, geom)
+    lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+    out = _throughput(ahom, P, lame, ph, steps, f"transformed {n}^3")
+    return dict(workload=f"Hashin structure on P_L(diag({n},{n},{n})), 6 loads", L=CELL, **out)
 
 
 def precision_workload(ahom, n=256):
@@ -321,7 +346,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-member batched 2-D workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 FP32-vs-FP64 time to tolerance")
-    ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 lattice throughput")
+    ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 lattice and transformed-cell throughput")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. 5.1 shear sweep (one batched launch)")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
@@ -413,8 +438,10 @@ def main():
     if not args.no_ttt and not args.no_precision:
         precision = precision_workload(ahom)
     rank1 = None
+    transformed = None
     if not args.no_rank1 and not args.fp64_only:
         rank1 = rank1_workload(ahom)
+        transformed = transformed_workload(ahom, args.size)
     if not args.no_batch:
         batch = batch_workload(ahom)
     sweep = None
@@ -442,6 +469,7 @@ def main():
         time_to_1e6_resid_period=args.ttt_resid_period,
         precision_256=precision,
         rank1_2e21=rank1,
+        transformed_cell=transformed,
         batch_2d=batch,
         shear_sweep=sweep,
         learned_guess=learned,
