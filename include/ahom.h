@@ -234,6 +234,19 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
  */
 int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
 
+/*
+ * Cauchy measure of Sec. 5.2 beside the residual (reported, not a stop rule):
+ * c(n) = |eps(n+1) - eps(n)|_{l2(P(M))} / |eps(0)|, Frobenius norms summed over
+ * the points, |eps(0)| = sqrt(m) |eps_bar|_F (the start without an initial
+ * guess; the same normalisation is kept with one).  Evaluated on the
+ * iterations whose residual is evaluated (-1 elsewhere) from the traction
+ * step the residual uses: on active frequencies eps_hat(n+1) - eps_hat(n) =
+ * -sym(xi (x) K(xi)^{-1} (t(n) - t(n-1))).  With a user initial guess that is
+ * not compatible, c(0) measures against its compatible part.  Same output
+ * convention as ahom_solver_history.
+ */
+int ahom_solver_cauchy_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
+
 /* ------------------------------------------------------------------------
  * Batched solves: Algorithm 1 on many patterns P(M_i) of uneven size (same
  * dimension) in one persistent device launch.  A workgroup takes one

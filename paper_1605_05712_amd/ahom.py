@@ -44,7 +44,7 @@ EXPORTS = [
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
-    "ahom_solver_pass_times", "ahom_batch_create", "ahom_batch_destroy", "ahom_batch_member_info",
+    "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_destroy", "ahom_batch_member_info",
     "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
     "ahom_batch_strain", "ahom_batch_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
     "ahom_guess_create", "ahom_guess_destroy", "ahom_guess_num_params", "ahom_guess_get_params", "ahom_guess_set_params",
@@ -86,6 +86,7 @@ _lib.ahom_effective_stiffness.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_restarts.argtypes = [_P, _ip]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
+_lib.ahom_solver_cauchy_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
 _lib.ahom_batch_create.argtypes = [ct.c_int, ct.c_int, _i64p, _P, ct.POINTER(_P)]
 _lib.ahom_batch_destroy.argtypes = [_P]
@@ -355,6 +356,13 @@ class Solver:
         out = np.zeros(cap, np.float64)
         cnt = ct.c_int()
         _check(_lib.ahom_solver_history(self._h, load, _ptr(out, ct.c_double), cap, ct.byref(cnt)))
+        return out[:cnt.value]
+
+    def cauchy_history(self, load=0, cap=100000):
+        """|eps(n+1) - eps(n)| / |eps(0)| per iteration (-1 where not evaluated)."""
+        out = np.zeros(cap, np.float64)
+        cnt = ct.c_int()
+        _check(_lib.ahom_solver_cauchy_history(self._h, load, _ptr(out, ct.c_double), cap, ct.byref(cnt)))
         return out[:cnt.value]
 
     def __del__(self):

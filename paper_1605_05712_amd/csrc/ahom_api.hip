@@ -138,6 +138,9 @@ struct ahom_solver {
     double* d_sig = nullptr;
     double* d_res = nullptr;
     double* d_hist = nullptr;
+    double* d_cau = nullptr;       // [load][wg] Cauchy-measure partial sums
+    double* d_chist = nullptr;     // [load][hist_cap] Cauchy measure per iteration
+    double* d_norm0 = nullptr;     // [load] |eps(0)| of the plain start
     double* d_epsbar = nullptr;
     double* d_real = nullptr;
     int hist_cap = 0;
@@ -209,7 +212,7 @@ struct ahom_solver {
 
     int release_buffers() {
         dfree(d_buf0); dfree(d_buf1); dfree(d_tbuf); dfree(d_st); dfree(d_sig);
-        dfree(d_res); dfree(d_hist); dfree(d_epsbar); dfree(d_real); dfree(d_toff); dfree(d_sigbase);
+        dfree(d_res); dfree(d_hist); dfree(d_cau); dfree(d_chist); dfree(d_norm0); dfree(d_epsbar); dfree(d_real); dfree(d_toff); dfree(d_sigbase);
         if (h_st) (void)hipHostFree(h_st);
         h_st = nullptr;
         cap = 0;
@@ -236,8 +239,11 @@ struct ahom_solver {
         const int mt_spec = max_tiles(FAST_SPEC, P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len);
         HIPCHK(hipMalloc((void**)&d_sig, (size_t)nload * std::max(g_real.nwg, mt_real) * ncomp * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_res, (size_t)nload * std::max(g_spec.nwg, mt_spec) * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_cau, (size_t)nload * std::max(g_spec.nwg, mt_spec) * sizeof(double)));
         hist_cap = cfg.max_iter + 1;
         HIPCHK(hipMalloc((void**)&d_hist, (size_t)nload * hist_cap * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_chist, (size_t)nload * hist_cap * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&d_norm0, (size_t)nload * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_epsbar, (size_t)nload * ncomp * sizeof(double)));
         HIPCHK(hipMalloc((void**)&d_sigbase, (size_t)nload * ncomp * sizeof(double)));
         if (prec == AHOM_FP32_MIXED && cfg.refine > 0.0) {
@@ -315,6 +321,7 @@ struct ahom_solver {
         a.mu0 = mu0;
         a.beta = (lam0 + mu0) / (lam0 + 2.0 * mu0);
         a.res_part = d_res;
+        a.cau_part = d_cau;
         a.NC = g_spec.NC;
         a.CS = g_spec.CS;
         a.resid_period = cfg.resid_period;
@@ -373,6 +380,10 @@ struct ahom_solver {
         r.max_iter = cfg.max_iter;
         r.resid_period = cfg.resid_period;
         r.sig_base = red_sig_base;
+        r.cau_part = d_cau;
+        r.chist = d_chist;
+        r.norm0 = d_norm0;
+        r.cau_scale = (double)P.m / (2.0 * mu0 * mu0);
         if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
         return AHOM_OK;
     }
@@ -494,7 +505,7 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
     const size_t es = s->es();
     auto bad = [&](int code) { delete s; return code; };
     if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)s->ncomp * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
-    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
+    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)2 * AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
     for (int a = 1; a <= P.D - 2; ++a) {
         int64_t O = 1, I = 1;
         for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
@@ -837,6 +848,18 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     for (int l = 0; l < n_load; ++l)
         for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
     HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    // denominator of the Cauchy measure: |eps(0)| = sqrt(m) |eps_bar|_F for the
+    // plain start (kept with a user initial guess)
+    std::vector<double> norm0(n_load);
+    for (int l = 0; l < n_load; ++l) {
+        double f = 0.0;
+        for (int c = 0; c < nc; ++c) {
+            const bool diag = s->dim == 3 ? c < 3 : c < 2;
+            f += (diag ? 1.0 : 2.0) * eb[(size_t)l * nc + c] * eb[(size_t)l * nc + c];
+        }
+        norm0[l] = std::sqrt((double)P.m * f);
+    }
+    HIPCHK(hipMemcpyAsync(s->d_norm0, norm0.data(), norm0.size() * sizeof(double), hipMemcpyHostToDevice, st));
     if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
     if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
     auto fill = [&](void* buf) -> int {
@@ -1129,6 +1152,14 @@ int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, i
     if (!s || !hist || !count || load < 0 || load >= s->last_nload) return fail(AHOM_E_ARG, "bad history arguments");
     const int n = std::min(cap, std::min(s->hist_cap, s->h_st[load].iter + 1));
     HIPCHK(hipMemcpy(hist, s->d_hist + (size_t)load * s->hist_cap, n * sizeof(double), hipMemcpyDeviceToHost));
+    *count = n;
+    return AHOM_OK;
+}
+
+int ahom_solver_cauchy_history(const ahom_solver* s, int load, double* hist, int cap, int* count) {
+    if (!s || !hist || !count || load < 0 || load >= s->last_nload) return fail(AHOM_E_ARG, "bad history arguments");
+    const int n = std::min(cap, std::min(s->hist_cap, s->h_st[load].iter + 1));
+    HIPCHK(hipMemcpy(hist, s->d_chist + (size_t)load * s->hist_cap, n * sizeof(double), hipMemcpyDeviceToHost));
     *count = n;
     return AHOM_OK;
 }

@@ -1101,11 +1101,12 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     C* twl = F + G::TILE;
     int64_t* kb = reinterpret_cast<int64_t*>(twl + L);   // [NC][4]: kappa base (3) + weight
     double* nbd = reinterpret_cast<double*>(kb + NC * 4); // [NC][3]: base numerators (exact doubles)
-    double* red = nbd + NC * 3;                           // [NW] per-wave residual sums
+    double* red = nbd + NC * 3;                           // [2][NW] per-wave residual and Cauchy sums
     Twiddles<L, TH, C> twr;
     twr.load(reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, tid);
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
+    const double cau_c1 = 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
     const int last_snf = P.ax[D - 1].snf;
     const int64_t last_mult = P.ax[D - 1].mult;
     // Along a column only the last axis moves: kappa = kappa_b + l mult u_snf,
@@ -1286,7 +1287,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
         fft_cols<L, -1, CS>(F, NCOMP * NC, twl);
 
         const double* eb = a.eps_bar + (int64_t)load * NCOMP;
-        double res = 0.0;
+        double res = 0.0, cau = 0.0;
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
@@ -1354,11 +1355,13 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
             }
             const int64_t spos = c0 * L + e;
             if (chk) {
-                double r2 = 0.0;
+                double r2 = 0.0, xdx = 0.0, xdy = 0.0;
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
                     const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
                     r2 += dx * dx + dy * dy;
+                    xdx += (double)xi[c] * dx;
+                    xdy += (double)xi[c] * dy;
                     if (a.dout) {
                         const int64_t o = ((int64_t)load * NT + c) * P.S + spos;
                         reinterpret_cast<float2*>(a.dout)[o] = float2{(float)dx, (float)dy};
@@ -1366,6 +1369,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                     }
                 }
                 res += (double)kb[j * 4 + 3] * r2;
+                // Cauchy term |eps_hat(n+1) - eps_hat(n)|^2 up to 1 / (2 mu0^2)
+                cau += (double)kb[j * 4 + 3] * (r2 + cau_c1 * (xdx * xdx + xdy * xdy));
             }
             if (wrt) {
 #pragma unroll
@@ -1400,14 +1405,22 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
             }
         });
-        // fixed-order residual sum: inside the wave, then waves in order
+        // fixed-order residual and Cauchy sums: inside the wave, then waves in order
         res = wave_sum_lane63(res);
-        if ((tid & 63) == 63) red[tid >> 6] = res;
+        cau = wave_sum_lane63(cau);
+        if ((tid & 63) == 63) {
+            red[tid >> 6] = res;
+            red[NW + (tid >> 6)] = cau;
+        }
         __syncthreads();
         if (tid == 0) {
-            double acc = 0.0;
-            for (int w = 0; w < NW; ++w) acc += red[w];
+            double acc = 0.0, acc2 = 0.0;
+            for (int w = 0; w < NW; ++w) {
+                acc += red[w];
+                acc2 += red[NW + w];
+            }
             a.res_part[(int64_t)load * nct + tt % nct] = acc;
+            if (a.cau_part) a.cau_part[(int64_t)load * nct + tt % nct] = acc2;
         }
         fft_cols<L, +1, CS>(F, NCOMP * NC, twl);
         // read the tile out into registers, then store (the LDS reads go out
@@ -1454,7 +1467,7 @@ FastGeom geom_of(int kind) {
     g.persistent = G::PERSIST;
     // tile + twiddles + per-column integers (spec: kappa + weight) or
     // per-wave stress sums (real; the phase table is added at launch)
-    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * (32 + 24) + (size_t)(G::THREADS / 64) * 8
+    size_t extra = kind == FAST_SPEC ? (size_t)G::NC * (32 + 24) + (size_t)(G::THREADS / 64) * 16
                                      : (kind == FAST_REAL ? (size_t)6 * (G::THREADS / 64) * 8 : 0);
     size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
     // block reduction of the other passes reuses the tile: one double per thread

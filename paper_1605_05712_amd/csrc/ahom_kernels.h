@@ -68,6 +68,7 @@ struct SpecArgs {
     double mu0, beta;
     double lam0_init;          // lambda0 (used by SPEC_INIT)
     double* res_part;         // [load][wg]
+    double* cau_part;         // [load][wg] Cauchy-measure partial sums (nullable)
     int NC, CS;
     int nload;                // fast path: load cases covered by the persistent grid
     int resid_period;         // evaluate the residual for iter = 0 (mod resid_period) and at max_iter
@@ -100,6 +101,12 @@ struct ReduceArgs {
     int max_iter;
     int resid_period;
     const double* sig_base;   // [load][ncomp] added to the mean stress (nullptr: none)
+    // Cauchy measure (nullable chist: not recorded): c(n) = sqrt(cau_scale *
+    // sum of cau_part) / norm0[load], cau_scale = m / (2 mu0^2)
+    const double* cau_part;
+    double* chist;
+    const double* norm0;
+    double cau_scale;
 };
 
 struct FillArgs {

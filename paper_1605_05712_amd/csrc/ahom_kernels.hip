@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
 // =============================================================================
 // One tile of the last-axis pass; the residual terms are added to res.
 template <typename T, int DIM, int MODE>
-__device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int64_t tile, double& res) {
+__device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int64_t tile, double& res, double& cau) {
     using C = typename CT<T>::t;
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
     const Plan& P = *a.plan;
@@ -567,6 +567,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     const double* eb = a.eps_bar + (int64_t)load * NC_;
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
+    const double cau_c1 = 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
     const int L0 = P.ax[0].len;
     // Centred numerators in exact doubles while emax <= 2^24 (A in [0, emax),
     // 0 <= kappa_s < e_s <= emax: products < 2^48, sums of three < 2^53), the
@@ -694,13 +695,15 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         const double wgt = (kpos[0] == 0 || 2 * kpos[0] == L0) ? 1.0 : 2.0;
         const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
         const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
-        double r2 = 0.0;
+        double r2 = 0.0, xdx = 0.0, xdy = 0.0;
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             if (chk) {
                 const C old = tb[(int64_t)c * P.S + spos];
                 const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
                 r2 += dx * dx + dy * dy;
+                xdx += (double)xi[c] * dx;
+                xdy += (double)xi[c] * dy;
                 if (a.dout) {
                     const int64_t o = ((int64_t)load * NT + c) * P.S + spos;
                     reinterpret_cast<float2*>(a.dout)[o] = float2{(float)dx, (float)dy};
@@ -710,6 +713,9 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
             if (wrt) tb[(int64_t)c * P.S + spos] = t[c];
         }
         res += wgt * r2;
+        // Cauchy term: eps_hat(n+1) - eps_hat(n) = -sym(xi (x) K^{-1} dt) has squared
+        // norm (|dt|^2 + (1 - 4 beta + 2 beta^2) |xi . dt|^2) / (2 mu0^2)
+        cau += wgt * (r2 + cau_c1 * (xdx * xdx + xdy * xdy));
         if (a.toff) {
             const C* to = reinterpret_cast<const C*>(a.toff) + (int64_t)load * NT * P.S;
 #pragma unroll
@@ -755,12 +761,15 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
     constexpr int NC_ = Comp<DIM>::N;
     const int load = blockIdx.y;
     if (a.st[load].done) return;
-    double res = 0.0;
-    spec_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, res);
+    double res = 0.0, cau = 0.0;
+    spec_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, res, cau);
     if (MODE == SPEC_INIT) return;
-    double rv[1] = {res};
-    block_sum<1>(rv, reinterpret_cast<double*>(lds_base<C>() + (NC_ + 1) * a.NC * a.CS));
-    if (threadIdx.x == 0) a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
+    double rv[2] = {res, cau};
+    block_sum<2>(rv, reinterpret_cast<double*>(lds_base<C>() + (NC_ + 1) * a.NC * a.CS));
+    if (threadIdx.x == 0) {
+        a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
+        if (a.cau_part) a.cau_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[1];
+    }
 }
 
 // =============================================================================
@@ -780,6 +789,12 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
         for (int c = 0; c < NC_; ++c) v[c] += a.sig_part[((int64_t)load * a.n_real + w) * NC_ + c];
     for (int w = tid; w < a.n_spec; w += AHOM_WG) v[NC_] += a.res_part[(int64_t)load * a.n_spec + w];
     block_sum<NC_ + 1>(v, scratch);
+    double cs[1] = {0.0};
+    if (a.chist) {
+        __syncthreads();
+        for (int w = tid; w < a.n_spec; w += AHOM_WG) cs[0] += a.cau_part[(int64_t)load * a.n_spec + w];
+        block_sum<1>(cs, scratch);
+    }
     if (tid != 0) return;
     const double inv_m = 1.0 / (double)a.m;
     double mean[NC_];
@@ -794,11 +809,14 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
     if (!ahom_check_iter(n, a.resid_period, a.max_iter)) {
         // residual not evaluated on this iteration (recorded as -1)
         if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = -1.0;
+        if (a.chist && n < a.hist_cap) a.chist[(int64_t)load * a.hist_cap + n] = -1.0;
         st.iter = n + 1;
         return;
     }
     const double r = sqrt(v[NC_]) / sqrt(fro);
     if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = r;
+    // Cauchy measure |eps(n+1) - eps(n)| / |eps(0)| (Parseval, 1/m-normalised transform)
+    if (a.chist && n < a.hist_cap) a.chist[(int64_t)load * a.hist_cap + n] = sqrt(a.cau_scale * cs[0]) / a.norm0[load];
     if (n == 0) st.r0 = r;
     st.resid = r;
     const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
@@ -911,7 +929,8 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             group_sync(it, phase, wait);
         }
         for (int64_t t = slot; t < t_spec; t += k) {
-            spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_]);
+            double cau_unused = 0.0;
+            spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_], cau_unused);
             __syncthreads();
         }
         group_sync(it, phase, wait);

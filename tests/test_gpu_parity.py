@@ -124,6 +124,8 @@ def test_fields_after_fixed_iterations(name, M, lame, pf, d):
     hist = S.history(0)
     assert len(hist) == N + 1
     assert np.allclose(hist, r.history, rtol=1e-10, atol=0)
+    # Cauchy measure |eps(n+1) - eps(n)| / |eps(0)| beside the residual
+    assert np.allclose(S.cauchy_history(0)[:N], r.cauchy, rtol=1e-9, atol=0)
     ms = out["mean_stress"][0][:d, :d]
     assert np.allclose(ms, r.mean_stress, rtol=1e-10, atol=1e-12 * np.abs(r.mean_stress).max())
 

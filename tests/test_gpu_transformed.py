@@ -79,6 +79,9 @@ def test_transformed_fields_after_fixed_iterations(name, M, L, lame, N, prec):
     assert rel_err(out["strain"][0], ref) < tol
     if prec == ahom.FP64:
         assert np.allclose(S.history(0), r.history, rtol=1e-10, atol=0)
+        assert np.allclose(S.cauchy_history(0)[:N], r.cauchy, rtol=1e-9, atol=0)
+    else:
+        assert np.allclose(S.cauchy_history(0)[:N], r.cauchy, rtol=1e-3, atol=0)
     ms = out["mean_stress"][0][:d, :d]
     assert np.allclose(ms, r.mean_stress, rtol=tol, atol=tol * np.abs(r.mean_stress).max())
 
