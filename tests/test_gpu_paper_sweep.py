@@ -173,6 +173,8 @@ def test_subsampling_sec_5_2():
         e_eff = E.error_eff(out["mean_stress"][0][:2, :2], ref_eff)
         c = S.cauchy_history(0)
         assert np.allclose(c[: r.iters], r.cauchy, rtol=1e-8, atol=1e-15)
+        below = np.flatnonzero((c >= 0) & (c < 1e-9))
+        print("[subsampling] M_%s: first Cauchy measure below 1e-9 at n = %s" % (name, below[0] if below.size else None))
         res[name] = (int(out["iters"][0]), e_l2, e_eff)
         print("[subsampling] M_%s: m %d, iterations %d, e_l2 %.4f, e_eff %.4f" % (name, P.m, *res[name]), flush=True)
     assert res["b"][1] < 1e-12 and res["b"][2] < 1e-12
