@@ -937,6 +937,7 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     // t(e(-1)) = -d.  The mean stress is that of eps_b plus that of e.
     int nrestart = 0;
     std::vector<double> hsig((size_t)n_load * nc), zeros((size_t)n_load * nc, 0.0), hrec(n_load);
+    const double not_evaluated = -1.0;   // Cauchy measure of a restart's FP64 step: not recorded
     while (refine) {
         bool need = false, stop = false;
         for (int l = 0; l < n_load; ++l) {
@@ -981,8 +982,11 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
             else if (ls.iter >= s->cfg.max_iter) { ls.done = 1; ls.status = 1; }
             else { rmax = std::max(rmax, lr.resid); any = true; }
             hrec[l] = lr.resid;
-            if (ls.done && ls.iter < s->hist_cap)
+            if (ls.done && ls.iter < s->hist_cap) {
                 HIPCHK(hipMemcpyAsync(s->d_hist + (size_t)l * s->hist_cap + ls.iter, &hrec[l], sizeof(double), hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->d_chist + (size_t)l * s->hist_cap + ls.iter, &not_evaluated, sizeof(double),
+                                      hipMemcpyHostToDevice, st));
+            }
             s->h_st[l] = ls;
         }
         HIPCHK(hipMemcpyAsync(s->d_st, s->h_st, n_load * sizeof(LoadState), hipMemcpyHostToDevice, st));

@@ -78,6 +78,13 @@ def test_refined_fp32_reaches_tol_below_fp32_floor():
         # the same fixed point as the FP64 iteration
         assert rel_err(out["strain"][k], o64["strain"][k]) < 1e-6
         assert abs(int(out["iters"][k]) - int(o64["iters"][k])) <= 0.05 * o64["iters"][k] + 5
+        # Cauchy measure across restarts: evaluated entries finite and >= 0, the
+        # rest -1; it falls with the residual (within FP32 rounding early on)
+        c = S.cauchy_history(k)
+        assert len(c) == out["iters"][k] + 1
+        assert np.all(np.isfinite(c)) and np.all((c >= 0) | (c == -1.0))
+        c64 = ref64.cauchy_history(k)
+        assert c[-1] < 1e-3 * c[0] and c64[-1] < 1e-3 * c64[0]
     # without restarts FP32 cannot get there: its output is far from equilibrium
     plain = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=tol, max_iter=3000, refine=-1.0)
     plain.set_material(LAM100, pf(P.points(), P.m))
