@@ -265,6 +265,16 @@ typedef struct ahom_batch ahom_batch;
  * library's HIP runtime).  Errors as ahom_pattern_create, per member.
  */
 int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config* cfg, ahom_batch** out);
+
+/*
+ * As ahom_batch_create for transformed patterns P_L(M) (Def. 3.3, as
+ * ahom_pattern_create_transformed): L holds one real regular cell matrix per
+ * member (n_members * d * d doubles, row-major, host memory, copied); member
+ * i's Gamma0 and residual use the wave vectors L_i^{-T} h.  Errors: those of
+ * ahom_batch_create, AHOM_E_ARG (null L, non-finite entry), AHOM_E_SINGULAR.
+ */
+int ahom_batch_create_transformed(int d, int n_members, const int64_t* M, const double* L, const ahom_config* cfg,
+                                  ahom_batch** out);
 void ahom_batch_destroy(ahom_batch* b);
 
 /* m = |det M_i| and the elementary divisors e[0..d-1] of member i. */

@@ -44,7 +44,8 @@ EXPORTS = [
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
-    "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_destroy", "ahom_batch_member_info",
+    "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_create_transformed",
+    "ahom_batch_destroy", "ahom_batch_member_info",
     "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
     "ahom_batch_strain", "ahom_batch_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
     "ahom_guess_create", "ahom_guess_destroy", "ahom_guess_num_params", "ahom_guess_get_params", "ahom_guess_set_params",
@@ -89,6 +90,7 @@ _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_cauchy_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
 _lib.ahom_batch_create.argtypes = [ct.c_int, ct.c_int, _i64p, _P, ct.POINTER(_P)]
+_lib.ahom_batch_create_transformed.argtypes = [ct.c_int, ct.c_int, _i64p, _dp, ct.POINTER(Config), ct.POINTER(_P)]
 _lib.ahom_batch_destroy.argtypes = [_P]
 _lib.ahom_batch_destroy.restype = None
 _lib.ahom_batch_member_info.argtypes = [_P, ct.c_int, _i64p, _i64p]
@@ -374,7 +376,7 @@ class Solver:
 class Batch:
     """Many patterns (same dimension) solved in one persistent device launch."""
 
-    def __init__(self, Ms, precision=FP64, tol=1e-8, max_iter=1000, resid_period=1, refine=0.0, stream=None):
+    def __init__(self, Ms, precision=FP64, tol=1e-8, max_iter=1000, resid_period=1, refine=0.0, stream=None, cells=None):
         Ms = [np.asarray(M, dtype=np.int64) for M in Ms]
         self.d = Ms[0].shape[0]
         if any(M.shape != (self.d, self.d) for M in Ms):
@@ -384,7 +386,12 @@ class Batch:
         flat = np.ascontiguousarray(np.stack(Ms).reshape(-1))
         self.cfg = Config(precision, tol, max_iter, 1, NYQUIST_HERMITIAN, stream, resid_period, refine)
         h = _P()
-        _check(_lib.ahom_batch_create(self.d, self.n, _ptr(flat, ct.c_int64), ct.byref(self.cfg), ct.byref(h)))
+        if cells is None:
+            _check(_lib.ahom_batch_create(self.d, self.n, _ptr(flat, ct.c_int64), ct.byref(self.cfg), ct.byref(h)))
+        else:
+            Ls = np.ascontiguousarray(np.asarray(cells, dtype=np.float64).reshape(self.n, self.d, self.d))
+            _check(_lib.ahom_batch_create_transformed(self.d, self.n, _ptr(flat, ct.c_int64), _ptr(Ls, ct.c_double),
+                                                      ct.byref(self.cfg), ct.byref(h)))
         self._h = h
         self.nload = 0
 

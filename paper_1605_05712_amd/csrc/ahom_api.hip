@@ -610,35 +610,12 @@ int ahom_pattern_create_transformed(int d, const int64_t* M, const double* L, ah
     if (!M || !L || !out) return fail(AHOM_E_ARG, "null argument");
     *out = nullptr;
     if (d != 2 && d != 3) return fail(AHOM_E_ARG, "d must be 2 or 3");
-    double a[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    double scale = 0.0;
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < d; ++j) {
-            a[i][j] = L[i * d + j];
-            if (!std::isfinite(a[i][j])) return fail(AHOM_E_ARG, "L has a non-finite entry");
-            scale = std::max(scale, std::fabs(a[i][j]));
-        }
-    // L^{-1} by cofactors (d <= 3); a determinant that vanishes next to the
-    // entries' size is a singular cell
-    const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
-                       a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
-    if (!(std::fabs(det) > 1e-12 * std::pow(scale, d))) return fail(AHOM_E_SINGULAR, "L is singular");
-    double inv[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3, i1 = (i + 1) % 3, i2 = (i + 2) % 3;
-            inv[i][j] = (a[j1][i1] * a[j2][i2] - a[j1][i2] * a[j2][i1]) / det;
-        }
+    Plan probe{};
+    std::string err;
+    if (int rc = ahom_plan_set_cell(&probe, d, L, &err)) return fail(rc, err);   // validate L first
     const int rc = ahom_pattern_create(d, M, out);
     if (rc != AHOM_OK) return rc;
-    FreqMap& fm = (*out)->plan.fm;
-    // G = L^{-T} M^T: (L^{-T})_{ij} = (L^{-1})_{ji}
-    for (int i = 0; i < d; ++i)
-        for (int s = 0; s < d; ++s) {
-            double g = 0.0;
-            for (int j = 0; j < d; ++j) g += inv[j][i] * (double)fm.MT[j][s];
-            fm.G[i][s] = g;
-        }
+    if ((*out)->sf.m > 1) ahom_plan_set_cell(&(*out)->plan, d, L, &err);
     return AHOM_OK;
 }
 

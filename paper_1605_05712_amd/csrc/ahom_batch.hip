@@ -72,6 +72,8 @@ struct Member {
     float2* d_tw32 = nullptr;
     uint8_t* d_phase = nullptr;
     double* d_lame = nullptr;
+    bool has_cell = false;          // transformed pattern P_L(M): cell matrix L (d*d, row-major)
+    double cell[9] = {};
     double lam0 = 0, mu0 = 0;
     double lam_lo = 0, lam_hi = 0, mu_lo = 0, mu_hi = 0;
     bool has_material = false, ref_set = false;
@@ -163,6 +165,7 @@ struct ahom_batch {
         std::string err;
         int rc = ahom_build_plan_ex(mb.sf, 256, kVariants[variant].max_radix, &mb.plan, &err);
         if (rc) return bfail(rc, err);
+        if (mb.has_cell && (rc = ahom_plan_set_cell(&mb.plan, mb.sf.d, mb.cell, &err))) return bfail(rc, err);
         ahom_build_twiddles(&mb.plan, &mb.tw);
         dfree(mb.d_plan); dfree(mb.d_tw64); dfree(mb.d_tw32);
         BCHK(hipMalloc((void**)&mb.d_plan, sizeof(Plan)));
@@ -489,7 +492,8 @@ int ahom_batch::autotune() {
 
 extern "C" {
 
-int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config* cfg, ahom_batch** out) {
+static int batch_create(int d, int n_members, const int64_t* M, const double* L, const ahom_config* cfg,
+                        ahom_batch** out) {
     if (!out || !M || !cfg || n_members < 1 || (d != 2 && d != 3)) return bfail(AHOM_E_ARG, "bad batch arguments");
     *out = nullptr;
     if (cfg->precision != AHOM_FP64 && cfg->precision != AHOM_FP32_MIXED) return bfail(AHOM_E_ARG, "bad precision");
@@ -515,6 +519,12 @@ int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config*
         if (mb.sf.m < 2) { delete b; return bfail(AHOM_E_ARG, "member " + std::to_string(i) + ": trivial pattern"); }
         rc = ahom_build_plan_ex(mb.sf, 256, 8, &mb.plan, &err);   // validates the size; replaced by the tuned plan
         if (rc) { delete b; return bfail(rc, "member " + std::to_string(i) + ": " + err); }
+        if (L) {
+            mb.has_cell = true;
+            for (int k = 0; k < d * d; ++k) mb.cell[k] = L[(size_t)i * d * d + k];
+            rc = ahom_plan_set_cell(&mb.plan, d, mb.cell, &err);   // validates L
+            if (rc) { delete b; return bfail(rc, "member " + std::to_string(i) + ": " + err); }
+        }
     }
     if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess) {
@@ -523,6 +533,16 @@ int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config*
     }
     *out = b;
     return AHOM_OK;
+}
+
+int ahom_batch_create(int d, int n_members, const int64_t* M, const ahom_config* cfg, ahom_batch** out) {
+    return batch_create(d, n_members, M, nullptr, cfg, out);
+}
+
+int ahom_batch_create_transformed(int d, int n_members, const int64_t* M, const double* L, const ahom_config* cfg,
+                                  ahom_batch** out) {
+    if (!L) return bfail(AHOM_E_ARG, "null cell matrices");
+    return batch_create(d, n_members, M, L, cfg, out);
 }
 
 void ahom_batch_destroy(ahom_batch* b) { delete b; }

@@ -100,6 +100,10 @@ int ahom_smith_form(int d, const int64_t* M, SmithForm* out, std::string* err);
 int ahom_build_plan(const SmithForm& sf, int lmax, Plan* plan, std::string* err);
 // max_radix 8: radix-8 stages first; 4: radix 4 and 2 only for the powers of two
 int ahom_build_plan_ex(const SmithForm& sf, int lmax, int max_radix, Plan* plan, std::string* err);
+// Transformed pattern P_L(M) (Def. 3.3): sets the plan's direction map
+// G = L^{-T} M^T for the real regular cell matrix L (d*d, row-major).
+// AHOM_E_ARG for a non-finite entry, AHOM_E_SINGULAR for |det L| <= 1e-12 max|L_ij|^d.
+int ahom_plan_set_cell(Plan* plan, int d, const double* L, std::string* err);
 // Twiddle tables for a plan: FP64 values (and their FP32 rounding).
 void ahom_build_twiddles(Plan* plan, std::vector<double>* tw64);
 void ahom_canonical_points(const SmithForm& sf, int64_t* num);

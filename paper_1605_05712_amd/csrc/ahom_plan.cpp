@@ -190,6 +190,43 @@ void ahom_canonical_points(const SmithForm& sf, int64_t* num) {
     }
 }
 
+int ahom_plan_set_cell(Plan* plan, int d, const double* L, std::string* err) {
+    double a[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double scale = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            a[i][j] = L[i * d + j];
+            if (!std::isfinite(a[i][j])) {
+                *err = "L has a non-finite entry";
+                return AHOM_E_ARG;
+            }
+            scale = std::max(scale, std::fabs(a[i][j]));
+        }
+    // L^{-1} by cofactors; a determinant that vanishes next to the entries'
+    // size is a singular cell
+    const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                       a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    if (!(std::fabs(det) > 1e-12 * std::pow(scale, d))) {
+        *err = "L is singular";
+        return AHOM_E_SINGULAR;
+    }
+    double inv[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int j1 = (j + 1) % 3, j2 = (j + 2) % 3, i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+            inv[i][j] = (a[j1][i1] * a[j2][i2] - a[j1][i2] * a[j2][i1]) / det;
+        }
+    // G = L^{-T} M^T: (L^{-T})_{ij} = (L^{-1})_{ji}
+    FreqMap& fm = plan->fm;
+    for (int i = 0; i < d; ++i)
+        for (int s = 0; s < d; ++s) {
+            double g = 0.0;
+            for (int j = 0; j < d; ++j) g += inv[j][i] * (double)fm.MT[j][s];
+            fm.G[i][s] = g;
+        }
+    return AHOM_OK;
+}
+
 // Canonical frequency order: kappa lexicographic; h = M^T N / emax.
 void ahom_canonical_freqs(const SmithForm& sf, const FreqMap& fm, int64_t* h) {
     const int d = sf.d;

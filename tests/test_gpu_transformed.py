@@ -129,3 +129,29 @@ def test_transformed_fast_path_matches_generic_path(prec, monkeypatch):
     tol = 1e-12 if prec == ahom.FP64 else 2e-5
     assert rel_err(outs[0]["strain"], outs[1]["strain"]) < tol
     assert np.allclose(outs[0]["resid"], outs[1]["resid"], rtol=tol * 10)
+
+
+def test_transformed_batch_members_match_oracle():
+    """ahom_batch_create_transformed: 2-D members, each in its own cell, FP64, 3 updates."""
+    Ms = [[[24, 0], [0, 40]], [[16, 16], [-16, 16]], [[8, -4], [2, 7]], [[64, 32], [0, 1]]]
+    cells = [L2, L2.T, np.array([[0.8, 0.0], [0.5, 1.2]]), np.eye(2)]
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((2, 2))
+    eb = 0.5 * (A + A.T)
+    say("transformed batch", Ms)
+    B = ahom.Batch(Ms, precision=ahom.FP64, tol=0.0, max_iter=3, cells=cells)
+    for i in range(len(Ms)):
+        m, _ = B.info(i)
+        B.set_material(i, LAM3, rnd_phase(60 + i, 3)(B.points(i), m))
+    out = B.solve(np.pad(eb, ((0, 1), (0, 1)))[None])
+    assert np.all(out["iters"] == 3)
+    for i, M in enumerate(Ms):
+        T = make_transform(M)
+        ph = rnd_phase(60 + i, 3)(T.points, T.m)
+        r = E.basic_scheme(M, ph, LAM3, E.default_reference(LAM3), eb, transform=T, fixed_iters=3, cell=cells[i])
+        ip = perm_between(T.points, B.points(i))
+        assert rel_err(B.strain(i, 0), tensors_to_fields(r.eps[:, :, ip])) < 1e-10, M
+        assert np.allclose(B.history(i, 0), r.history, rtol=1e-9), M
+    with pytest.raises(ahom.AhomError) as ex:
+        ahom.Batch(Ms[:1], cells=[[[1.0, 2.0], [0.5, 1.0]]])
+    assert ex.value.code == ahom.AHOM_E_SINGULAR
