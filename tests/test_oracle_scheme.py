@@ -146,3 +146,41 @@ def test_naive_and_fft_routes_give_same_solve():
     back = np.array([rn.eps[:, :, pos[tuple(p)]] for p in F.points.tolist()])
     assert np.allclose(back, rf.eps.transpose(2, 0, 1), atol=1e-13)
     assert np.allclose(rn.history, rf.history, rtol=1e-10)
+
+
+@pytest.mark.parametrize("M", [[[12, 0, 0], [0, 6, 0], [3, 0, 4]], [[16, 0], [4, 16]]])
+def test_cauchy_step_from_traction_step(M):
+    """The update of Algorithm 1 depends on tau_hat only through t = tau_hat xi, so
+    |eps(n+1) - eps(n)|^2 = m sum_{h active, h != 0} |sym(xi (x) K^{-1} dt_h)|^2 with
+    dt = t(n) - t(n-1) and K^{-1} = (I - beta xi xi^T) / mu0, i.e. per frequency
+    (|dt|^2 + (1 - 4 beta + 2 beta^2) |xi . dt|^2) / (2 mu0^2) (Parseval with the
+    1/m-normalised transform).  Checked against differences of the iterates."""
+    T = make_transform(M)
+    d = len(M)
+    lame = np.array([[1.0, 0.5], [4.0, 2.0], [2.0, 3.0]])
+    lam0, mu0 = E.default_reference(lame)
+    beta = (lam0 + mu0) / (lam0 + 2.0 * mu0)
+    ph = np.random.default_rng(7).integers(0, 3, T.m)
+    A = np.random.default_rng(8).standard_normal((d, d))
+    eps0 = 0.5 * (A + A.T)
+    H = np.asarray(T.freqs, dtype=np.int64)
+    zero = np.flatnonzero(np.all(H == 0, axis=1))[0]
+    act = E.active_classes(M, H)
+    act[zero] = False
+    xi = H[act] / np.linalg.norm(H[act], axis=1)[:, None]
+    tensors = [E.iso_tensor(l, mu, d) for l, mu in lame]
+    C0 = E.iso_tensor(lam0, mu0, d)
+
+    def traction(eps):
+        tau = E.apply_phases(tensors, ph, eps) - E.contract(C0, eps)
+        return np.einsum("ijn,nj->ni", T.forward(tau)[:, :, act], xi)
+
+    runs = [E.basic_scheme(M, ph, lame, (lam0, mu0), eps0, transform=T, fixed_iters=n) for n in range(5)]
+    for n in range(1, 4):
+        dt = traction(runs[n].eps) - traction(runs[n - 1].eps)
+        xd = np.einsum("ni,ni->n", xi, dt)
+        per = (np.sum(np.abs(dt) ** 2, axis=1) + (1 - 4 * beta + 2 * beta ** 2) * np.abs(xd) ** 2) / (2 * mu0 ** 2)
+        lhs = float(np.sum((runs[n + 1].eps - runs[n].eps) ** 2))
+        assert math.isclose(lhs, T.m * float(np.sum(per)), rel_tol=1e-10)
+        # and the oracle's own Cauchy record is that difference
+        assert math.isclose(runs[4].cauchy[n], math.sqrt(lhs) / float(np.linalg.norm(runs[0].eps)), rel_tol=1e-12)
