@@ -83,7 +83,15 @@ typedef struct ahom_config {
                            with the whole field.  0 = default 1e-3; < 0 = no restarts (the
                            plain FP32 iteration, whose residual floor is set by FP32
                            rounding of the polarization). */
+    int stop_rule;      /* AHOM_STOP_RESIDUAL (0, default): stop at r(n) <= tol.
+                           AHOM_STOP_CAUCHY (1): the criterion of Sec. 5.2, stop at the
+                           first evaluated n with c(n) = |eps(n+1) - eps(n)| / |eps(0)| <= tol
+                           (see ahom_solver_cauchy_history) and return eps(n).  Single-pattern
+                           solver only; in AHOM_FP32_MIXED it needs refine < 0. */
 } ahom_config;
+
+#define AHOM_STOP_RESIDUAL 0
+#define AHOM_STOP_CAUCHY 1
 
 /* Library version, (major << 16) | (minor << 8) | patch. */
 int ahom_version(void);

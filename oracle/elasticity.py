@@ -178,13 +178,15 @@ def wave_vectors(H, cell=None):
 
 
 def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=None,
-                 transform=None, rule="hermitian", fixed_iters=None, cell=None):
+                 transform=None, rule="hermitian", fixed_iters=None, cell=None, stop="residual"):
     """Algorithm 1 on P(M) (or on P_L(M) with cell = L) with the equilibrium-residual stop.
 
     phase: (m,) ints in the transform's point order; lame: (n_phase, 2) rows
     (lambda, mu); lame0 = (lambda0, mu0); eps_bar: (d, d) macroscopic strain;
     init: optional (d, d, m) fluctuation added to eps_bar in eps(0).
     fixed_iters: run exactly this many updates, ignoring tol.
+    stop="cauchy": the Sec. 5.2 criterion instead, |eps(n+1) - eps(n)| / |eps(0)|
+    <= tol; the result is eps(n) for the first such n (n updates performed).
     """
     T = transform or make_transform(M)
     d = len(as_int_matrix(M))
@@ -215,7 +217,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
         mean = np.sum(sigma, axis=2) / m
         if not math.isfinite(r) or (r0 > 0 and r > 1e3 * r0):
             return SchemeResult(eps, n, r, 2, mean, hist, cauchy)
-        if fixed_iters is None and r <= tol:
+        if fixed_iters is None and stop == "residual" and r <= tol:
             return SchemeResult(eps, n, r, 0, mean, hist, cauchy)
         if n == (fixed_iters if fixed_iters is not None else max_iter):
             status = 0 if fixed_iters is not None else 1
@@ -230,6 +232,8 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
             assert np.max(np.abs(new.imag)) <= 1e-9 * max(1.0, np.max(np.abs(new.real)))
         new = new.real
         cauchy.append(float(np.linalg.norm(new - eps)) / norm0)
+        if fixed_iters is None and stop == "cauchy" and cauchy[-1] <= tol:
+            return SchemeResult(eps, n, r, 0, mean, hist, cauchy)
         eps = new
         n += 1
 

@@ -384,6 +384,7 @@ struct ahom_solver {
         r.chist = d_chist;
         r.norm0 = d_norm0;
         r.cau_scale = (double)P.m / (2.0 * mu0 * mu0);
+        r.stop_cauchy = cfg.stop_rule == AHOM_STOP_CAUCHY;
         if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
         return AHOM_OK;
     }
@@ -718,6 +719,9 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     if (cfg->max_iter < 0 || !(cfg->tol >= 0.0)) return fail(AHOM_E_ARG, "bad tol/max_iter");
     if (cfg->nyquist != AHOM_NYQUIST_HERMITIAN) return fail(AHOM_E_ARG, "unsupported Nyquist rule");
     if (!(cfg->refine < 1.0)) return fail(AHOM_E_ARG, "refine must be < 1");
+    if (cfg->stop_rule != AHOM_STOP_RESIDUAL && cfg->stop_rule != AHOM_STOP_CAUCHY) return fail(AHOM_E_ARG, "unknown stop rule");
+    if (cfg->stop_rule == AHOM_STOP_CAUCHY && cfg->precision == AHOM_FP32_MIXED && !(cfg->refine < 0.0))
+        return fail(AHOM_E_ARG, "the Cauchy stop rule in FP32 needs refine < 0 (no restarts)");
     return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
 }
 
@@ -1026,7 +1030,8 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
             }
         }
         if (ls.status == 2) ret = AHOM_E_DIVERGED;
-        else if ((ls.status == 1 || ls.resid > s->cfg.tol) && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
+        else if ((ls.status == 1 || (s->cfg.stop_rule == AHOM_STOP_RESIDUAL && ls.resid > s->cfg.tol)) && ret == AHOM_OK)
+            ret = AHOM_W_NOT_CONVERGED;
     }
     if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
     return ret;

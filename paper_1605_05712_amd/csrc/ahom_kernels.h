@@ -107,6 +107,7 @@ struct ReduceArgs {
     double* chist;
     const double* norm0;
     double cau_scale;
+    int stop_cauchy;          // 1: stop on c(n) <= tol instead of r(n) <= tol (needs chist)
 };
 
 struct FillArgs {

@@ -816,12 +816,16 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
     const double r = sqrt(v[NC_]) / sqrt(fro);
     if (n < a.hist_cap) a.hist[(int64_t)load * a.hist_cap + n] = r;
     // Cauchy measure |eps(n+1) - eps(n)| / |eps(0)| (Parseval, 1/m-normalised transform)
-    if (a.chist && n < a.hist_cap) a.chist[(int64_t)load * a.hist_cap + n] = sqrt(a.cau_scale * cs[0]) / a.norm0[load];
+    double c = r;
+    if (a.chist) {
+        c = sqrt(a.cau_scale * cs[0]) / a.norm0[load];
+        if (n < a.hist_cap) a.chist[(int64_t)load * a.hist_cap + n] = c;
+    }
     if (n == 0) st.r0 = r;
     st.resid = r;
     const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
     if (bad) { st.done = 1; st.status = 2; st.final_buf = n & 1; return; }
-    if (r <= a.tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; return; }
+    if ((a.stop_cauchy ? c : r) <= a.tol) { st.done = 1; st.status = 0; st.final_buf = n & 1; return; }
     if (n >= a.max_iter) { st.done = 1; st.status = 1; st.final_buf = n & 1; return; }
     st.iter = n + 1;
 }

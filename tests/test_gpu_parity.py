@@ -400,3 +400,28 @@ def test_device_memory_path():
     host = P.dft(a, -1, ahom.FP64)
     dev = P.dft(ahom.DeviceArray.from_numpy(a), -1, ahom.FP64).numpy()
     assert np.array_equal(dev, host)
+
+
+@pytest.mark.parametrize("M,tol", [([[64, 0], [0, 64]], 1e-9), ([[12, 0, 0], [0, 6, 0], [3, 0, 4]], 1e-8)])
+def test_cauchy_stop_rule_matches_oracle(M, tol):
+    """STOP_CAUCHY: the first n with |eps(n+1) - eps(n)| / |eps(0)| <= tol, eps(n) returned."""
+    d = len(M)
+    say("cauchy stop", M, tol)
+    P = ahom.Pattern(M)
+    lame = LAM2 if d == 2 else LAM3
+    pf = (lambda p, m: synth.laminate_phase(p, m, q=(2, 1))) if d == 2 else rnd_phase(5, 3)
+    eps_bar = np.diag([1.0, 0.0, 0.0][:d]) if d == 2 else np.diag([1.0, -0.2, 0.3])
+    S = ahom.Solver(P, tol=tol, max_iter=3000, stop_rule=ahom.STOP_CAUCHY)
+    S.set_material(lame, pf(P.points(), P.m))
+    out = S.solve(eps_bar[None] if d == 3 else np.pad(eps_bar, ((0, 1), (0, 1)))[None], want_strain=True)
+    T = make_transform(M)
+    r = E.basic_scheme(M, pf(T.points, T.m), lame, E.default_reference(lame), eps_bar, tol=tol, max_iter=3000,
+                       transform=T, stop="cauchy")
+    assert out["status"] == ahom.AHOM_OK and int(out["iters"][0]) == r.iters
+    ip = perm_between(T.points, P.points())
+    assert rel_err(out["strain"][0], tensors_to_fields(r.eps[:, :, ip])) < 1e-9
+    c = S.cauchy_history(0)
+    assert c[r.iters] <= tol and np.all(c[: r.iters] > tol)
+    with pytest.raises(ahom.AhomError) as ex:          # FP32 restarts and the Cauchy rule do not mix
+        ahom.Solver(P, precision=ahom.FP32_MIXED, tol=tol, stop_rule=ahom.STOP_CAUCHY)
+    assert ex.value.code == ahom.AHOM_E_ARG

@@ -184,3 +184,16 @@ def test_cauchy_step_from_traction_step(M):
         assert math.isclose(lhs, T.m * float(np.sum(per)), rel_tol=1e-10)
         # and the oracle's own Cauchy record is that difference
         assert math.isclose(runs[4].cauchy[n], math.sqrt(lhs) / float(np.linalg.norm(runs[0].eps)), rel_tol=1e-12)
+
+
+def test_cauchy_stop_rule_returns_first_iterate_below_tol():
+    """stop="cauchy" (Sec. 5.2): eps(n) for the first n with |eps(n+1) - eps(n)| / |eps(0)| <= tol."""
+    M = [[32, 0], [0, 32]]
+    T = make_transform(M)
+    ph = synth.laminate_phase(T.points, T.m, q=(2, 1))
+    r = E.basic_scheme(M, ph, LAM, REF, E.unit_loads(2)[0], tol=1e-9, transform=T, stop="cauchy")
+    assert r.status == 0 and len(r.cauchy) == r.iters + 1
+    assert r.cauchy[-1] <= 1e-9 and all(c > 1e-9 for c in r.cauchy[:-1])
+    # the same iterate as running exactly that many updates
+    f = E.basic_scheme(M, ph, LAM, REF, E.unit_loads(2)[0], transform=T, fixed_iters=r.iters)
+    assert np.array_equal(f.eps, r.eps)
