@@ -425,3 +425,27 @@ def test_cauchy_stop_rule_matches_oracle(M, tol):
     with pytest.raises(ahom.AhomError) as ex:          # FP32 restarts and the Cauchy rule do not mix
         ahom.Solver(P, precision=ahom.FP32_MIXED, tol=tol, stop_rule=ahom.STOP_CAUCHY)
     assert ex.value.code == ahom.AHOM_E_ARG
+
+
+def test_cauchy_measure_with_residual_period():
+    """resid_period 4: c(n) recorded on evaluated iterations only (-1 elsewhere); the
+    Cauchy stop lands on the first evaluated n with c(n) <= tol."""
+    M = [[64, 0], [0, 64]]
+    tol = 1e-8
+    say("cauchy stop, resid_period 4", M)
+    P = ahom.Pattern(M)
+    ph = synth.laminate_phase(P.points(), P.m, q=(2, 1))
+    S = ahom.Solver(P, tol=tol, max_iter=3000, resid_period=4, stop_rule=ahom.STOP_CAUCHY)
+    S.set_material(LAM2, ph)
+    out = S.solve(np.diag([1.0, 0.0, 0.0])[None])
+    n = int(out["iters"][0])
+    c = S.cauchy_history(0)
+    assert n % 4 == 0 and len(c) == n + 1
+    assert np.all(c[[k for k in range(n + 1) if k % 4]] == -1.0)
+    T = make_transform(M)
+    r = E.basic_scheme(M, synth.laminate_phase(T.points, T.m, q=(2, 1)), LAM2, E.default_reference(LAM2),
+                       np.diag([1.0, 0.0]), transform=T, fixed_iters=n + 1)
+    ev = [k for k in range(0, n + 1, 4)]
+    assert np.allclose(c[ev], np.array(r.cauchy)[ev], rtol=1e-9)
+    first = next(k for k in range(0, len(r.cauchy), 4) if r.cauchy[k] <= tol)
+    assert n == first
