@@ -129,3 +129,13 @@ def test_transformed_pattern_host_side():
         assert ex.value.code == code
     with pytest.raises(ValueError):
         ahom.Pattern([[8, 0], [0, 8]], L=np.eye(3))
+
+
+def test_stop_rule_arguments_checked_before_any_device_work():
+    P = ahom.Pattern([[8, 0], [0, 8]])
+    with pytest.raises(ahom.AhomError) as ex:
+        ahom.Solver(P, stop_rule=7)
+    assert ex.value.code == ahom.AHOM_E_ARG
+    with pytest.raises(ahom.AhomError) as ex:     # FP32 restarts and the Cauchy rule do not mix
+        ahom.Solver(P, precision=ahom.FP32_MIXED, stop_rule=ahom.STOP_CAUCHY)
+    assert ex.value.code == ahom.AHOM_E_ARG
