@@ -384,10 +384,10 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the 256^3 FP32-vs-FP64 time to tolerance")
     ap.add_argument("--no-rank1", action="store_true", help="skip the rank-1 lattice and transformed-cell throughput")
     ap.add_argument("--no-sweep", action="store_true", help="skip the Sec. 5.1 shear sweep (one batched launch)")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the learned initial guess on 64^3 ellipsoid solves and time it (minutes)")
-    ap.add_argument("--learned-train", type=int, default=64, help="training solves for --learned")
-    ap.add_argument("--learned-steps", type=int, default=400, help="Adam steps for --learned")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the learned initial guess on 64^3 ellipsoid solves and timing it (~40 s)")
+    ap.add_argument("--learned-train", type=int, default=64, help="training solves of the learned-guess leg")
+    ap.add_argument("--learned-steps", type=int, default=400, help="Adam steps of the learned-guess leg")
     ap.add_argument("--fp64-only", action="store_true", help="throughput of the FP64 path only (profiling runs)")
     ap.add_argument("--ttt-resid-period", type=int, default=4,
                     help="residual evaluated every k iterations in the time-to-tolerance solves")
@@ -486,7 +486,7 @@ def main():
     if not args.no_sweep and not args.no_batch:
         sweep = sweep_workload(ahom)
     learned = None
-    if args.learned:
+    if not args.no_learned and not args.no_ttt and not args.fp64_only:
         learned = learned_workload(ahom, args.learned_train, args.learned_steps)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
