@@ -317,6 +317,11 @@ int ahom_batch_strain(ahom_batch* b, int member, int load, double* out);
 /* Residual history of (member, load), as ahom_solver_history. */
 int ahom_batch_history(const ahom_batch* b, int member, int load, double* hist, int cap, int* count);
 
+/* Cauchy measure history of (member, load), as ahom_solver_cauchy_history
+ * (|eps(0)| = sqrt(m) |eps_bar|_F of the load; -1 on iterations whose residual
+ * is not evaluated and on the FP64 step of a restart). */
+int ahom_batch_cauchy_history(const ahom_batch* b, int member, int load, double* hist, int cap, int* count);
+
 /* Device time of the last batch launch (HIP events) and total restarts. */
 int ahom_batch_last_timing(const ahom_batch* b, double* ms, int* restarts);
 

@@ -49,7 +49,7 @@ EXPORTS = [
     "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_create_transformed",
     "ahom_batch_destroy", "ahom_batch_member_info",
     "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
-    "ahom_batch_strain", "ahom_batch_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
+    "ahom_batch_strain", "ahom_batch_history", "ahom_batch_cauchy_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
     "ahom_guess_create", "ahom_guess_destroy", "ahom_guess_num_params", "ahom_guess_get_params", "ahom_guess_set_params",
     "ahom_guess_add_sample", "ahom_guess_num_samples", "ahom_guess_gradients", "ahom_guess_train",
     "ahom_guess_adam_step", "ahom_guess_infer", "ahom_guess_predict_sample", "ahom_guess_save", "ahom_guess_load",
@@ -102,6 +102,7 @@ _lib.ahom_batch_set_reference.argtypes = [_P, ct.c_int, ct.c_double, ct.c_double
 _lib.ahom_batch_solve.argtypes = [_P, ct.c_int, _dp, _ip, _dp, _dp, _ip, ct.c_int]
 _lib.ahom_batch_strain.argtypes = [_P, ct.c_int, ct.c_int, _dp]
 _lib.ahom_batch_history.argtypes = [_P, ct.c_int, ct.c_int, _dp, ct.c_int, _ip]
+_lib.ahom_batch_cauchy_history.argtypes = [_P, ct.c_int, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_batch_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_batch_member_variant.argtypes = [_P, ct.c_int, _ip]
 _fp = ct.POINTER(ct.c_float)
@@ -444,6 +445,12 @@ class Batch:
         h = np.zeros(cap, np.float64)
         n = ct.c_int()
         _check(_lib.ahom_batch_history(self._h, i, load, _ptr(h, ct.c_double), cap, ct.byref(n)))
+        return h[: n.value]
+
+    def cauchy_history(self, i, load, cap=100000):
+        h = np.zeros(cap, np.float64)
+        n = ct.c_int()
+        _check(_lib.ahom_batch_cauchy_history(self._h, i, load, _ptr(h, ct.c_double), cap, ct.byref(n)))
         return h[: n.value]
 
     def last_timing(self):

@@ -219,7 +219,7 @@ int ahom_batch::build_items(int n_load) {
     for (int i = 0; i < nm; ++i) Sv[i] = mem[i].plan.S;
     for (int q = 0; q < n_items; ++q) {
         const int64_t S = Sv[q / n_load];
-        size_t b = 2 * align256((size_t)ncomp * S * es()) + align256((size_t)nt * S * es()) + align256((size_t)hist_cap * 8);
+        size_t b = 2 * align256((size_t)ncomp * S * es()) + align256((size_t)nt * S * es()) + 2 * align256((size_t)hist_cap * 8);
         if (ref) b += align256((size_t)nt * S * 8) + 2 * align256((size_t)ncomp * S * 16) + align256((size_t)nt * S * 16);
         off[q + 1] = off[q] + b;
     }
@@ -254,6 +254,7 @@ int ahom_batch::build_items(int n_load) {
         void* buf1 = take((size_t)ncomp * S * es());
         void* tbuf = take((size_t)nt * S * es());
         double* hist = (double*)take((size_t)hist_cap * 8);
+        double* chist = (double*)take((size_t)hist_cap * 8);
         void *toff = nullptr, *b64_0 = nullptr, *b64_1 = nullptr, *tb64 = nullptr;
         if (ref) {
             toff = take((size_t)nt * S * 8);
@@ -267,6 +268,7 @@ int ahom_batch::build_items(int n_load) {
         it.row = S / P.ax[0].slen;
         it.m = P.m;
         it.hist = hist;
+        it.chist = chist;
         it.hist_cap = hist_cap;
         it.st = d_st + q;
         it.restarts = d_restarts + q;
@@ -678,6 +680,16 @@ int ahom_batch_history(const ahom_batch* b, int member, int load, double* hist, 
     const int q = member * b->nload + load;
     const int n = std::min(cap, std::min(b->hist_cap, b->h_st[q].iter + 1));
     BCHK(hipMemcpy(hist, b->h_items[q].hist, n * sizeof(double), hipMemcpyDeviceToHost));
+    *count = n;
+    return AHOM_OK;
+}
+
+int ahom_batch_cauchy_history(const ahom_batch* b, int member, int load, double* hist, int cap, int* count) {
+    if (!b || !hist || !count || member < 0 || member >= (int)b->mem.size() || load < 0 || load >= b->nload)
+        return bfail(AHOM_E_ARG, "bad batch history arguments");
+    const int q = member * b->nload + load;
+    const int n = std::min(cap, std::min(b->hist_cap, b->h_st[q].iter + 1));
+    BCHK(hipMemcpy(hist, b->h_items[q].chist, n * sizeof(double), hipMemcpyDeviceToHost));
     *count = n;
     return AHOM_OK;
 }

@@ -166,6 +166,7 @@ struct BatchItem {
     int64_t t_real, t_spec, t_axis[AHOM_MAX_AXES];          // tiles per pass
     int64_t t_real64, t_spec64, t_axis64[AHOM_MAX_AXES];
     double* hist;                      // [hist_cap] residual history
+    double* chist;                     // [hist_cap] Cauchy measure history
     int hist_cap;
     LoadState* st;                     // result state of the item
     int* restarts;

@@ -909,14 +909,14 @@ template <typename T, int DIM>
 __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisArgs* ax, const SpecArgs& sa,
                             int64_t t_real, int64_t t_spec, const int64_t* t_axis, LoadState& st,
                             const double* sig_base, double tol, int max_iter, int resid_period, bool record,
-                            double* red, int slot, int& phase, int& rround, long long wait) {
+                            double* red, int slot, int& phase, int& rround, long long wait, double norm0) {
     constexpr int NC_ = Comp<DIM>::N;
     const int tid = threadIdx.x;
     const int k = it.k;
     for (;;) {
-        double v[NC_ + 1];
+        double v[NC_ + 2];   // stress sums, residual sum, Cauchy sum
 #pragma unroll
-        for (int c = 0; c <= NC_; ++c) v[c] = 0.0;
+        for (int c = 0; c <= NC_ + 1; ++c) v[c] = 0.0;
         // the tiles of every pass are dealt round-robin to the group's workgroups
         for (int64_t t = slot; t < t_real; t += k) {
             real_tile<T, DIM, REAL_TURN>(ra, st, 0, t, v);
@@ -933,8 +933,7 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             group_sync(it, phase, wait);
         }
         for (int64_t t = slot; t < t_spec; t += k) {
-            double cau_unused = 0.0;
-            spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_], cau_unused);
+            spec_tile<T, DIM, SPEC_TURN>(sa, st, 0, t, v[NC_], v[NC_ + 1]);
             __syncthreads();
         }
         group_sync(it, phase, wait);
@@ -946,15 +945,15 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             }
             group_sync(it, phase, wait);
         }
-        block_sum<NC_ + 1>(v, red);
+        block_sum<NC_ + 2>(v, red);
         if (k > 1) {
             // the group's partial sums, combined in slot order by every member
             double* gp = it.gpart + (rround & 1) * (k * 8);
             if (tid == 0)
-                for (int c = 0; c <= NC_; ++c) gp[slot * 8 + c] = v[c];
+                for (int c = 0; c <= NC_ + 1; ++c) gp[slot * 8 + c] = v[c];
             group_sync(it, phase, wait);
             if (tid == 0)
-                for (int c = 0; c <= NC_; ++c) {
+                for (int c = 0; c <= NC_ + 1; ++c) {
                     double acc = 0.0;
                     for (int s2 = 0; s2 < k; ++s2) acc += gp[s2 * 8 + c];
                     v[c] = acc;
@@ -973,11 +972,18 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             const int n = st.iter;
             const bool rec = record && slot == 0;
             if (!ahom_check_iter(n, resid_period, max_iter)) {
-                if (rec && n < it.hist_cap) it.hist[n] = -1.0;
+                if (rec && n < it.hist_cap) {
+                    it.hist[n] = -1.0;
+                    it.chist[n] = -1.0;
+                }
                 st.iter = n + 1;
             } else {
                 const double r = sqrt(v[NC_]) / sqrt(fro);
-                if (rec && n < it.hist_cap) it.hist[n] = r;
+                if (rec && n < it.hist_cap) {
+                    it.hist[n] = r;
+                    // Cauchy measure |eps(n+1) - eps(n)| / |eps(0)|
+                    it.chist[n] = sqrt((double)it.m * v[NC_ + 1] / (2.0 * sa.mu0 * sa.mu0)) / norm0;
+                }
                 if (n == 0) st.r0 = r;
                 st.resid = r;
                 const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
@@ -1010,10 +1016,17 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
     wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_, slot, k);
     wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S, slot, k);
     if (tid == 0) st = LoadState{};
+    // |eps(0)| = sqrt(m) |eps_bar|_F of the item's load (the Cauchy denominator)
+    double nb = 0.0;
+    for (int c = 0; c < NC_; ++c) {
+        const bool diag = DIM == 3 ? c < 3 : c < 2;
+        nb += (diag ? 1.0 : 2.0) * it.ra.eps_bar[c] * it.ra.eps_bar[c];
+    }
+    const double norm0 = sqrt((double)it.m * nb);
     group_sync(it, phase, wait);
     double stage_tol = b.refine_on ? fmax(b.tol, b.refine) : b.tol;
     batch_stage<T, DIM>(it, it.ra, it.ax, it.sa, it.t_real, it.t_spec, it.t_axis, st, nullptr, stage_tol, b.max_iter,
-                        b.resid_period, true, red, slot, phase, rround, b.group_wait);
+                        b.resid_period, true, red, slot, phase, rround, b.group_wait, norm0);
     int nres = 0;
     if constexpr (sizeof(T) == 4) {
         while (b.refine_on && st.status == 0 && st.resid > b.tol) {
@@ -1034,7 +1047,7 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
             if (tid == 0) st64 = LoadState{};
             group_sync(it, phase, wait);
             batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64,
-                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait);
+                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait, norm0);
             ++nres;
             // correction stage: e(0) = 0, t(e(-1)) = -d (written by the FP64 pass)
             if (tid == 0) {
@@ -1048,7 +1061,10 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
                 if (!(r == r) || isinf(r)) { ns.done = 1; ns.status = 2; }
                 else if (r <= b.tol) { ns.done = 1; ns.status = 0; }
                 else if (ns.iter >= b.max_iter) { ns.done = 1; ns.status = 1; }
-                if (slot == 0 && ns.done && ns.iter < it.hist_cap) it.hist[ns.iter] = r;
+                if (slot == 0 && ns.done && ns.iter < it.hist_cap) {
+                    it.hist[ns.iter] = r;
+                    it.chist[ns.iter] = -1.0;   // a restart's FP64 step: Cauchy measure not recorded
+                }
                 st = ns;
             }
             wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S, slot, k);
@@ -1057,7 +1073,7 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
             if (st.done) break;
             stage_tol = fmax(b.tol, b.refine * st.resid);
             batch_stage<T, DIM>(it, it.ra, it.ax, it.sa_corr, it.t_real, it.t_spec, it.t_axis, st, sbase, stage_tol,
-                                b.max_iter, b.resid_period, true, red, slot, phase, rround, b.group_wait);
+                                b.max_iter, b.resid_period, true, red, slot, phase, rround, b.group_wait, norm0);
         }
     }
     if (tid == 0 && slot == 0) {
@@ -1069,7 +1085,7 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
 template <typename T, int DIM>
 __global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
     constexpr int NC_ = Comp<DIM>::N;
-    __shared__ double red[(NC_ + 1) * AHOM_WG];
+    __shared__ double red[(NC_ + 2) * AHOM_WG];
     __shared__ LoadState st, st64;
     __shared__ double sbase[NC_];
     __shared__ int qi;
@@ -1100,7 +1116,7 @@ int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t 
 
 size_t ahom_batch_static_lds(int dim) {
     const int nc = dim == 3 ? 6 : 3;
-    return (size_t)(nc + 1) * AHOM_WG * 8 + 2 * sizeof(LoadState) + nc * 8 + 16;
+    return (size_t)(nc + 2) * AHOM_WG * 8 + 2 * sizeof(LoadState) + nc * 8 + 16;
 }
 
 int ahom_batch_occupancy(int prec, int dim, size_t lds) {

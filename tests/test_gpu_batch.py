@@ -65,6 +65,7 @@ def test_batch_fields_match_oracle_after_fixed_iterations():
             r = E.basic_scheme(M, ph, lame, E.default_reference(lame), eb[:2, :2], transform=T, fixed_iters=3)
             assert rel_err(B.strain(i, l), tensors_to_fields(r.eps[:, :, ip])) < 1e-10, (seeds[i], l)
             assert np.allclose(B.history(i, l), r.history, rtol=1e-9), (seeds[i], l)
+            assert np.allclose(B.cauchy_history(i, l)[:3], r.cauchy, rtol=1e-9), (seeds[i], l)
             assert np.allclose(out["mean_stress"][i, l][:2, :2], r.mean_stress, rtol=1e-10, atol=1e-14)
 
 

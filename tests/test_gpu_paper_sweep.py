@@ -69,6 +69,7 @@ def test_batch_of_3d_members_matches_oracle_after_fixed_iterations():
         ip = perm_between(T.points, B.points(i))
         assert rel_err(B.strain(i, 0), tensors_to_fields(r.eps[:, :, ip])) < 1e-10, M
         assert np.allclose(B.history(i, 0), r.history, rtol=1e-9), M
+        assert np.allclose(B.cauchy_history(i, 0)[:3], r.cauchy, rtol=1e-9), M
         assert np.allclose(out["mean_stress"][i, 0], r.mean_stress, rtol=1e-10, atol=1e-13), M
 
 
