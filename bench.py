@@ -395,7 +395,7 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(load cases shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
