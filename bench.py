@@ -396,7 +396,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(load cases shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+              "(load cases would shard across GPUs with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
