@@ -540,6 +540,18 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
             for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v < 4 ? v : 0;
             s->tuned = true;
         }
+        // per-pass pin "real,spec,axis" (profiling runs that must execute the
+        // kernels another run tuned); a variant a pass lacks falls back to 0
+        const char* penv = getenv("AHOM_FAST_VARIANTS");
+        int vr = -1, vs = -1, va = -1;
+        if (penv && std::sscanf(penv, "%d,%d,%d", &vr, &vs, &va) == 3 && vr >= 0 && vr <= 4 && vs >= 0 && vs <= 3 &&
+            va >= 0 && va <= 3) {
+            FastGeom fgp;
+            s->v_real = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, vr, &fgp) ? vr : 0;
+            s->v_spec = vs;
+            for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = va;
+            s->tuned = true;
+        }
         s->apply_variants();
     }
     if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
