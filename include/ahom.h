@@ -170,15 +170,21 @@ void ahom_solver_destroy(ahom_solver* s);
 int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags);
 
 /*
- * Per-point isotropic stiffness: lame_pts[2*i], lame_pts[2*i+1] = (lambda,
- * mu) at canonical point i (m*2 doubles).  Replaces any phase table.
+ * Per-point isotropic stiffness (Sec. 3.2: the stiffness field C(x) is only
+ * needed at the pattern points y, collocation): lame_pts[2*i],
+ * lame_pts[2*i+1] = (lambda, mu) at canonical point i (m*2 doubles, host or,
+ * with AHOM_MEM_DEVICE, device memory; copied).  Replaces any phase table.
+ * Errors: AHOM_E_MATERIAL (some mu <= 0 or 3 lambda + 2 mu <= 0), AHOM_E_ARG.
  */
 int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int mem_flags);
 
 /*
- * Reference medium C0 (isotropic Lame pair).  If never called, the mean of
- * the extreme values over the material (phase table or field) is used.
- * Errors: AHOM_E_MATERIAL for mu0 <= 0 or lambda0 + 2 mu0 <= 0.
+ * Reference medium C0 of the Lippmann-Schwinger equation (Sec. 3.1; Gamma0 is
+ * built from it): an isotropic Lame pair.  The paper's numerics do not state
+ * C0; if never called, the mean of the extreme values over the material
+ * (phase table or field) is used, (lambda_min + lambda_max) / 2 and
+ * (mu_min + mu_max) / 2.  Errors: AHOM_E_MATERIAL for mu0 <= 0 or
+ * lambda0 + 2 mu0 <= 0.
  */
 int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0);
 
@@ -194,7 +200,7 @@ int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0);
  * Any of iters, resid, mean_stress may be NULL.
  * Returns AHOM_OK if every load converged, AHOM_W_NOT_CONVERGED if some load
  * reached max_iter (outputs hold that iterate), AHOM_E_DIVERGED if some
- * load diverged, or an error.
+ * load diverged, or an error (AHOM_E_ARG for init with the Cauchy stop rule).
  * AHOM_FP32_MIXED with refine > 0: after each FP32 stage the iterate is
  * handed to FP64 (see ahom_config.refine); a restart performs two FP64
  * updates and advances n_k by one, and the returned strain is the FP64
@@ -204,9 +210,11 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
                int* iters, double* resid, double* mean_stress, int mem_flags);
 
 /*
- * Effective stiffness in Mandel form (c x c row-major, c = 6 or 3): runs the
- * c Mandel unit loads as one batched solve; column k is Mandel(<sigma>) of
- * load k.  iters: NULL or c ints.  Same return codes as ahom_solve.
+ * Effective stiffness (Def. 3.1: C_eff : eps_bar is the mean stress <sigma>
+ * of the solution for the macroscopic strain eps_bar) in Mandel form (c x c
+ * row-major, c = 6 or 3): runs the c Mandel unit loads as one batched solve;
+ * column k is Mandel(<sigma>) of load k.  iters: NULL or c ints.  Same
+ * return codes as ahom_solve.
  */
 int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters);
 
@@ -243,15 +251,17 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
 int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
 
 /*
- * Cauchy measure of Sec. 5.2 beside the residual (reported, not a stop rule):
+ * Cauchy measure of Sec. 5.2 beside the residual (the stop rule when
+ * ahom_config.stop_rule = AHOM_STOP_CAUCHY):
  * c(n) = |eps(n+1) - eps(n)|_{l2(P(M))} / |eps(0)|, Frobenius norms summed over
- * the points, |eps(0)| = sqrt(m) |eps_bar|_F (the start without an initial
- * guess; the same normalisation is kept with one).  Evaluated on the
- * iterations whose residual is evaluated (-1 elsewhere) from the traction
- * step the residual uses: on active frequencies eps_hat(n+1) - eps_hat(n) =
- * -sym(xi (x) K(xi)^{-1} (t(n) - t(n-1))).  With a user initial guess that is
- * not compatible, c(0) measures against its compatible part.  Same output
- * convention as ahom_solver_history.
+ * the points, |eps(0)| = sqrt(m) |eps_bar|_F.  Evaluated on the iterations
+ * whose residual is evaluated (-1 elsewhere) from the traction step the
+ * residual uses: on active frequencies eps_hat(n+1) - eps_hat(n) =
+ * -sym(xi (x) K(xi)^{-1} (t(n) - t(n-1))).  With a user initial guess the
+ * denominator stays sqrt(m) |eps_bar|_F (not the norm of the guessed start),
+ * and c(0) measures against the compatible part of the guess; the Cauchy
+ * stop rule therefore rejects an initial guess (AHOM_E_ARG from ahom_solve).
+ * Same output convention as ahom_solver_history.
  */
 int ahom_solver_cauchy_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
 

@@ -8,14 +8,19 @@ Two routes:
 * ``NaiveDFT``: the matrix written out with exact integer phases
   r = (h . p) mod m for y = p/m, O(m^2); for small patterns.
 * ``SnfFFT``: the oracle's own Smith-normal-form addressing (see
-  ``lattice.SnfIndexing``) and numpy's d_M-dimensional FFT, as Sec. 2.2
-  states the pattern DFT reduces to one.  Cross-checked against NaiveDFT.
+  ``lattice.SnfIndexing``) and a library d_M-dimensional FFT (scipy.fft,
+  threaded over the host cores; ``AHOM_ORACLE_WORKERS`` caps the threads), as
+  Sec. 2.2 states the pattern DFT reduces to one.  Cross-checked against
+  NaiveDFT.
 Both act on the last axes of arrays shaped (..., m) in the point order /
 frequency order the object exposes as ``points`` / ``freqs``.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft
 
 from .lattice import SnfIndexing, int_det, as_int_matrix, pattern_points, generating_set, transpose
 
@@ -41,6 +46,12 @@ class NaiveDFT:
         return np.asarray(ahat) @ self.Finv.T
 
 
+def fft_workers():
+    """Threads of the library FFT: all host cores unless AHOM_ORACLE_WORKERS is set."""
+    env = os.environ.get("AHOM_ORACLE_WORKERS")
+    return max(1, int(env)) if env else (os.cpu_count() or 1)
+
+
 class SnfFFT:
     def __init__(self, M):
         self.idx = SnfIndexing(M)
@@ -54,14 +65,14 @@ class SnfFFT:
         lead = a.shape[:-1]
         A = a.reshape(lead + self.shape)
         axes = tuple(range(len(lead), len(lead) + len(self.shape)))
-        return (np.fft.fftn(A, axes=axes) / self.m).reshape(lead + (self.m,))
+        return (scipy.fft.fftn(A, axes=axes, workers=fft_workers()) / self.m).reshape(lead + (self.m,))
 
     def inverse(self, ahat):
         ahat = np.asarray(ahat)
         lead = ahat.shape[:-1]
         A = ahat.reshape(lead + self.shape)
         axes = tuple(range(len(lead), len(lead) + len(self.shape)))
-        return (np.fft.ifftn(A, axes=axes) * self.m).reshape(lead + (self.m,))
+        return (scipy.fft.ifftn(A, axes=axes, workers=fft_workers()) * self.m).reshape(lead + (self.m,))
 
 
 def make_transform(M, naive_limit=1024):

@@ -177,9 +177,34 @@ def wave_vectors(H, cell=None):
     return Hf @ np.linalg.inv(np.asarray(cell, dtype=np.float64))
 
 
+def lippmann_schwinger_map(T, C0, K, upd, zero, eps_bar, eps, sigma, rule="hermitian"):
+    """The fixed-point map of the collocated Lippmann-Schwinger equation (Sec. 3.1-3.2).
+
+    With the polarization tau = sigma - C0 : eps = (C - C0) : eps, the
+    equation eps = eps_bar - Gamma0 * tau holds at the solution; evaluated on
+    the pattern, the convolution is a product per frequency of G(M^T):
+        eps_new = F(M)^{-1} [ eps_bar at h = 0;  -Gamma0(k_h) tau_hat_h on the
+                  active h != 0 (rows `upd`);  0 on the unpaired classes ].
+    K: the wave vectors of the frequencies (L^{-T} h on P_L(M)).
+    Returns the real field eps_new (its imaginary part vanishes under the
+    Hermitian rule and is dropped).
+    """
+    tau_hat = T.forward(sigma - contract(C0, eps))
+    eps_hat = np.zeros_like(tau_hat)
+    eps_hat[:, :, upd] = gamma0_apply(C0, K[upd], tau_hat[:, :, upd])
+    eps_hat[:, :, zero] = eps_bar
+    new = T.inverse(eps_hat)
+    if rule == "hermitian":
+        assert np.max(np.abs(new.imag)) <= 1e-9 * max(1.0, np.max(np.abs(new.real)))
+    return new.real
+
+
 def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=None,
                  transform=None, rule="hermitian", fixed_iters=None, cell=None, stop="residual"):
-    """Algorithm 1 on P(M) (or on P_L(M) with cell = L) with the equilibrium-residual stop.
+    """The Basic Scheme (Algorithm 1, Sec. 3.2) on P(M), or on P_L(M) with cell = L.
+
+    Picard iteration of ``lippmann_schwinger_map`` from eps(0) = eps_bar
+    (+ init), stopped on the equilibrium residual of the current iterate.
 
     phase: (m,) ints in the transform's point order; lame: (n_phase, 2) rows
     (lambda, mu); lame0 = (lambda0, mu0); eps_bar: (d, d) macroscopic strain;
@@ -222,15 +247,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
         if n == (fixed_iters if fixed_iters is not None else max_iter):
             status = 0 if fixed_iters is not None else 1
             return SchemeResult(eps, n, r, status, mean, hist, cauchy)
-        tau = sigma - contract(C0, eps)
-        tau_hat = T.forward(tau)
-        eps_hat = np.zeros_like(tau_hat)
-        eps_hat[:, :, upd] = gamma0_apply(C0, K[upd], tau_hat[:, :, upd])
-        eps_hat[:, :, zero] = eps_bar
-        new = T.inverse(eps_hat)
-        if rule == "hermitian":
-            assert np.max(np.abs(new.imag)) <= 1e-9 * max(1.0, np.max(np.abs(new.real)))
-        new = new.real
+        new = lippmann_schwinger_map(T, C0, K, upd, zero, eps_bar, eps, sigma, rule)
         cauchy.append(float(np.linalg.norm(new - eps)) / norm0)
         if fixed_iters is None and stop == "cauchy" and cauchy[-1] <= tol:
             return SchemeResult(eps, n, r, 0, mean, hist, cauchy)

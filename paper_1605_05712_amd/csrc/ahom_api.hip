@@ -822,6 +822,8 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
                int* iters, double* resid, double* mean_stress, int mem_flags) {
     if (!s || !eps_bar || n_load < 1) return fail(AHOM_E_ARG, "bad solve arguments");
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
+    if (init && s->cfg.stop_rule == AHOM_STOP_CAUCHY)
+        return fail(AHOM_E_ARG, "the Cauchy stop rule measures against sqrt(m) |eps_bar|, not a guessed start: no init");
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;

@@ -1496,6 +1496,14 @@ bool geom_TV(int kind, int dim, int L, FastGeom* g) {
 #undef AHOM_G
 }
 
+// Geometry of the kernel that a launch of variant V runs for length L: axes
+// shorter than the tuned lengths instantiate variant 0 only, so their launch
+// geometry (threads, LDS, grid) must be variant 0's as well.
+template <typename T, int V>
+bool geom_launch(int kind, int dim, int L, FastGeom* g) {
+    return tuned_length(L) ? geom_TV<T, V>(kind, dim, L, g) : geom_TV<T, 0>(kind, dim, L, g);
+}
+
 // Set the LDS attribute and return the grid: one workgroup per tile, or for
 // the persistent schedule the workgroups that fit on the device at once
 // (occupancy API: registers, LDS and threads), capped by the tiles.
@@ -1522,7 +1530,7 @@ int go(F fn, const FastGeom& g, int64_t total, int ncu, hipStream_t s, const A& 
 template <typename T, int V>
 int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_TV<T, V>(FAST_REAL, dim, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_REAL, dim, L, &g)) return -1;
     // the phase table (Lame pairs in the working precision) follows in LDS
     if (!a.lame_pts_t && (a.n_phase < 1 || a.n_phase > 256 || !a.lame_tab)) return -1;
     if (!a.lame_pts_t) g.lds += (size_t)a.n_phase * 2 * sizeof(T);
@@ -1540,7 +1548,7 @@ int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream
 template <typename T, int V>
 int axis_TV(int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_TV<T, V>(FAST_AXIS, 3, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_AXIS, 3, L, &g)) return -1;
 #define AHOM_FA(LL)                                                                    \
     case LL:                                                                           \
         return dir < 0 ? go(kf_axis<T, LL, -1, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
@@ -1555,7 +1563,7 @@ int axis_TV(int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream
 template <typename T, int V>
 int spec_TV(int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_TV<T, V>(FAST_SPEC, dim, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_SPEC, dim, L, &g)) return -1;
 #define AHOM_FS(LL)                                                                    \
     case LL:                                                                           \
         return dim == 3 ? go(kf_spec<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \

@@ -1,10 +1,13 @@
-"""Write spheres_c3_32.json: oracle C_eff of the sphere workload on diag(32,32,32).
+"""Write spheres_c3_<n>.json: oracle C_eff of the sphere workload on diag(n,n,n).
 
 Random sequential addition of periodic spheres (numpy PCG64 seed 3, radii
 U[0.03, 0.08], volume fraction 0.3), matrix E = 1 and inclusions E = 100,
-nu = 0.25 (the 3-D precision workload, coarsened to 32^3 so the CPU FP64
-oracle can converge all 6 unit loads to a 1e-10 residual).  Calls only the
-oracle and the shared generators.
+nu = 0.25 (the 3-D precision workload of 256^3, coarsened so that the CPU
+FP64 oracle can converge all 6 unit loads: 32^3 to a 1e-10 residual, 64^3 to
+1e-8; 256^3 would take days on the host).  Calls only the oracle and the
+shared generators.
+
+Usage: python tests/golden/make_spheres.py [n] [tol]
 """
 import json
 import os
@@ -36,4 +39,7 @@ def main(n=32, tol=1e-10):
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1:
+        main(int(sys.argv[1]), float(sys.argv[2]))
+    else:
+        main()

@@ -63,22 +63,36 @@ def test_laminate_64_fp64_vs_oracle_and_closed_form():
 
 
 def test_hashin_128_two_updates_match_oracle():
-    """Full size 128^3: strain after 2 updates and residuals equal the oracle's."""
+    """Full size 128^3: strain after 2 updates and residuals equal the oracle's,
+    in FP64 (1e-10) and in FP32 (fields 1e-5 of max|eps|, residuals 1e-3
+    relative, mean stress 1e-5: the FP32 kernels of the workload, length 128)."""
     g, geom, lame = hashin_inputs()
     M = [[128, 0, 0], [0, 128, 0], [0, 0, 128]]
-    say("hashin 128^3 fields", M)
-    P = ahom.Pattern(M)
-    pts = P.points()
-    S = ahom.Solver(P, tol=0.0, max_iter=2)
-    S.set_material(lame, synth.hashin_phase(pts, P.m, geom))
     eps0 = np.array(g["eps0"])
-    out = S.solve(eps0[None], want_strain=True)
     T = make_transform(M)
     r = E.basic_scheme(M, synth.hashin_phase(T.points, T.m, geom), lame, E.default_reference(lame), eps0, transform=T, fixed_iters=2)
+    P = ahom.Pattern(M)
+    pts = P.points()
     ip = perm_between(T.points, pts)
-    assert rel_err(out["strain"][0], tensors_to_fields(r.eps[:, :, ip])) < 1e-10
-    assert np.allclose(S.history(0), r.history, rtol=1e-10)
-    assert np.allclose(out["mean_stress"][0], r.mean_stress, rtol=1e-10)
+    ref = tensors_to_fields(r.eps[:, :, ip])
+    del T
+    ph = synth.hashin_phase(pts, P.m, geom)
+    for prec in (ahom.FP64, ahom.FP32_MIXED):
+        say("hashin 128^3 fields", M, "prec", prec)
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=2, refine=-1.0)
+        S.set_material(lame, ph)
+        out = S.solve(eps0[None], want_strain=True)
+        err = rel_err(out["strain"][0], ref)
+        print(f"  prec {prec}: field err {err:.2e}", flush=True)
+        if prec == ahom.FP64:
+            assert err < 1e-10
+            assert np.allclose(S.history(0), r.history, rtol=1e-10)
+            assert np.allclose(out["mean_stress"][0], r.mean_stress, rtol=1e-10)
+        else:
+            assert err < 1e-5
+            assert np.allclose(S.history(0), r.history, rtol=1e-3)
+            assert np.allclose(out["mean_stress"][0], r.mean_stress, rtol=1e-5, atol=1e-6 * np.abs(r.mean_stress).max())
+        del S
 
 
 def test_hashin_128_ceff_closed_form_fp64_and_fp32():
@@ -140,12 +154,15 @@ def sphere_lame():
     return np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
 
 
-def test_spheres_32_fp32_vs_fp64_oracle():
-    """FP32 mixed precision, contrast 100: every C_eff entry vs the FP64 oracle.
+@pytest.mark.parametrize("n", [32, 64])
+def test_spheres_fp32_vs_fp64_oracle(n):
+    """The precision workload's recipe (spheres, contrast 100) coarsened to n^3:
+    FP32 mixed precision with restarts, every C_eff entry vs the FP64 oracle's
+    converged C_eff (tests/golden/make_spheres.py).
 
     Bound: |C32_ij - Coracle_ij| <= 1e-5 max|C| (FP32 run stopped at r <= 1e-6).
     """
-    gold = json.load(open(os.path.join(GOLD, "spheres_c3_32.json")))
+    gold = json.load(open(os.path.join(GOLD, f"spheres_c3_{n}.json")))
     n = gold["n"]
     M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
     say("spheres 32^3 fp32", M)

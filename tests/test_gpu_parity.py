@@ -130,6 +130,58 @@ def test_fields_after_fixed_iterations(name, M, lame, pf, d):
     assert np.allclose(ms, r.mean_stress, rtol=1e-10, atol=1e-12 * np.abs(r.mean_stress).max())
 
 
+# Patterns whose 256-long Smith axes land in each pass of the power-of-two
+# kernels: diag(1,256,256) runs the 3-D real-space and spectral turnarounds
+# at length 256, diag(2,256,256) adds a 256-long middle-axis pass, and the
+# 2-D grid runs the 2-D turnarounds at 256.
+LONG_AXIS_CASES = [
+    ("3-D 1x256x256", [[1, 0, 0], [0, 256, 0], [0, 0, 256]], 3),
+    ("3-D 2x256x256", [[2, 0, 0], [0, 256, 0], [0, 0, 256]], 3),
+    ("2-D 256x256", [[256, 0], [0, 256]], 2),
+]
+
+
+@pytest.mark.parametrize("name,M,d", LONG_AXIS_CASES, ids=[c[0] for c in LONG_AXIS_CASES])
+def test_256_long_axes_match_oracle(name, M, d):
+    """The 256-long power-of-two kernels (the 256^3 workload's path) against the
+    oracle: strain after N updates, residual history and mean stress.  FP64 to
+    1e-10; FP32 fields to 1e-5 of max|eps| (single-precision transforms of
+    length 256 per axis, a few ulp per stage) and residuals to 1e-3 relative
+    (the residual is a difference of two FP32 tractions)."""
+    N = 3
+    pf = rnd_phase(41, 3)
+    rng = np.random.default_rng(19)
+    A = rng.standard_normal((d, d))
+    eps_bar = 0.5 * (A + A.T)
+    T, r = oracle_case(M, LAM3, pf, eps_bar, fixed_iters=N)
+    P = ahom.Pattern(M)
+    assert 256 in P.e.tolist()
+    ip = perm_between(T.points, P.points())
+    ref = tensors_to_fields(r.eps[:, :, ip])
+    ph = pf(P.points(), P.m)
+    eb = eps_bar[None] if d == 3 else np.pad(eps_bar, ((0, 1), (0, 1)))[None]
+    for prec in (ahom.FP64, ahom.FP32_MIXED):
+        say("long axes", name, M, "N", N, "prec", prec)
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=N, check_period=4, refine=-1.0)
+        S.set_material(LAM3, ph)
+        out = S.solve(eb, want_strain=True)
+        assert int(out["iters"][0]) == N
+        err = rel_err(out["strain"][0], ref)
+        hist = S.history(0)
+        ms = out["mean_stress"][0][:d, :d]
+        print(f"  prec {prec}: field err {err:.2e}, resid err "
+              f"{np.max(np.abs(hist - r.history) / np.array(r.history)):.2e}", flush=True)
+        if prec == ahom.FP64:
+            assert err < 1e-10
+            assert np.allclose(hist, r.history, rtol=1e-10, atol=0)
+            assert np.allclose(ms, r.mean_stress, rtol=1e-10, atol=1e-12 * np.abs(r.mean_stress).max())
+        else:
+            assert err < 1e-5
+            assert np.allclose(hist, r.history, rtol=1e-3, atol=0)
+            assert np.allclose(ms, r.mean_stress, rtol=1e-5, atol=1e-6 * np.abs(r.mean_stress).max())
+        del S
+
+
 def test_converged_ceff_laminate_and_symmetry():
     M = [[32, 0], [0, 32]]
     say("ceff laminate", M)
@@ -266,6 +318,9 @@ VARIANT_CASES = [
     ("3-D 128x64x256 fp32", [[128, 0, 0], [0, 64, 0], [0, 0, 256]], ahom.FP32_MIXED),
     ("2-D 256x256 sheared", [[256, 0], [64, 256]], ahom.FP64),
     ("rank-1 2^18", [[262144, 0, 0], [5, 1, 0], [25, 0, 1]], ahom.FP64),
+    # 16-long real-space and middle axes: pinned variants 1-3 must launch the
+    # variant-0 geometry those lengths are compiled with
+    ("3-D 16x16x256 fp32", [[16, 0, 0], [0, 16, 0], [0, 0, 256]], ahom.FP32_MIXED),
 ]
 
 
