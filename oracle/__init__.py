@@ -15,6 +15,8 @@ dft           naive pattern DFT F(M) (eq. Fouriermatrix) and a fast route
 elasticity    stiffness tensors, the Green operator Gamma^0 (Sec. 3.1),
               Algorithm 1 with the equilibrium residual, C_eff (Def. 3.1).
 closed_forms  laminate (Sec. 4.1) and generalized Hashin structure (Sec. 4.2).
+accelerated   conjugate gradients on the same Lippmann-Schwinger system (the
+              accelerated schemes named in Sec. 1 and Sec. 6).
 
 Readings of the paper where it is silent or garbled are listed in the
 module docstrings where they are applied.
