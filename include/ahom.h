@@ -88,10 +88,23 @@ typedef struct ahom_config {
                            first evaluated n with c(n) = |eps(n+1) - eps(n)| / |eps(0)| <= tol
                            (see ahom_solver_cauchy_history) and return eps(n).  Single-pattern
                            solver only; in AHOM_FP32_MIXED it needs refine < 0. */
+    int scheme;         /* AHOM_SCHEME_BASIC (0, default): Algorithm 1 (Sec. 3.2).
+                           AHOM_SCHEME_CG (1): conjugate gradients on the same discrete
+                           Lippmann-Schwinger system (the accelerated schemes the paper
+                           names in Sec. 1 and Sec. 6): x = eps - eps_bar compatible with
+                           zero mean, A x = Gamma0 * (C : x) = -Gamma0 * (C : eps_bar), in
+                           the C0 inner product sum_x u : C0 : v, in which A is symmetric
+                           positive definite on compatible fields.  Each update costs one
+                           sweep of the passes plus two vector kernels; the stop test, the
+                           history and the outputs are those of the Basic Scheme (r(n) of
+                           eps(n) = eps_bar + x_n; n = updates performed).  Single-pattern
+                           solver, AHOM_FP64, AHOM_STOP_RESIDUAL, no init. */
 } ahom_config;
 
 #define AHOM_STOP_RESIDUAL 0
 #define AHOM_STOP_CAUCHY 1
+#define AHOM_SCHEME_BASIC 0
+#define AHOM_SCHEME_CG 1
 
 /* Library version, (major << 16) | (minor << 8) | patch. */
 int ahom_version(void);

@@ -39,6 +39,8 @@ MEM_DEVICE = 1
 NYQUIST_HERMITIAN = 0
 STOP_RESIDUAL = 0
 STOP_CAUCHY = 1
+SCHEME_BASIC = 0
+SCHEME_CG = 1
 
 EXPORTS = [
     "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_create_transformed", "ahom_pattern_destroy",
@@ -60,7 +62,7 @@ EXPORTS = [
 class Config(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p),
-                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int)]
+                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int), ("scheme", ct.c_int)]
 
 
 _P = ct.c_void_p
@@ -274,12 +276,13 @@ class Solver:
     """Algorithm 1 on a pattern (device buffers owned by the library)."""
 
     def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1,
-                 refine=0.0, stop_rule=0):
-        """stop_rule: STOP_RESIDUAL (r(n) <= tol) or STOP_CAUCHY (the Sec. 5.2 criterion)."""
+                 refine=0.0, stop_rule=0, scheme=SCHEME_BASIC):
+        """stop_rule: STOP_RESIDUAL (r(n) <= tol) or STOP_CAUCHY (the Sec. 5.2 criterion);
+        scheme: SCHEME_BASIC (Algorithm 1) or SCHEME_CG (conjugate gradients)."""
         self.pattern = pattern
         self.ncomp = 6 if pattern.d == 3 else 3
         self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period, refine,
-                          stop_rule)
+                          stop_rule, scheme)
         h = _P()
         _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
         self._h = h

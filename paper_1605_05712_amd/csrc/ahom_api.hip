@@ -151,6 +151,17 @@ struct ahom_solver {
     bool borrowed = false;
     void* d_toff = nullptr;
     double* d_sigbase = nullptr;
+    // conjugate gradients (cfg.scheme == AHOM_SCHEME_CG): iterate, residual
+    // field, scalars, and the partial sums of <p, C p> and <r, r>_C0
+    bool cg = false;
+    void* d_x = nullptr;
+    void* d_r = nullptr;
+    CgScalars* d_cg = nullptr;
+    double* d_alpha = nullptr;
+    double* d_en = nullptr;
+    double* d_rr = nullptr;
+    double* d_zero6 = nullptr;     // [load][ncomp] zeros: the mean of the operator output
+    int cg_nblk = 1;
     // per-stage settings read by the launches
     double cur_tol = 0.0;
     const void* spec_toff = nullptr;
@@ -213,6 +224,7 @@ struct ahom_solver {
     int release_buffers() {
         dfree(d_buf0); dfree(d_buf1); dfree(d_tbuf); dfree(d_st); dfree(d_sig);
         dfree(d_res); dfree(d_hist); dfree(d_cau); dfree(d_chist); dfree(d_norm0); dfree(d_epsbar); dfree(d_real); dfree(d_toff); dfree(d_sigbase);
+        dfree(d_x); dfree(d_r); dfree(d_cg); dfree(d_alpha); dfree(d_en); dfree(d_rr); dfree(d_zero6);
         if (h_st) (void)hipHostFree(h_st);
         h_st = nullptr;
         cap = 0;
@@ -251,6 +263,17 @@ struct ahom_solver {
             HIPCHK(hipMalloc(&d_toff, tb));
             HIPCHK(hipMemset(d_toff, 0, tb));
         }
+        if (cg) {
+            cg_nblk = ahom_cg_blocks(P.S);
+            HIPCHK(hipMalloc(&d_x, fb));
+            HIPCHK(hipMalloc(&d_r, fb));
+            HIPCHK(hipMalloc((void**)&d_cg, (size_t)nload * sizeof(CgScalars)));
+            HIPCHK(hipMalloc((void**)&d_alpha, (size_t)nload * sizeof(double)));
+            HIPCHK(hipMalloc((void**)&d_en, (size_t)nload * std::max(g_real.nwg, mt_real) * sizeof(double)));
+            HIPCHK(hipMalloc((void**)&d_rr, (size_t)nload * cg_nblk * sizeof(double)));
+            HIPCHK(hipMalloc((void**)&d_zero6, (size_t)nload * ncomp * sizeof(double)));
+            HIPCHK(hipMemset(d_zero6, 0, (size_t)nload * ncomp * sizeof(double)));
+        }
         cap = nload;
         return AHOM_OK;
     }
@@ -281,8 +304,11 @@ struct ahom_solver {
         a.phase_t = d_phase_t;
         a.lame_pts_t = d_lame_pts_t;
         a.n_phase = d_lame_pts_t ? 0 : n_phase;
-        a.lam0 = lam0;
-        a.mu0 = mu0;
+        // conjugate gradients apply C itself (reference constants zero) and
+        // collect <p, C p>
+        a.lam0 = cg ? 0.0 : lam0;
+        a.mu0 = cg ? 0.0 : mu0;
+        a.en_part = cg ? d_en : nullptr;
         a.sig_part = d_sig;
         a.real_io = d_real;
         a.eps_bar = d_epsbar;
@@ -329,6 +355,12 @@ struct ahom_solver {
         a.toff = spec_toff;
         a.dout = spec_dout;
         a.dneg = spec_dneg;
+        if (cg) {
+            // operator output of zero mean, traction recurrence every iteration
+            a.eps_bar = d_zero6;
+            a.cg_alpha = d_alpha;
+            a.resid_period = 1;
+        }
         return a;
     }
 
@@ -390,6 +422,57 @@ struct ahom_solver {
     }
 };
 
+// ------------------------------------------------------- conjugate gradients
+// One CG update per load (see ahom_cg.hip): the operator sweep on the
+// direction p(n) (buf[n & 1] -> -A p(n) in buf[(n + 1) & 1]), alpha, the
+// vector update of x and r, <r, r>_C0, beta and the stop test, the new
+// direction.  With start = 1: the sweep on eps_bar gives r(0) = p(0) and the
+// residual r(0) of eps_bar.
+namespace {
+int cg_sweep(ahom_solver* s, int nload, int start) {
+    const Plan& P = s->pat->plan;
+    hipStream_t st = s->stream;
+    CgArgs c{};
+    c.st = s->d_st;
+    c.cg = s->d_cg;
+    c.alpha = s->d_alpha;
+    c.buf0 = s->d_buf0;
+    c.buf1 = s->d_buf1;
+    c.xbuf = s->d_x;
+    c.rbuf = s->d_r;
+    c.sig_part = s->d_sig;
+    c.en_part = s->d_en;
+    c.res_part = s->d_res;
+    c.rr_part = s->d_rr;
+    c.hist = s->d_hist;
+    c.n_real = s->n_real_wg();
+    c.n_spec = s->n_spec_wg();
+    c.nblk = s->cg_nblk;
+    c.hist_cap = s->hist_cap;
+    c.S = P.S;
+    c.I = P.S / P.ax[0].slen;
+    c.m = P.m;
+    c.L0 = P.ax[0].len;
+    c.lam0 = s->lam0;
+    c.mu0 = s->mu0;
+    c.tol = s->cfg.tol;
+    c.max_iter = s->cfg.max_iter;
+    c.start = start;
+    if (s->launch_real_turn(nload, st)) return fail(AHOM_E_DEVICE, "launch real-space pass failed");
+    if (ahom_launch_cg_alpha(s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_alpha failed");
+    for (int a = 1; a <= P.D - 2; ++a)
+        if (s->launch_axis(a, -1, nload, st)) return fail(AHOM_E_DEVICE, "launch axis pass failed");
+    if (s->launch_spec(nload, st)) return fail(AHOM_E_DEVICE, "launch spectral pass failed");
+    for (int a = P.D - 2; a >= 1; --a)
+        if (s->launch_axis(a, +1, nload, st)) return fail(AHOM_E_DEVICE, "launch axis pass failed");
+    if (ahom_launch_cg_update(s->prec, s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_update failed");
+    if (ahom_launch_cg_reduce(s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_reduce failed");
+    if (!start && ahom_launch_cg_direction(s->prec, s->dim, c, nload, st))
+        return fail(AHOM_E_DEVICE, "launch k_cg_direction failed");
+    return AHOM_OK;
+}
+}  // namespace
+
 // ---------------------------------------------------------------- autotuner
 // Times every compiled tile variant of each power-of-two pass on the solver's
 // own buffers and keeps the fastest.  Results are cached per process by
@@ -414,7 +497,10 @@ std::mutex& tune_mutex() {
 }  // namespace
 
 int ahom_solver::autotune(int nload) {
-    if (tuned || !use_fast) return AHOM_OK;
+    if (tuned || !use_fast) {
+        if (cg && v_real == 4) { v_real = 0; apply_variants(); }
+        return AHOM_OK;
+    }
     const Plan& P = pat->plan;
     hipStream_t st = stream;
     const char* venv = getenv("AHOM_VERBOSE");
@@ -452,6 +538,7 @@ int ahom_solver::autotune(int nload) {
             for (auto& o : seen) dup = dup || (o.NC == fg.NC && o.persistent == fg.persistent);
             if (dup) continue;
             seen.push_back(fg);
+            if (cg && kind == FAST_REAL && v == 4) continue;   // no <p, C p> sums in the register-resident variant
             *vsel = v;
             apply_variants();
             float ms = 0.f;
@@ -476,6 +563,7 @@ int ahom_solver::autotune(int nload) {
         if (f_axis[a] && (rc = tune_one(FAST_AXIS, P.ax[a].len, a, O * I, &v_axis[a], [&]() { return launch_axis(a, -1, nload, st); }))) return rc;
     }
     if (f_spec && (rc = tune_one(FAST_SPEC, P.ax[P.D - 1].len, P.D - 1, P.S / P.ax[P.D - 1].len, &v_spec, [&]() { return launch_spec(nload, st); }))) return rc;
+    if (cg && v_real == 4) v_real = 0;   // a cached or pinned choice from a Basic-Scheme solver
     apply_variants();  // tile counts must follow the chosen variants (also on cache hits)
     tuned = true;
     return AHOM_OK;
@@ -502,10 +590,11 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
     s->npack = s->dim == 3 ? 3 : 2;
     s->nt = s->dim == 3 ? 3 : 2;
     s->stream = (hipStream_t)cfg->stream;
+    s->cg = cfg->scheme == AHOM_SCHEME_CG;
     const Plan& P = p->plan;
     const size_t es = s->es();
     auto bad = [&](int code) { delete s; return code; };
-    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)s->ncomp * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
+    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)(s->ncomp + 1) * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
     if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)2 * AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
     for (int a = 1; a <= P.D - 2; ++a) {
         int64_t O = 1, I = 1;
@@ -588,6 +677,93 @@ int ensure_ref64(ahom_solver* s, int nload) {
     int rc = r->ensure_capacity(nload);
     if (rc) return rc;
     return r->autotune(nload);
+}
+
+// Conjugate gradients for n_load strains (cfg.scheme == AHOM_SCHEME_CG).
+int solve_cg(ahom_solver* s, int n_load, const double* eps_bar, void* strain_out, int* iters, double* resid,
+             double* mean_stress, int mem_flags) {
+    int rc = s->ensure_capacity(n_load);
+    if (rc) return rc;
+    s->spec_toff = nullptr;
+    s->spec_dout = s->spec_dneg = nullptr;
+    s->red_sig_base = nullptr;
+    s->cur_tol = s->cfg.tol;
+    if ((rc = s->autotune(n_load))) return rc;
+    const Plan& P = s->pat->plan;
+    const int nc = s->ncomp;
+    const int* comp = s->dim == 3 ? kComp3 : kComp2;
+    hipStream_t st = s->stream;
+    std::vector<double> eb((size_t)n_load * nc);
+    for (int l = 0; l < n_load; ++l)
+        for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
+    HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+    if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    FillArgs f{};
+    f.eps_bar = s->d_epsbar;
+    f.S = P.S;
+    f.row = P.S / P.ax[0].slen;
+    f.nfield = nc;
+    f.buf = s->d_buf0;                 // the start's operator input eps_bar
+    if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    f.buf = s->d_x;                    // x(0) = 0: the iterate eps_bar
+    if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    HIPCHK(hipEventRecord(s->ev0, st));
+    if ((rc = cg_sweep(s, n_load, 1))) return rc;
+    int enq = 1;
+    const int limit = s->cfg.max_iter + 1;
+    bool all_done = false;
+    while (!all_done) {
+        HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        all_done = true;
+        for (int l = 0; l < n_load; ++l) all_done = all_done && s->h_st[l].done;
+        if (all_done) break;
+        if (enq > limit + 2 * s->cfg.check_period) return fail(AHOM_E_DEVICE, "loop control did not terminate");
+        const int k = std::min(s->cfg.check_period, std::max(1, limit - enq + 1));
+        for (int i = 0; i < k; ++i) {
+            if ((rc = cg_sweep(s, n_load, 0))) return rc;
+            ++enq;
+        }
+    }
+    float ms = 0.f;
+    HIPCHK(hipEventRecord(s->ev1, st));
+    HIPCHK(hipEventSynchronize(s->ev1));
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->last_ms = ms;
+    s->last_enqueued = enq;
+    s->last_nload = n_load;
+    s->last_restarts = 0;
+    if (strain_out) {
+        if (mem_flags != AHOM_MEM_DEVICE && (rc = s->ensure_real_staging())) return rc;
+        RealArgs ra = s->real_args(REAL_TO_REAL);
+        ra.buf0 = ra.buf1 = s->d_x;
+        ra.real_io = mem_flags == AHOM_MEM_DEVICE ? static_cast<double*>(strain_out) : s->d_real;
+        if (ahom_launch_real(s->prec, s->dim, REAL_TO_REAL, ra, s->g_real.nwg, n_load, s->g_real.lds, st))
+            return fail(AHOM_E_DEVICE, "launch to_real");
+        if (mem_flags != AHOM_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(strain_out, s->d_real, (size_t)n_load * nc * P.m * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    int ret = AHOM_OK;
+    for (int l = 0; l < n_load; ++l) {
+        const LoadState& ls = s->h_st[l];
+        if (iters) iters[l] = ls.iter;
+        if (resid) resid[l] = ls.resid;
+        if (mean_stress) {
+            double* ms9 = mean_stress + (size_t)l * 9;
+            for (int q = 0; q < 9; ++q) ms9[q] = 0.0;
+            for (int c = 0; c < nc; ++c) {
+                const int pos = comp[c];
+                ms9[pos] = ls.mean[c];
+                ms9[(pos % 3) * 3 + pos / 3] = ls.mean[c];
+            }
+        }
+        if (ls.status == 2) ret = AHOM_E_DIVERGED;
+        else if (ls.status == 1 && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
+    }
+    if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
+    return ret;
 }
 
 }  // namespace
@@ -734,6 +910,9 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     if (cfg->stop_rule != AHOM_STOP_RESIDUAL && cfg->stop_rule != AHOM_STOP_CAUCHY) return fail(AHOM_E_ARG, "unknown stop rule");
     if (cfg->stop_rule == AHOM_STOP_CAUCHY && cfg->precision == AHOM_FP32_MIXED && !(cfg->refine < 0.0))
         return fail(AHOM_E_ARG, "the Cauchy stop rule in FP32 needs refine < 0 (no restarts)");
+    if (cfg->scheme != AHOM_SCHEME_BASIC && cfg->scheme != AHOM_SCHEME_CG) return fail(AHOM_E_ARG, "unknown scheme");
+    if (cfg->scheme == AHOM_SCHEME_CG && (cfg->precision != AHOM_FP64 || cfg->stop_rule != AHOM_STOP_RESIDUAL))
+        return fail(AHOM_E_ARG, "the conjugate-gradient scheme runs in AHOM_FP64 with the residual stop rule");
     return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
 }
 
@@ -824,6 +1003,10 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
     if (init && s->cfg.stop_rule == AHOM_STOP_CAUCHY)
         return fail(AHOM_E_ARG, "the Cauchy stop rule measures against sqrt(m) |eps_bar|, not a guessed start: no init");
+    if (s->cg) {
+        if (init) return fail(AHOM_E_ARG, "the conjugate-gradient scheme starts from eps_bar (no init)");
+        return solve_cg(s, n_load, eps_bar, strain_out, iters, resid, mean_stress, mem_flags);
+    }
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;

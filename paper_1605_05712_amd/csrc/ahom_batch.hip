@@ -503,6 +503,7 @@ static int batch_create(int d, int n_members, const int64_t* M, const double* L,
     if (cfg->nyquist != AHOM_NYQUIST_HERMITIAN) return bfail(AHOM_E_ARG, "unsupported Nyquist rule");
     if (!(cfg->refine < 1.0)) return bfail(AHOM_E_ARG, "refine must be < 1");
     if (cfg->stop_rule != AHOM_STOP_RESIDUAL) return bfail(AHOM_E_ARG, "batches stop on the residual only");
+    if (cfg->scheme != AHOM_SCHEME_BASIC) return bfail(AHOM_E_ARG, "batches run the Basic Scheme only");
     ahom_batch* b = new (std::nothrow) ahom_batch();
     if (!b) return bfail(AHOM_E_NOMEM, "host allocation failed");
     b->d = d;

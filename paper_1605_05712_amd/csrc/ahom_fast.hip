@@ -453,8 +453,8 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
     const int wave = tid >> 6;
     C* Z = smem<C>();
     C* twl = Z + G::TILE;
-    double* red = reinterpret_cast<double*>(twl + L);   // [NCOMP][NW] per-wave stress sums
-    T* mat = reinterpret_cast<T*>(red + NCOMP * NW);     // [n_phase][2] Lame pairs
+    double* red = reinterpret_cast<double*>(twl + L);   // [NCOMP + 1][NW] per-wave stress (and energy) sums
+    T* mat = reinterpret_cast<T*>(red + (NCOMP + 1) * NW);   // [n_phase][2] Lame pairs
     const bool table = a.lame_pts_t == nullptr;
     const T lam0 = (T)a.lam0, mu0 = (T)a.mu0;
 
@@ -556,9 +556,12 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         });
     };
 
-    // local law on the tile in LDS; per-wave stress sums into red[]
+    // local law on the tile in LDS; per-wave stress sums into red[] (and,
+    // with a.en_part set, the sums of eps : tau)
+    const bool energy = a.en_part != nullptr;
     auto law = [&](const Tile& x, const uint8_t (&ph)[EPL]) __attribute__((always_inline)) {
         double sig[NCOMP];
+        double en = 0.0;
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c) sig[c] = 0.0;
         auto point = [&](int j, int n, T lam, T mu) __attribute__((always_inline)) {
@@ -577,6 +580,10 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
                 const bool diag = DIM == 3 ? c < 3 : c < 2;
                 sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
                 tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+            }
+            if (energy) {
+#pragma unroll
+                for (int c = 0; c < NCOMP; ++c) en += ((DIM == 3 ? c < 3 : c < 2) ? 1.0 : 2.0) * (double)eps[c] * (double)tau[c];
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
@@ -607,18 +614,27 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
         // fixed-order sums inside the wave, one entry per wave
 #pragma unroll
         for (int c = 0; c < NCOMP; ++c) sig[c] = wave_sum_lane63(sig[c]);
-        if ((tid & 63) == 63)
+        if (energy) en = wave_sum_lane63(en);
+        if ((tid & 63) == 63) {
 #pragma unroll
             for (int c = 0; c < NCOMP; ++c) red[c * NW + wave] = sig[c];
+            red[NCOMP * NW + wave] = en;
+        }
     };
     // tile's stress partial from the per-wave sums (thread 0, waves in order)
     auto write_sig = [&](const Tile& x) __attribute__((always_inline)) {
-        if (tid == 0)
+        if (tid == 0) {
             for (int c = 0; c < NCOMP; ++c) {
                 double acc = 0.0;
                 for (int w = 0; w < NW; ++w) acc += red[c * NW + w];
                 a.sig_part[((int64_t)x.load * nct + x.ct) * NCOMP + c] = acc;
             }
+            if (energy) {
+                double acc = 0.0;
+                for (int w = 0; w < NW; ++w) acc += red[NCOMP * NW + w];
+                a.en_part[(int64_t)x.load * nct + x.ct] = acc;
+            }
+        }
     };
 
     // half spectra of the transformed tile into out[]
@@ -1354,7 +1370,18 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 tt[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
             }
             const int64_t spos = c0 * L + e;
-            if (chk) {
+            if (a.cg_alpha) {
+                // conjugate gradients: traction of the updated iterate t + alpha t_p
+                const T cg_a = (T)a.cg_alpha[load];
+                double r2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const C nt = C{oldv[q][c].x + cg_a * tt[c].x, oldv[q][c].y + cg_a * tt[c].y};
+                    r2 += (double)nt.x * (double)nt.x + (double)nt.y * (double)nt.y;
+                    stg(tb + (int64_t)c * P.S + spos, nt);
+                }
+                res += (double)kb[j * 4 + 3] * r2;
+            } else if (chk) {
                 double r2 = 0.0, xdx = 0.0, xdy = 0.0;
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
@@ -1372,7 +1399,7 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                 // Cauchy term |eps_hat(n+1) - eps_hat(n)|^2 up to 1 / (2 mu0^2)
                 cau += (double)kb[j * 4 + 3] * (r2 + cau_c1 * (xdx * xdx + xdy * xdy));
             }
-            if (wrt) {
+            if (wrt && !a.cg_alpha) {
 #pragma unroll
                 for (int c = 0; c < NT; ++c) stg(tb + (int64_t)c * P.S + spos, tt[c]);
             }
@@ -1468,7 +1495,7 @@ FastGeom geom_of(int kind) {
     // tile + twiddles + per-column integers (spec: kappa + weight) or
     // per-wave stress sums (real; the phase table is added at launch)
     size_t extra = kind == FAST_SPEC ? (size_t)G::NC * (32 + 24) + (size_t)(G::THREADS / 64) * 16
-                                     : (kind == FAST_REAL ? (size_t)6 * (G::THREADS / 64) * 8 : 0);
+                                     : (kind == FAST_REAL ? (size_t)7 * (G::THREADS / 64) * 8 : 0);
     size_t lds = (size_t)G::TILE * G::es + (size_t)L * G::es + extra;
     // block reduction of the other passes reuses the tile: one double per thread
     const size_t red = (size_t)G::THREADS * 8;
@@ -1648,7 +1675,7 @@ AHOM_INST_SPEC(float, 0) AHOM_INST_SPEC(float, 1) AHOM_INST_SPEC(float, 2) AHOM_
 template <typename T>
 int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_rr_T<T>(dim, L, &g)) return -1;
+    if (a.en_part || !geom_rr_T<T>(dim, L, &g)) return -1;   // no energy sums in this variant
 #define AHOM_FRR(LL)                                                                 \
     case LL:                                                                         \
         return dim == 3 ? go(kf_real_rr<T, 3, LL>, g, total, ncu, s, a) : go(kf_real_rr<T, 2, LL>, g, total, ncu, s, a);

@@ -41,6 +41,10 @@ struct RealArgs {
     int nload;                // fast path: load cases covered by the persistent grid
     int accumulate;           // TO_REAL: add to real_io instead of overwriting it
     int n_phase;              // entries of lame_tab (fast path stages them in LDS)
+    // [load][tile] sums of eps : tau over the tile's points (nullable); with
+    // lam0 = mu0 = 0 the law is tau = C : eps and these are eps : C : eps
+    // (the conjugate-gradient scheme's <p, A p>)
+    double* en_part;
 };
 
 struct AxisArgs {
@@ -80,6 +84,11 @@ struct SpecArgs {
     const void* toff;
     void* dout;
     void* dneg;
+    // conjugate-gradient traction recurrence (nullable): with alpha =
+    // cg_alpha[load] the pass writes t <- t + alpha tau_hat xi and sums |t|^2
+    // of the new t (the equilibrium residual of the updated iterate) instead
+    // of t <- tau_hat xi with |t(n+1) - t(n)|^2
+    const double* cg_alpha;
 };
 
 // traction traffic of iteration n: read (and evaluate r(n)) / write t(n + 1)
@@ -147,6 +156,49 @@ struct GatherArgs {
 int ahom_launch_refine_gather(const GatherArgs& a, int nload, hipStream_t s);
 // dst[c * L0 + n] = src[n * I + c] for elements of `bytes` bytes (1 or 16)
 int ahom_launch_transpose(const void* src, void* dst, int64_t L0, int64_t I, int bytes, hipStream_t s);
+
+// ---- conjugate gradients on the same passes (ahom_cg.hip).  Per load: the
+// direction p in state buffer buf[iter & 1], the operator output -Gamma0 C p
+// in buf[(iter + 1) & 1] (the passes run with the law C : eps and cg_alpha
+// set), the iterate eps_bar + x in xbuf and the residual field r in rbuf;
+// all in the state layout (half spectrum along axis 0).
+struct CgScalars {
+    double rr;        // <r, r>_C0 of the current residual field
+    double alpha;     // step length of the current update (1 for the start)
+    double beta;      // direction update after the current step
+    double pcp;       // <p, C p> of the current direction
+};
+
+struct CgArgs {
+    LoadState* st;
+    CgScalars* cg;
+    double* alpha;            // [load] alpha, read by the spectral pass
+    void* buf0;
+    void* buf1;
+    void* xbuf;
+    void* rbuf;
+    const double* sig_part;   // [load][n_real][ncomp] sums of C p
+    const double* en_part;    // [load][n_real] sums of p : C p
+    const double* res_part;   // [load][n_spec] |t|^2 of the updated iterate's traction
+    double* rr_part;          // [load][nblk] sums of r : C0 : r (update kernel)
+    double* hist;             // [load][hist_cap] residual history
+    int n_real, n_spec, nblk, hist_cap;
+    int64_t S;                // stored complex elements per field
+    int64_t I;                // S / stored length of axis 0
+    int64_t m;
+    int L0;                   // transform length of axis 0 (Hermitian weights)
+    double lam0, mu0;
+    double tol;
+    int max_iter;
+    int start;                // 1: the start (r(0), p_0 = r_0), 0: an update
+};
+
+int ahom_launch_cg_alpha(int dim, const CgArgs& a, int nload, hipStream_t s);
+int ahom_launch_cg_update(int prec, int dim, const CgArgs& a, int nload, hipStream_t s);
+int ahom_launch_cg_reduce(int dim, const CgArgs& a, int nload, hipStream_t s);
+int ahom_launch_cg_direction(int prec, int dim, const CgArgs& a, int nload, hipStream_t s);
+// workgroups per load of the update kernel (size of rr_part)
+int ahom_cg_blocks(int64_t S);
 
 // ---- batched solves: one persistent launch over many (pattern, load) items.
 // A workgroup takes an item from the queue and runs Algorithm 1 for it to the

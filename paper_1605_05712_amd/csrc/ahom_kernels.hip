@@ -254,8 +254,9 @@ template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
 // axis 0: real-space turnaround
 // =============================================================================
 // One tile (a.NC columns) of the axis-0 pass for load case `load`; the
-// stress sums of REAL_TURN are added to sig (per thread).  All threads of
-// the workgroup take part (LDS barriers inside).
+// stress sums of REAL_TURN are added to sig[0..ncomp) (per thread), and with
+// a.en_part set the sum of eps : tau to sig[ncomp].  All threads of the
+// workgroup take part (LDS barriers inside).
 template <typename T, int DIM, int MODE>
 __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int64_t tile, double* sig) {
     using C = typename CT<T>::t;
@@ -377,6 +378,12 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
                 sig[c] += (double)s;
                 tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
             }
+            if (a.en_part) {
+                double en = 0.0;
+#pragma unroll
+                for (int c = 0; c < NC_; ++c) en += ((DIM == 3 ? c < 3 : c < 2) ? 1.0 : 2.0) * (double)eps[c] * (double)tau[c];
+                sig[NC_] += en;
+            }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
                 Z[p * a.NC * CS + j * CS + n] = C{tau[2 * p], 2 * p + 1 < NC_ ? tau[2 * p + 1] : (T)0};
@@ -453,16 +460,18 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
     constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
     const int load = blockIdx.y;
     if (MODE == REAL_TURN && a.st[load].done) return;
-    double sig[NC_];
+    double sig[NC_ + 1];
 #pragma unroll
-    for (int c = 0; c < NC_; ++c) sig[c] = 0.0;
+    for (int c = 0; c <= NC_; ++c) sig[c] = 0.0;
     real_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, sig);
     if (MODE == REAL_TURN) {
         __syncthreads();
         double* red = reinterpret_cast<double*>(lds_base<C>() + (NP + 1) * a.NC * a.CS);
-        block_sum<NC_>(sig, red);
-        if (threadIdx.x == 0)
+        block_sum<NC_ + 1>(sig, red);
+        if (threadIdx.x == 0) {
             for (int c = 0; c < NC_; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NC_ + c] = sig[c];
+            if (a.en_part) a.en_part[(int64_t)load * gridDim.x + blockIdx.x] = sig[NC_];
+        }
     }
 }
 
@@ -691,13 +700,22 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
             t[0] = C{T00.x * xi[0] + T01.x * xi[1], T00.y * xi[0] + T01.y * xi[1]};
             t[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
         }
-        // residual: sigma_hat(n) xi = t(n+1) - t(n) on active frequencies
+        // residual: sigma_hat(n) xi = t(n+1) - t(n) on active frequencies;
+        // conjugate gradients: the traction of the updated iterate, t + alpha t_p
         const double wgt = (kpos[0] == 0 || 2 * kpos[0] == L0) ? 1.0 : 2.0;
         const bool chk = ahom_check_iter(st.iter, a.resid_period, a.max_iter);
         const bool wrt = ahom_write_traction(st.iter, a.resid_period, a.max_iter);
+        const T cg_a = a.cg_alpha ? (T)a.cg_alpha[load] : (T)0;
         double r2 = 0.0, xdx = 0.0, xdy = 0.0;
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
+            if (a.cg_alpha) {
+                const C old = tb[(int64_t)c * P.S + spos];
+                const C nt = C{old.x + cg_a * t[c].x, old.y + cg_a * t[c].y};
+                r2 += (double)nt.x * (double)nt.x + (double)nt.y * (double)nt.y;
+                tb[(int64_t)c * P.S + spos] = nt;
+                continue;
+            }
             if (chk) {
                 const C old = tb[(int64_t)c * P.S + spos];
                 const double dx = (double)t[c].x - (double)old.x, dy = (double)t[c].y - (double)old.y;
