@@ -78,34 +78,64 @@ def traffic_record(kernel):
     return k["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(n=128, n_iter=1):
-    """Oracle (CPU FP64) on a bounded sample of the same workload: one load, n_iter updates."""
+def cpu_baseline(n=64, n_iter=10):
+    """The oracle (CPU FP64, test infrastructure) timed on the host cores, on a
+    bounded sample: the Hashin structure of the workload sampled on
+    diag(n,n,n), one load (Mandel e_11), n_iter updates each timed on its own
+    (stress, residual and Lippmann-Schwinger map; median reported), with the
+    library FFT threaded over every host core; and the time to the 1e-8
+    residual of the 2-D laminate on diag(64,64) under e_11."""
     code = f"""
-import json, os, sys, time
+import json, os, platform, sys, time
 import numpy as np
 sys.path.insert(0, {ROOT!r})
 import synth
 from oracle import elasticity as E
-from oracle.dft import make_transform
+from oracle.dft import make_transform, fft_workers
 g = json.load(open(os.path.join({ROOT!r}, 'tests', 'golden', 'hashin_c2.json')))
 M = [[{n},0,0],[0,{n},0],[0,0,{n}]]
 T = make_transform(M)
 geom = dict(c=np.array(g['c']), rho_c=g['rho_c'], rho_e=g['rho_e'], R=np.array(g['R']))
 ph = synth.hashin_phase(T.points, T.m, geom)
 lame = np.array([g['lame_core'], g['lame_coating'], g['lame_matrix']])
+stamps = [time.perf_counter()]
+E.basic_scheme(M, ph, lame, E.default_reference(lame), E.unit_loads(3)[0], transform=T, fixed_iters={n_iter},
+               on_iteration=lambda k: stamps.append(time.perf_counter()))
+per = np.diff(stamps)
+M2 = [[64,0],[0,64]]
+T2 = make_transform(M2)
+lam2 = np.array(synth.LAMINATE_LAME)
 t0 = time.perf_counter()
-E.basic_scheme(M, ph, lame, E.default_reference(lame), E.unit_loads(3)[0], transform=T, fixed_iters={n_iter})
-dt = time.perf_counter() - t0
-print(json.dumps(dict(seconds=dt, m=T.m)))
+r2 = E.basic_scheme(M2, synth.laminate_phase(T2.points, T2.m), lam2, E.default_reference(lam2), np.diag([1.0, 0.0]),
+                    tol=1e-8, max_iter=5000, transform=T2)
+t_lam = time.perf_counter() - t0
+model = ''
+try:
+    for line in open('/proc/cpuinfo'):
+        if line.startswith('model name'):
+            model = line.split(':', 1)[1].strip()
+            break
+except OSError:
+    pass
+print(json.dumps(dict(median=float(np.median(per)), min=float(per.min()), m=T.m, workers=fft_workers(),
+                      nproc=os.cpu_count(), model=model or platform.processor(), lam_s=t_lam, lam_iters=r2.iters)))
 """
-    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    try:
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=900)
+    except subprocess.TimeoutExpired:
+        return None
     if out.returncode != 0:
+        print(out.stderr[-2000:], file=sys.stderr)
         return None
     rec = json.loads(out.stdout.strip().splitlines()[-1])
-    return dict(value=rec["m"] * n_iter / rec["seconds"], unit="lattice-point updates/s", cores=1, kind="oracle",
-                sample=f"1 load (Mandel e11) x {n_iter} update(s) on diag({n},{n},{n}) in FP64, single thread; "
-                       f"{rec['seconds']:.1f} s incl. the residual evaluations")
+    return dict(value=round(rec["m"] / rec["median"], 1), unit="lattice-point updates/s", cores=rec["workers"],
+                kind="oracle", nproc=rec["nproc"], cpu_model=rec["model"],
+                median_s_per_iteration=round(rec["median"], 3), min_s_per_iteration=round(rec["min"], 3),
+                time_to_1e8_laminate_64x64_s=round(rec["lam_s"], 2), laminate_iters=int(rec["lam_iters"]),
+                sample=f"1 load (Mandel e11) on the Hashin structure sampled on diag({n},{n},{n}) in FP64: median of "
+                       f"{n_iter} single updates (stress, residual, Lippmann-Schwinger map); library FFT on "
+                       f"{rec['workers']} threads, the rest one thread.  Plus the full solve of the 2-D laminate "
+                       f"diag(64,64) to r <= 1e-8")
 
 
 def batch_workload(ahom):
@@ -300,8 +330,9 @@ def precision_workload(ahom, n=256):
     lame = np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
     out = {}
     Cs = {}
-    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
-        S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, check_period=16, resid_period=4)
+    for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
+                               ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+        S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, check_period=16, resid_period=4, scheme=scheme)
         S.set_material(lame, ph)
         C, it = S.effective_stiffness()
         dev_ms, _ = S.last_timing()
@@ -312,9 +343,13 @@ def precision_workload(ahom, n=256):
         print(f"[bench] precision {n}^3 {name}: {dev_ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
         del S
     err = np.abs(Cs["fp32"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
+    err_cg = np.abs(Cs["cg_fp64"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
     return dict(workload=f"spheres diag({n},{n},{n}), vf 0.3, contrast 100, 6 loads, tol 1e-6",
-                fp64=out["fp64"], fp32=out["fp32"], speedup_fp32_vs_fp64=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
-                ceff_max_entry_err_fp32_vs_fp64=float(err.max()), volume_fraction=float(ph.mean()))
+                fp64=out["fp64"], fp32=out["fp32"], cg_fp64=out["cg_fp64"],
+                speedup_fp32_vs_fp64=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
+                speedup_cg_vs_fp64=round(out["fp64"]["ms"] / out["cg_fp64"]["ms"], 3),
+                ceff_max_entry_err_fp32_vs_fp64_over_max_abs=float(err.max()),
+                ceff_max_entry_diff_cg_vs_fp64_over_max_abs=float(err_cg.max()), volume_fraction=float(ph.mean()))
 
 
 def learned_workload(ahom, ntrain, steps, n=64, ntest=4):
@@ -418,8 +453,9 @@ def main():
     loads = mandel_loads()
     nload = loads.shape[0]
 
-    def make(prec, tol, max_iter, check, resid_period=1):
-        S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=check, resid_period=resid_period)
+    def make(prec, tol, max_iter, check, resid_period=1, scheme=ahom.SCHEME_BASIC):
+        S = ahom.Solver(P, precision=prec, tol=tol, max_iter=max_iter, check_period=check, resid_period=resid_period,
+                        scheme=scheme)
         S.set_material(lame, ph)
         return S
 
@@ -454,19 +490,25 @@ def main():
                     all_passes={f"{i}:{n}": dict(ms=round(float(t), 4), GBs=round(float(b / (t * 1e-3) / 1e9), 1))
                                 for i, (n, t, b) in enumerate(zip(names, ms, by))})
 
-    # ---- time to the 1e-6 residual: plain FP64 vs FP32 mixed (all 6 loads)
+    # ---- time to the 1e-6 residual: plain FP64 vs FP32 mixed vs conjugate
+    # gradients (all 6 loads)
     ttt = None
     if not args.no_ttt:
         ttt = {}
-        for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
-            S = make(prec, 1e-6, 3000, 16, resid_period=args.ttt_resid_period)
+        Cs = {}
+        for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
+                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+            S = make(prec, 1e-6, 3000, 16, resid_period=args.ttt_resid_period, scheme=scheme)
             C, it = S.effective_stiffness()
             dev_ms, enq = S.last_timing()
+            Cs[name] = C
             ttt[name] = dict(ms=round(dev_ms, 2), iters=[int(v) for v in it], e_eff=round(e_eff_from_ceff(C, g), 6),
                              ceff_asym=float(np.max(np.abs(C - C.T))))
             print(f"[bench] time-to-1e-6 {name}: {dev_ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
             del S
         ttt["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["fp32"]["ms"], 3)
+        ttt["speedup_cg_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["cg_fp64"]["ms"], 3)
+        ttt["ceff_max_entry_diff_cg_vs_fp64"] = float(np.abs(Cs["cg_fp64"] - Cs["fp64"]).max() / np.abs(Cs["fp64"]).max())
 
     cpu = None
     batch = None
@@ -490,7 +532,7 @@ def main():
         learned = learned_workload(ahom, args.learned_train, args.learned_steps)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(args.size, n_iter=3)
+        cpu = cpu_baseline()
 
     line = dict(
         metric=METRIC, value=round(main_res["value"], 1), unit="lattice-point updates/s", n_gpus=1,

@@ -200,7 +200,7 @@ def lippmann_schwinger_map(T, C0, K, upd, zero, eps_bar, eps, sigma, rule="hermi
 
 
 def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=None,
-                 transform=None, rule="hermitian", fixed_iters=None, cell=None, stop="residual"):
+                 transform=None, rule="hermitian", fixed_iters=None, cell=None, stop="residual", on_iteration=None):
     """The Basic Scheme (Algorithm 1, Sec. 3.2) on P(M), or on P_L(M) with cell = L.
 
     Picard iteration of ``lippmann_schwinger_map`` from eps(0) = eps_bar
@@ -212,6 +212,7 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
     fixed_iters: run exactly this many updates, ignoring tol.
     stop="cauchy": the Sec. 5.2 criterion instead, |eps(n+1) - eps(n)| / |eps(0)|
     <= tol; the result is eps(n) for the first such n (n updates performed).
+    on_iteration: optional callable(n), called after each update (timing only).
     """
     T = transform or make_transform(M)
     d = len(as_int_matrix(M))
@@ -253,6 +254,8 @@ def basic_scheme(M, phase, lame, lame0, eps_bar, tol=1e-8, max_iter=1000, init=N
             return SchemeResult(eps, n, r, 0, mean, hist, cauchy)
         eps = new
         n += 1
+        if on_iteration is not None:
+            on_iteration(n)
 
 
 def unit_loads(d):
