@@ -167,6 +167,20 @@ int ahom_pattern_freqs(const ahom_pattern* p, int64_t* h);
 int ahom_dft(const ahom_pattern* p, int sign, int prec, const void* in, void* out, int mem_flags, void* stream);
 
 /*
+ * ahom_dft for callers that cannot allocate device memory (code that must not
+ * call hipMalloc, e.g. tight serving loops or harnesses that forbid it): the
+ * same transform through the same kernels, with no hipMalloc, hipFree or
+ * other allocating call.  in and out are device pointers (m complex values as
+ * for ahom_dft, not aliasing).  The plan, the twiddle tables and the working
+ * array live in one static device array of the library (about 33 MiB, held
+ * on each GPU the library runs on until the process ends): m must not exceed
+ * 2^21 points (AHOM_E_ARG otherwise).  Every call on a GPU shares that array,
+ * so calls that overlap on one GPU (two streams, two threads) race; the call
+ * returns after the transform has completed on `stream`.
+ */
+int ahom_dft_noalloc(const ahom_pattern* p, int sign, int prec, const void* in, void* out, void* stream);
+
+/*
  * Solver for Algorithm 1 (Sec. 3.2) on the pattern p (which must outlive
  * the solver).  Allocates device buffers.  Errors: AHOM_E_ARG, AHOM_E_DEVICE,
  * AHOM_E_NOMEM.

@@ -45,7 +45,7 @@ SCHEME_CG = 1
 EXPORTS = [
     "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_create_transformed", "ahom_pattern_destroy",
     "ahom_pattern_info",
-    "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_solver_create", "ahom_solver_destroy",
+    "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_dft_noalloc", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
     "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_create_transformed",
@@ -80,6 +80,7 @@ _lib.ahom_pattern_info.argtypes = [_P, _i64p, _ip, _i64p, _i64p, _i64p]
 _lib.ahom_pattern_points.argtypes = [_P, _i64p]
 _lib.ahom_pattern_freqs.argtypes = [_P, _i64p]
 _lib.ahom_dft.argtypes = [_P, ct.c_int, ct.c_int, _P, _P, ct.c_int, _P]
+_lib.ahom_dft_noalloc.argtypes = [_P, ct.c_int, ct.c_int, _P, _P, _P]
 _lib.ahom_solver_create.argtypes = [_P, ct.POINTER(Config), ct.POINTER(_P)]
 _lib.ahom_solver_destroy.argtypes = [_P]
 _lib.ahom_solver_destroy.restype = None
@@ -264,6 +265,11 @@ class Pattern:
             raise ValueError("need m values")
         out = np.empty_like(a)
         _check(_lib.ahom_dft(self._h, sign, precision, a.ctypes.data, out.ctypes.data, MEM_HOST, None))
+        return out
+
+    def dft_noalloc(self, a, out, sign=-1, precision=FP64, stream=None):
+        """The pattern DFT through the library's static scratch (no device allocation); a, out: DeviceArray."""
+        _check(_lib.ahom_dft_noalloc(self._h, sign, precision, a.data_ptr(), out.data_ptr(), stream))
         return out
 
     def __del__(self):

@@ -47,6 +47,47 @@ const int kComp2[3] = {0, 4, 1};
 
 void ahom_set_error(const std::string& msg) { g_err = msg; }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free pattern DFT (ahom_dft_noalloc): the plan,
+// the twiddle tables (FP64 and their FP32 rounding) and one working array of
+// up to kScratchMaxPoints complex doubles.  Each GPU holds its own copy from
+// load until the process ends; every call on a GPU shares it.  Host code
+// never passes the array's name to a kernel: it takes the device address
+// from hipGetSymbolAddress once per device (scratch_base below).
+constexpr size_t kScratchPlanBytes = 4096;
+constexpr size_t kScratchTableBytes = size_t(1) << 20;       // plan + both twiddle tables
+constexpr int64_t kScratchMaxPoints = int64_t(1) << 21;
+constexpr size_t kScratchBytes = kScratchTableBytes + (size_t)kScratchMaxPoints * 16;
+static_assert(sizeof(Plan) <= kScratchPlanBytes, "plan does not fit its scratch slot");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kScratchMaxDevices = 64;
+void* g_scratch_ptr[kScratchMaxDevices] = {};
+
+// device address of `scratch` on the current device (resolved once per device)
+int scratch_base(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchMaxDevices) return fail(AHOM_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(AHOM_E_DEVICE, "no device address for the DFT scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AHOM_OK;
+}
+
+__global__ void k_twiddles_to_f32(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = float2{(float)in[i].x, (float)in[i].y};
+}
+}  // namespace
+
 struct DeviceTables {
     int device = -1;
     Plan* plan = nullptr;
@@ -897,6 +938,77 @@ int ahom_dft(const ahom_pattern* pc, int sign, int prec, const void* in, void* o
     if (hipMemcpyAsync(out, sign < 0 ? Y : X, m * es, kout, s) != hipSuccess) { cleanup(); return fail(AHOM_E_DEVICE, "copy out"); }
     if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return fail(AHOM_E_DEVICE, "sync"); }
     cleanup();
+    return AHOM_OK;
+}
+
+int ahom_dft_noalloc(const ahom_pattern* p, int sign, int prec, const void* in, void* out, void* stream) {
+    if (!p || !in || !out || (sign != -1 && sign != 1)) return fail(AHOM_E_ARG, "bad argument");
+    if (prec != AHOM_FP64 && prec != AHOM_FP32_MIXED) return fail(AHOM_E_ARG, "bad precision");
+    const int64_t m = p->sf.m;
+    const size_t es = prec == AHOM_FP64 ? 16 : 8;
+    hipStream_t s = (hipStream_t)stream;
+    if (m > kScratchMaxPoints)
+        return fail(AHOM_E_ARG, "pattern of " + std::to_string(m) + " points exceeds the 2^21-point scratch of the allocation-free DFT");
+    if (m == 1) {
+        HIPCHK(hipMemcpyAsync(out, in, es, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return AHOM_OK;
+    }
+    const size_t ntw = p->tw.size() / 2;
+    const size_t off64 = kScratchPlanBytes;
+    const size_t off32 = (off64 + ntw * 16 + 255) / 256 * 256;
+    if (off32 + ntw * 8 > kScratchTableBytes) return fail(AHOM_E_ARG, "twiddle tables exceed the scratch of the allocation-free DFT");
+    void* base = nullptr;
+    int rc = scratch_base(&base);
+    if (rc) return rc;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    Plan* dplan = reinterpret_cast<Plan*>(b);
+    double2* tw64 = reinterpret_cast<double2*>(b + off64);
+    float2* tw32 = reinterpret_cast<float2*>(b + off32);
+    void* X = b + kScratchTableBytes;
+    const Plan& P = p->plan;
+    HIPCHK(hipMemcpyAsync(dplan, &P, sizeof(Plan), hipMemcpyHostToDevice, s));
+    if (ntw) {
+        HIPCHK(hipMemcpyAsync(tw64, p->tw.data(), ntw * 16, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_twiddles_to_f32, dim3((unsigned)std::min<size_t>((ntw + 255) / 256, 256)), dim3(256), 0, s,
+                           (const double2*)tw64, tw32, (int64_t)ntw);
+        HIPCHK(hipGetLastError());
+    }
+    ReorderArgs ro{};
+    ro.plan = dplan;
+    if (sign < 0) {
+        HIPCHK(hipMemcpyAsync(X, in, m * es, hipMemcpyDeviceToDevice, s));
+    } else {  // canonical frequency order -> kernel positions
+        ro.in = in; ro.out = X; ro.dir = 1; ro.scale = 1.0;
+        if (ahom_launch_reorder(prec, ro, m, s)) return fail(AHOM_E_DEVICE, "reorder");
+    }
+    for (int t = 0; t < P.D; ++t) {
+        const int a = sign < 0 ? t : P.D - 1 - t;
+        int64_t O = 1, I = 1;
+        for (int q = 0; q < a; ++q) O *= P.ax[q].len;
+        for (int q = a + 1; q < P.D; ++q) I *= P.ax[q].len;
+        PassGeom g;
+        if ((rc = choose_geom(P.ax[a].len, O * I, 2, 0, es, prec, &g))) return rc;
+        AxisArgs aa{};
+        aa.plan = dplan;
+        aa.buf0 = X;
+        aa.buf1 = X;
+        aa.tw = prec == AHOM_FP64 ? (const void*)tw64 : (const void*)tw32;
+        aa.tw64 = tw64;
+        aa.st = nullptr;
+        aa.axis = a;
+        aa.slen0_full = 1;
+        aa.NC = g.NC;
+        aa.CS = g.CS;
+        if (ahom_launch_axis(prec, sign, aa, g.nwg, 1, 1, g.lds, s)) return fail(AHOM_E_DEVICE, "axis launch");
+    }
+    if (sign < 0) {
+        ro.in = X; ro.out = out; ro.dir = 0; ro.scale = 1.0 / (double)m;
+        if (ahom_launch_reorder(prec, ro, m, s)) return fail(AHOM_E_DEVICE, "reorder");
+    } else {
+        HIPCHK(hipMemcpyAsync(out, X, m * es, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
     return AHOM_OK;
 }
 
