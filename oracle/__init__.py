@@ -17,6 +17,8 @@ elasticity    stiffness tensors, the Green operator Gamma^0 (Sec. 3.1),
 closed_forms  laminate (Sec. 4.1) and generalized Hashin structure (Sec. 4.2).
 accelerated   conjugate gradients on the same Lippmann-Schwinger system (the
               accelerated schemes named in Sec. 1 and Sec. 6).
+conductivity  the steady-state heat (conductivity) problem named in Sec. 3:
+              scalar Green operator, Basic Scheme and CG, K_eff.
 
 Readings of the paper where it is silent or garbled are listed in the
 module docstrings where they are applied.
