@@ -99,12 +99,23 @@ typedef struct ahom_config {
                            history and the outputs are those of the Basic Scheme (r(n) of
                            eps(n) = eps_bar + x_n; n = updates performed).  Single-pattern
                            solver, AHOM_FP64, AHOM_STOP_RESIDUAL, no init. */
+    int physics;        /* AHOM_ELASTICITY (0, default): quasi-static linear elasticity (Sec. 3.1).
+                           AHOM_CONDUCTIVITY (1): the steady-state heat (conductivity) equation that
+                           Sec. 3 names beside it: unknown the gradient e = grad theta of a
+                           periodic potential plus a prescribed mean (d components), flux
+                           q = k(x) e, equilibrium div q = 0, scalar Green operator
+                           Gamma0(h) tau = h (h . tau) / (k0 |h|^2).  Set the material with
+                           ahom_solver_set_conductivity, solve with ahom_solve_conductivity /
+                           ahom_effective_conductivity.  Single-pattern solver; both schemes,
+                           both precisions (FP32 restarts as for elasticity). */
 } ahom_config;
 
 #define AHOM_STOP_RESIDUAL 0
 #define AHOM_STOP_CAUCHY 1
 #define AHOM_SCHEME_BASIC 0
 #define AHOM_SCHEME_CG 1
+#define AHOM_ELASTICITY 0
+#define AHOM_CONDUCTIVITY 1
 
 /* Library version, (major << 16) | (minor << 8) | patch. */
 int ahom_version(void);
@@ -244,6 +255,39 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
  * return codes as ahom_solve.
  */
 int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters);
+
+/*
+ * Conductivity (ahom_config.physics = AHOM_CONDUCTIVITY; Sec. 3 names the
+ * steady-state heat equation as the other cell problem of the framework).
+ * Piecewise-constant isotropic conductivity: k[q] > 0 of phase q (host
+ * memory); phase[i] in [0, n_phase) the phase of canonical point i (m bytes,
+ * host or device memory as ahom_solver_set_material).  n_phase <= 256.  The
+ * reference k0 defaults to (k_min + k_max) / 2.  Errors: AHOM_E_MATERIAL
+ * (k <= 0 or not finite), AHOM_E_ARG (bad arguments or an elasticity solver).
+ */
+int ahom_solver_set_conductivity(ahom_solver* s, int n_phase, const double* k, const uint8_t* phase, int mem_flags);
+/* Reference conductivity k0 of the Lippmann-Schwinger equation.  AHOM_E_MATERIAL for k0 <= 0. */
+int ahom_solver_set_reference_conductivity(ahom_solver* s, double k0);
+
+/*
+ * The Basic Scheme (or CG, per ahom_config.scheme) for n_load mean gradients
+ * grad_bar (n_load*3 doubles, host; in 2-D the first two entries are used).
+ * field_out: NULL, or n_load*d*m doubles receiving the gradient field e(n_k)
+ * per load, component-major, canonical point order (host, or device memory
+ * with AHOM_MEM_DEVICE).  iters, resid: as ahom_solve, with the residual
+ * r(n) = sqrt(sum_{h active, h != 0} |q_hat_h . xi_h|^2) / |<q>| of the
+ * flux; mean_flux: n_load*3, <q(n_k)> (K_eff grad_bar).  Any output may be
+ * NULL.  Same return codes as ahom_solve.
+ */
+int ahom_solve_conductivity(ahom_solver* s, int n_load, const double* grad_bar, void* field_out, int* iters,
+                            double* resid, double* mean_flux, int mem_flags);
+
+/*
+ * Effective conductivity K_eff (d x d row-major): column j is <q> for the
+ * unit mean gradient e_j (the d loads solved together).  iters: NULL or d
+ * ints.  Same return codes as ahom_solve.
+ */
+int ahom_effective_conductivity(ahom_solver* s, double* Keff, int* iters);
 
 /*
  * Device timing of the last ahom_solve on this solver: total milliseconds

@@ -118,7 +118,8 @@ def basic_scheme_thermal(M, phase, kvals, k0, e_bar, tol=1e-8, max_iter=1000, tr
     pr = prob or ThermalProblem(M, phase, kvals, k0, transform=transform, rule=rule, cell=cell)
     e_bar = np.asarray(e_bar, dtype=np.float64)
     e = np.broadcast_to(e_bar[:, None], (pr.d, pr.T.m)).copy()
-    hist = []
+    norm0 = float(np.linalg.norm(e))
+    hist, cauchy = [], []
     n = 0
     r0 = None
     while True:
@@ -126,12 +127,14 @@ def basic_scheme_thermal(M, phase, kvals, k0, e_bar, tol=1e-8, max_iter=1000, tr
         hist.append(r)
         r0 = r if r0 is None else r0
         if not math.isfinite(r) or (r0 > 0 and r > 1e3 * r0):
-            return SchemeResult(e, n, r, 2, mean, hist)
+            return SchemeResult(e, n, r, 2, mean, hist, cauchy)
         if fixed_iters is None and r <= tol:
-            return SchemeResult(e, n, r, 0, mean, hist)
+            return SchemeResult(e, n, r, 0, mean, hist, cauchy)
         if n == (fixed_iters if fixed_iters is not None else max_iter):
-            return SchemeResult(e, n, r, 0 if fixed_iters is not None else 1, mean, hist)
-        e = pr.ls_map(e, e_bar)
+            return SchemeResult(e, n, r, 0 if fixed_iters is not None else 1, mean, hist, cauchy)
+        new = pr.ls_map(e, e_bar)
+        cauchy.append(float(np.linalg.norm(new - e)) / norm0)     # the Sec. 5.2 measure, reported
+        e = new
         n += 1
 
 

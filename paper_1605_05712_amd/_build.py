@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libahom.so")
 # (source, extra defines): the power-of-two kernels are compiled in parts
 SOURCES = [("ahom_plan.cpp", []), ("ahom_kernels.hip", []), ("ahom_api.hip", []), ("ahom_batch.hip", []), ("ahom_learn.hip", []), ("ahom_cg.hip", []),
            ("ahom_fast.hip", [])] + [
-    ("ahom_fast.hip", [f"-DAHOM_FAST_PART={k}"]) for k in range(8)
+    ("ahom_fast.hip", [f"-DAHOM_FAST_PART={k}"]) for k in range(12)
 ]
 
 HIP_FLAGS = [

@@ -41,12 +41,16 @@ STOP_RESIDUAL = 0
 STOP_CAUCHY = 1
 SCHEME_BASIC = 0
 SCHEME_CG = 1
+ELASTICITY = 0
+CONDUCTIVITY = 1
 
 EXPORTS = [
     "ahom_version", "ahom_last_error", "ahom_pattern_create", "ahom_pattern_create_transformed", "ahom_pattern_destroy",
     "ahom_pattern_info",
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_dft_noalloc", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
+    "ahom_solver_set_conductivity", "ahom_solver_set_reference_conductivity", "ahom_solve_conductivity",
+    "ahom_effective_conductivity",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
     "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_create_transformed",
     "ahom_batch_destroy", "ahom_batch_member_info",
@@ -62,7 +66,7 @@ EXPORTS = [
 class Config(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p),
-                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int), ("scheme", ct.c_int)]
+                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int), ("scheme", ct.c_int), ("physics", ct.c_int)]
 
 
 _P = ct.c_void_p
@@ -89,6 +93,10 @@ _lib.ahom_solver_set_stiffness_field.argtypes = [_P, _P, ct.c_int]
 _lib.ahom_solver_set_reference.argtypes = [_P, ct.c_double, ct.c_double]
 _lib.ahom_solve.argtypes = [_P, ct.c_int, _dp, _P, _P, _ip, _dp, _dp, ct.c_int]
 _lib.ahom_effective_stiffness.argtypes = [_P, _dp, _ip]
+_lib.ahom_solver_set_conductivity.argtypes = [_P, ct.c_int, _dp, _P, ct.c_int]
+_lib.ahom_solver_set_reference_conductivity.argtypes = [_P, ct.c_double]
+_lib.ahom_solve_conductivity.argtypes = [_P, ct.c_int, _dp, _P, _ip, _dp, _dp, ct.c_int]
+_lib.ahom_effective_conductivity.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_restarts.argtypes = [_P, _ip]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
@@ -282,13 +290,15 @@ class Solver:
     """Algorithm 1 on a pattern (device buffers owned by the library)."""
 
     def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1,
-                 refine=0.0, stop_rule=0, scheme=SCHEME_BASIC):
+                 refine=0.0, stop_rule=0, scheme=SCHEME_BASIC, physics=ELASTICITY):
         """stop_rule: STOP_RESIDUAL (r(n) <= tol) or STOP_CAUCHY (the Sec. 5.2 criterion);
-        scheme: SCHEME_BASIC (Algorithm 1) or SCHEME_CG (conjugate gradients)."""
+        scheme: SCHEME_BASIC (Algorithm 1) or SCHEME_CG (conjugate gradients);
+        physics: ELASTICITY or CONDUCTIVITY."""
         self.pattern = pattern
-        self.ncomp = 6 if pattern.d == 3 else 3
+        self.physics = physics
+        self.ncomp = (6 if pattern.d == 3 else 3) if physics == ELASTICITY else pattern.d
         self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period, refine,
-                          stop_rule, scheme)
+                          stop_rule, scheme, physics)
         h = _P()
         _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
         self._h = h
@@ -347,6 +357,38 @@ class Solver:
         rc = _lib.ahom_effective_stiffness(self._h, _ptr(C, ct.c_double), _ptr(iters, ct.c_int))
         _check(rc, allow)
         return C.reshape(k, k), iters
+
+    def set_conductivity(self, k, phase):
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1))
+        if _is_device(phase):
+            _check(_lib.ahom_solver_set_conductivity(self._h, k.size, _ptr(k, ct.c_double), phase.data_ptr(), MEM_DEVICE))
+        else:
+            ph = np.ascontiguousarray(np.asarray(phase, dtype=np.uint8))
+            _check(_lib.ahom_solver_set_conductivity(self._h, k.size, _ptr(k, ct.c_double), ph.ctypes.data, MEM_HOST))
+
+    def set_reference_conductivity(self, k0):
+        _check(_lib.ahom_solver_set_reference_conductivity(self._h, float(k0)))
+
+    def solve_conductivity(self, grad_bar, want_field=False, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        """grad_bar: (n_load, 3).  Returns dict(status, iters, resid, mean_flux (n_load, 3), field (n_load, d, m))."""
+        g = np.ascontiguousarray(np.asarray(grad_bar, dtype=np.float64).reshape(-1, 3))
+        n = g.shape[0]
+        iters = np.zeros(n, np.int32)
+        resid = np.zeros(n, np.float64)
+        mean = np.zeros((n, 3), np.float64)
+        field = np.empty((n, self.pattern.d, self.pattern.m), np.float64) if want_field else None
+        rc = _lib.ahom_solve_conductivity(self._h, n, _ptr(g, ct.c_double), field.ctypes.data if field is not None else None,
+                                          _ptr(iters, ct.c_int), _ptr(resid, ct.c_double), _ptr(mean, ct.c_double), MEM_HOST)
+        _check(rc, allow)
+        return dict(status=rc, iters=iters, resid=resid, mean_flux=mean, field=field)
+
+    def effective_conductivity(self, allow=(AHOM_OK, AHOM_W_NOT_CONVERGED)):
+        d = self.pattern.d
+        K = np.zeros(d * d, np.float64)
+        iters = np.zeros(d, np.int32)
+        rc = _lib.ahom_effective_conductivity(self._h, _ptr(K, ct.c_double), _ptr(iters, ct.c_int))
+        _check(rc, allow)
+        return K.reshape(d, d), iters
 
     def last_timing(self):
         ms = ct.c_double()

@@ -158,6 +158,7 @@ struct ahom_solver {
     ahom_pattern* pat = nullptr;
     ahom_config cfg{};
     int prec = 0, dim = 3, ncomp = 6, npack = 3, nt = 3;
+    int phys = PHYS_ELASTIC;           // elasticity or conductivity (k and k0 in the Lame slots)
     hipStream_t stream = nullptr;
     // material
     bool has_material = false, ref_set = false;
@@ -222,12 +223,12 @@ struct ahom_solver {
     void apply_variants() {
         const Plan& P = pat->plan;
         FastGeom fg;
-        if (f_real && ahom_fast_geom(prec, FAST_REAL, dim, P.ax[0].len, v_real, &fg)) {
+        if (f_real && ahom_fast_geom(prec, FAST_REAL, dim, P.ax[0].len, v_real, &fg, phys)) {
             const int64_t I = P.S / P.ax[0].slen;
             fn_real = (int)((I + fg.NC - 1) / fg.NC);
             fl_real = fg.lds;
         }
-        if (f_spec && ahom_fast_geom(prec, FAST_SPEC, dim, P.ax[P.D - 1].len, v_spec, &fg)) {
+        if (f_spec && ahom_fast_geom(prec, FAST_SPEC, dim, P.ax[P.D - 1].len, v_spec, &fg, phys)) {
             const int64_t nc = P.S / P.ax[P.D - 1].len;
             fn_spec = (int)((nc + fg.NC - 1) / fg.NC);
             fl_spec = fg.lds;
@@ -246,7 +247,7 @@ struct ahom_solver {
         int best = 1;
         for (int v = 0; v < AHOM_FAST_VARIANTS; ++v) {
             FastGeom fg;
-            if (ahom_fast_geom(prec, kind, dim, L, v, &fg)) best = std::max<int>(best, (int)((ncols + fg.NC - 1) / fg.NC));
+            if (ahom_fast_geom(prec, kind, dim, L, v, &fg, phys)) best = std::max<int>(best, (int)((ncols + fg.NC - 1) / fg.NC));
         }
         return best;
     }
@@ -333,6 +334,7 @@ struct ahom_solver {
 
     RealArgs real_args(int mode) const {
         RealArgs a{};
+        a.phys = phys;
         a.plan = pat->dev.plan;
         a.buf0 = d_buf0;
         a.buf1 = d_buf1;
@@ -378,6 +380,7 @@ struct ahom_solver {
 
     SpecArgs spec_args() const {
         SpecArgs a{};
+        a.phys = phys;
         a.plan = pat->dev.plan;
         a.buf0 = d_buf0;
         a.buf1 = d_buf1;
@@ -441,6 +444,7 @@ struct ahom_solver {
         for (int a = P.D - 2; a >= 1; --a)
             if (launch_axis(a, +1, nload, s)) return fail(AHOM_E_DEVICE, "launch axis pass failed");
         ReduceArgs r{};
+        r.phys = phys;
         r.st = d_st;
         r.sig_part = d_sig;
         r.res_part = d_res;
@@ -456,7 +460,9 @@ struct ahom_solver {
         r.cau_part = d_cau;
         r.chist = d_chist;
         r.norm0 = d_norm0;
-        r.cau_scale = (double)P.m / (2.0 * mu0 * mu0);
+        // |eps(n+1) - eps(n)|^2 = m sum |delta eps_hat|^2: 1/(2 mu0^2) of the kernel sums in
+        // elasticity, 1/k0^2 for conductivity (k0 in mu0)
+        r.cau_scale = (double)P.m / ((phys == PHYS_THERMAL ? 1.0 : 2.0) * mu0 * mu0);
         r.stop_cauchy = cfg.stop_rule == AHOM_STOP_CAUCHY;
         if (ahom_launch_reduce(dim, r, nload, s)) return fail(AHOM_E_DEVICE, "launch k_reduce failed");
         return AHOM_OK;
@@ -474,6 +480,7 @@ int cg_sweep(ahom_solver* s, int nload, int start) {
     const Plan& P = s->pat->plan;
     hipStream_t st = s->stream;
     CgArgs c{};
+    c.phys = s->phys;
     c.st = s->d_st;
     c.cg = s->d_cg;
     c.alpha = s->d_alpha;
@@ -523,8 +530,10 @@ namespace {
 struct TuneKey {
     int kind, prec, dim, L, axis, nload;
     int64_t ncols;
+    int phys;
     bool operator<(const TuneKey& o) const {
-        return std::tie(kind, prec, dim, L, axis, nload, ncols) < std::tie(o.kind, o.prec, o.dim, o.L, o.axis, o.nload, o.ncols);
+        return std::tie(kind, prec, dim, L, axis, nload, ncols, phys) <
+               std::tie(o.kind, o.prec, o.dim, o.L, o.axis, o.nload, o.ncols, o.phys);
     }
 };
 std::map<TuneKey, int>& tune_cache() {
@@ -539,7 +548,7 @@ std::mutex& tune_mutex() {
 
 int ahom_solver::autotune(int nload) {
     if (tuned || !use_fast) {
-        if (cg && v_real == 4) { v_real = 0; apply_variants(); }
+        if ((cg || phys != PHYS_ELASTIC) && v_real == 4) { v_real = 0; apply_variants(); }
         return AHOM_OK;
     }
     const Plan& P = pat->plan;
@@ -563,7 +572,7 @@ int ahom_solver::autotune(int nload) {
         return 0;
     };
     auto tune_one = [&](int kind, int L, int axis, int64_t ncols, int* vsel, auto&& launch_v) -> int {
-        TuneKey key{kind, prec, dim, L, axis, nload, ncols};
+        TuneKey key{kind, prec, dim, L, axis, nload, ncols, phys};
         {
             std::lock_guard<std::mutex> g(tune_mutex());
             auto it = tune_cache().find(key);
@@ -574,12 +583,13 @@ int ahom_solver::autotune(int nload) {
         std::vector<FastGeom> seen;
         for (int v = 0; v < AHOM_FAST_VARIANTS; ++v) {
             FastGeom fg;
-            if (!ahom_fast_geom(prec, kind, dim, L, v, &fg)) continue;
+            if (!ahom_fast_geom(prec, kind, dim, L, v, &fg, phys)) continue;
             bool dup = false;
             for (auto& o : seen) dup = dup || (o.NC == fg.NC && o.persistent == fg.persistent);
             if (dup) continue;
             seen.push_back(fg);
-            if (cg && kind == FAST_REAL && v == 4) continue;   // no <p, C p> sums in the register-resident variant
+            // the register-resident variant has neither <p, C p> sums nor the conductivity law
+            if ((cg || phys != PHYS_ELASTIC) && kind == FAST_REAL && v == 4) continue;
             *vsel = v;
             apply_variants();
             float ms = 0.f;
@@ -604,7 +614,7 @@ int ahom_solver::autotune(int nload) {
         if (f_axis[a] && (rc = tune_one(FAST_AXIS, P.ax[a].len, a, O * I, &v_axis[a], [&]() { return launch_axis(a, -1, nload, st); }))) return rc;
     }
     if (f_spec && (rc = tune_one(FAST_SPEC, P.ax[P.D - 1].len, P.D - 1, P.S / P.ax[P.D - 1].len, &v_spec, [&]() { return launch_spec(nload, st); }))) return rc;
-    if (cg && v_real == 4) v_real = 0;   // a cached or pinned choice from a Basic-Scheme solver
+    if ((cg || phys != PHYS_ELASTIC) && v_real == 4) v_real = 0;   // a cached or pinned choice of another solver
     apply_variants();  // tile counts must follow the chosen variants (also on cache hits)
     tuned = true;
     return AHOM_OK;
@@ -627,9 +637,10 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
     if (s->cfg.resid_period < 1) s->cfg.resid_period = 1;
     s->prec = cfg->precision;
     s->dim = p->sf.d;
-    s->ncomp = s->dim == 3 ? 6 : 3;
-    s->npack = s->dim == 3 ? 3 : 2;
-    s->nt = s->dim == 3 ? 3 : 2;
+    s->phys = cfg->physics == AHOM_CONDUCTIVITY ? PHYS_THERMAL : PHYS_ELASTIC;
+    s->ncomp = s->phys == PHYS_THERMAL ? s->dim : (s->dim == 3 ? 6 : 3);
+    s->npack = (s->ncomp + 1) / 2;
+    s->nt = s->phys == PHYS_THERMAL ? 1 : s->dim;
     s->stream = (hipStream_t)cfg->stream;
     s->cg = cfg->scheme == AHOM_SCHEME_CG;
     const Plan& P = p->plan;
@@ -656,15 +667,15 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
     }
     if (s->use_fast) {
         FastGeom fg;
-        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, 0, &fg)) s->f_real = true;
-        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, 0, &fg)) s->f_spec = true;
+        if (ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, 0, &fg, s->phys)) s->f_real = true;
+        if (ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, 0, &fg, s->phys)) s->f_spec = true;
         for (int a = 1; a <= P.D - 2; ++a)
             if (ahom_fast_geom(s->prec, FAST_AXIS, s->dim, P.ax[a].len, 0, &fg)) s->f_axis[a] = true;
         const char* venv = getenv("AHOM_FAST_VARIANT");
         if (venv && venv[0] >= '0' && venv[0] <= '4') {
             const int v = venv[0] - '0';
             FastGeom fg4;
-            const bool rr_ok = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, v, &fg4);
+            const bool rr_ok = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, v, &fg4, s->phys);
             s->v_real = rr_ok ? v : 0;          // variant 4 exists for the real-space pass only
             s->v_spec = v < 4 ? v : 0;
             for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v < 4 ? v : 0;
@@ -677,7 +688,7 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
         if (penv && std::sscanf(penv, "%d,%d,%d", &vr, &vs, &va) == 3 && vr >= 0 && vr <= 4 && vs >= 0 && vs <= 3 &&
             va >= 0 && va <= 3) {
             FastGeom fgp;
-            s->v_real = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, vr, &fgp) ? vr : 0;
+            s->v_real = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, vr, &fgp, s->phys) ? vr : 0;
             s->v_spec = vs;
             for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = va;
             s->tuned = true;
@@ -721,8 +732,8 @@ int ensure_ref64(ahom_solver* s, int nload) {
 }
 
 // Conjugate gradients for n_load strains (cfg.scheme == AHOM_SCHEME_CG).
-int solve_cg(ahom_solver* s, int n_load, const double* eps_bar, void* strain_out, int* iters, double* resid,
-             double* mean_stress, int mem_flags) {
+int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
+             double* mean_out, int mem_flags) {
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;
@@ -732,12 +743,8 @@ int solve_cg(ahom_solver* s, int n_load, const double* eps_bar, void* strain_out
     if ((rc = s->autotune(n_load))) return rc;
     const Plan& P = s->pat->plan;
     const int nc = s->ncomp;
-    const int* comp = s->dim == 3 ? kComp3 : kComp2;
     hipStream_t st = s->stream;
-    std::vector<double> eb((size_t)n_load * nc);
-    for (int l = 0; l < n_load; ++l)
-        for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
-    HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(s->d_epsbar, ebc, (size_t)n_load * nc * sizeof(double), hipMemcpyHostToDevice, st));
     if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
     if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
     FillArgs f{};
@@ -791,15 +798,8 @@ int solve_cg(ahom_solver* s, int n_load, const double* eps_bar, void* strain_out
         const LoadState& ls = s->h_st[l];
         if (iters) iters[l] = ls.iter;
         if (resid) resid[l] = ls.resid;
-        if (mean_stress) {
-            double* ms9 = mean_stress + (size_t)l * 9;
-            for (int q = 0; q < 9; ++q) ms9[q] = 0.0;
-            for (int c = 0; c < nc; ++c) {
-                const int pos = comp[c];
-                ms9[pos] = ls.mean[c];
-                ms9[(pos % 3) * 3 + pos / 3] = ls.mean[c];
-            }
-        }
+        if (mean_out)
+            for (int c = 0; c < nc; ++c) mean_out[(size_t)l * nc + c] = ls.mean[c];
         if (ls.status == 2) ret = AHOM_E_DIVERGED;
         else if (ls.status == 1 && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
     }
@@ -1023,6 +1023,7 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     if (cfg->stop_rule == AHOM_STOP_CAUCHY && cfg->precision == AHOM_FP32_MIXED && !(cfg->refine < 0.0))
         return fail(AHOM_E_ARG, "the Cauchy stop rule in FP32 needs refine < 0 (no restarts)");
     if (cfg->scheme != AHOM_SCHEME_BASIC && cfg->scheme != AHOM_SCHEME_CG) return fail(AHOM_E_ARG, "unknown scheme");
+    if (cfg->physics != AHOM_ELASTICITY && cfg->physics != AHOM_CONDUCTIVITY) return fail(AHOM_E_ARG, "unknown physics");
     if (cfg->scheme == AHOM_SCHEME_CG && (cfg->precision != AHOM_FP64 || cfg->stop_rule != AHOM_STOP_RESIDUAL))
         return fail(AHOM_E_ARG, "the conjugate-gradient scheme runs in AHOM_FP64 with the residual stop rule");
     return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
@@ -1030,12 +1031,53 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
 
 void ahom_solver_destroy(ahom_solver* s) { delete s; }
 
+}  // extern "C"
+
+namespace {
+// phase table (pairs per phase) and phase ids on the device; the default
+// reference is the mean of the extreme values of each slot
+int upload_table(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags);
+}  // namespace
+
+extern "C" {
+
 int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags) {
     if (!s || !lame || !phase || n_phase < 1 || n_phase > 256) return fail(AHOM_E_ARG, "bad material arguments");
-    double llo = 1e300, lhi = -1e300, mlo = 1e300, mhi = -1e300;
+    if (s->phys != PHYS_ELASTIC) return fail(AHOM_E_ARG, "a conductivity solver: use ahom_solver_set_conductivity");
     for (int k = 0; k < n_phase; ++k) {
         const double l = lame[2 * k], mu = lame[2 * k + 1];
         if (!(mu > 0.0) || !(3.0 * l + 2.0 * mu > 0.0)) return fail(AHOM_E_MATERIAL, "phase " + std::to_string(k) + ": need mu > 0 and 3 lambda + 2 mu > 0");
+    }
+    return upload_table(s, n_phase, lame, phase, mem_flags);
+}
+
+int ahom_solver_set_conductivity(ahom_solver* s, int n_phase, const double* k, const uint8_t* phase, int mem_flags) {
+    if (!s || !k || !phase || n_phase < 1 || n_phase > 256) return fail(AHOM_E_ARG, "bad material arguments");
+    if (s->phys != PHYS_THERMAL) return fail(AHOM_E_ARG, "an elasticity solver: use ahom_solver_set_material");
+    double tab[512];
+    for (int q = 0; q < n_phase; ++q) {
+        if (!(k[q] > 0.0) || !std::isfinite(k[q])) return fail(AHOM_E_MATERIAL, "phase " + std::to_string(q) + ": need 0 < k < inf");
+        tab[2 * q] = tab[2 * q + 1] = k[q];
+    }
+    return upload_table(s, n_phase, tab, phase, mem_flags);
+}
+
+int ahom_solver_set_reference_conductivity(ahom_solver* s, double k0) {
+    if (!s) return fail(AHOM_E_ARG, "null solver");
+    if (s->phys != PHYS_THERMAL) return fail(AHOM_E_ARG, "an elasticity solver: use ahom_solver_set_reference");
+    if (!(k0 > 0.0) || !std::isfinite(k0)) return fail(AHOM_E_MATERIAL, "reference needs 0 < k0 < inf");
+    s->lam0 = s->mu0 = k0;
+    s->ref_set = true;
+    return AHOM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int upload_table(ahom_solver* s, int n_phase, const double* lame, const uint8_t* phase, int mem_flags) {
+    double llo = 1e300, lhi = -1e300, mlo = 1e300, mhi = -1e300;
+    for (int k = 0; k < n_phase; ++k) {
+        const double l = lame[2 * k], mu = lame[2 * k + 1];
         llo = std::min(llo, l); lhi = std::max(lhi, l); mlo = std::min(mlo, mu); mhi = std::max(mhi, mu);
     }
     const int64_t m = s->pat->sf.m;
@@ -1067,8 +1109,13 @@ int ahom_solver_set_material(ahom_solver* s, int n_phase, const double* lame, co
     return AHOM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int mem_flags) {
     if (!s || !lame_pts) return fail(AHOM_E_ARG, "null argument");
+    if (s->phys != PHYS_ELASTIC) return fail(AHOM_E_ARG, "per-point fields are elastic only");
     const int64_t m = s->pat->sf.m;
     std::vector<double> h;
     const double* hp = lame_pts;
@@ -1102,6 +1149,7 @@ int ahom_solver_set_stiffness_field(ahom_solver* s, const double* lame_pts, int 
 
 int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0) {
     if (!s) return fail(AHOM_E_ARG, "null solver");
+    if (s->phys != PHYS_ELASTIC) return fail(AHOM_E_ARG, "a conductivity solver: use ahom_solver_set_reference_conductivity");
     if (!(mu0 > 0.0) || !(lambda0 + 2.0 * mu0 > 0.0)) return fail(AHOM_E_MATERIAL, "reference needs mu0 > 0 and lambda0 + 2 mu0 > 0");
     s->lam0 = lambda0;
     s->mu0 = mu0;
@@ -1109,15 +1157,20 @@ int ahom_solver_set_reference(ahom_solver* s, double lambda0, double mu0) {
     return AHOM_OK;
 }
 
-int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* init, void* strain_out,
-               int* iters, double* resid, double* mean_stress, int mem_flags) {
-    if (!s || !eps_bar || n_load < 1) return fail(AHOM_E_ARG, "bad solve arguments");
+}  // extern "C"
+
+namespace {
+// Algorithm 1 (or CG) for n_load macroscopic fields given as component
+// vectors ebc[n_load * ncomp] of the solver's field layout; mean_out
+// (nullable) receives the mean stress (flux) components the same way.
+int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, void* strain_out,
+               int* iters, double* resid, double* mean_out, int mem_flags) {
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
     if (init && s->cfg.stop_rule == AHOM_STOP_CAUCHY)
         return fail(AHOM_E_ARG, "the Cauchy stop rule measures against sqrt(m) |eps_bar|, not a guessed start: no init");
     if (s->cg) {
         if (init) return fail(AHOM_E_ARG, "the conjugate-gradient scheme starts from eps_bar (no init)");
-        return solve_cg(s, n_load, eps_bar, strain_out, iters, resid, mean_stress, mem_flags);
+        return solve_cg(s, n_load, ebc, strain_out, iters, resid, mean_out, mem_flags);
     }
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
@@ -1128,25 +1181,19 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
     if ((rc = s->autotune(n_load))) return rc;
     const Plan& P = s->pat->plan;
     const int nc = s->ncomp;
-    const int* comp = s->dim == 3 ? kComp3 : kComp2;
     hipStream_t st = s->stream;
     const bool refine = s->prec == AHOM_FP32_MIXED && s->cfg.refine > 0.0;
     if (refine) s->cur_tol = std::max(s->cfg.tol, s->cfg.refine);
     // set up the FP64 companion ahead of the timed region when a restart is expected
     if (refine && s->cfg.tol < s->cur_tol && (rc = ensure_ref64(s, n_load))) return rc;
-    std::vector<double> eb((size_t)n_load * nc);
-    for (int l = 0; l < n_load; ++l)
-        for (int c = 0; c < nc; ++c) eb[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
+    const std::vector<double> eb(ebc, ebc + (size_t)n_load * nc);
     HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
     // denominator of the Cauchy measure: |eps(0)| = sqrt(m) |eps_bar|_F for the
     // plain start (kept with a user initial guess)
     std::vector<double> norm0(n_load);
     for (int l = 0; l < n_load; ++l) {
         double f = 0.0;
-        for (int c = 0; c < nc; ++c) {
-            const bool diag = s->dim == 3 ? c < 3 : c < 2;
-            f += (diag ? 1.0 : 2.0) * eb[(size_t)l * nc + c] * eb[(size_t)l * nc + c];
-        }
+        for (int c = 0; c < nc; ++c) f += field_weight(s->phys, s->dim, c) * eb[(size_t)l * nc + c] * eb[(size_t)l * nc + c];
         norm0[l] = std::sqrt((double)P.m * f);
     }
     HIPCHK(hipMemcpyAsync(s->d_norm0, norm0.data(), norm0.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -1329,21 +1376,69 @@ int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* in
         const LoadState& ls = s->h_st[l];
         if (iters) iters[l] = ls.iter;
         if (resid) resid[l] = ls.resid;
-        if (mean_stress) {
-            double* ms9 = mean_stress + (size_t)l * 9;
-            for (int q = 0; q < 9; ++q) ms9[q] = 0.0;
-            for (int c = 0; c < nc; ++c) {
-                const int pos = comp[c];
-                ms9[pos] = ls.mean[c];
-                ms9[(pos % 3) * 3 + pos / 3] = ls.mean[c];
-            }
-        }
+        if (mean_out)
+            for (int c = 0; c < nc; ++c) mean_out[(size_t)l * nc + c] = ls.mean[c];
         if (ls.status == 2) ret = AHOM_E_DIVERGED;
         else if ((ls.status == 1 || (s->cfg.stop_rule == AHOM_STOP_RESIDUAL && ls.resid > s->cfg.tol)) && ret == AHOM_OK)
             ret = AHOM_W_NOT_CONVERGED;
     }
     if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
     return ret;
+}
+}  // namespace
+
+extern "C" {
+
+int ahom_solve(ahom_solver* s, int n_load, const double* eps_bar, const void* init, void* strain_out,
+               int* iters, double* resid, double* mean_stress, int mem_flags) {
+    if (!s || !eps_bar || n_load < 1) return fail(AHOM_E_ARG, "bad solve arguments");
+    if (s->phys != PHYS_ELASTIC) return fail(AHOM_E_ARG, "a conductivity solver: use ahom_solve_conductivity");
+    const int nc = s->ncomp;
+    const int* comp = s->dim == 3 ? kComp3 : kComp2;
+    std::vector<double> ebc((size_t)n_load * nc), mc((size_t)n_load * nc);
+    for (int l = 0; l < n_load; ++l)
+        for (int c = 0; c < nc; ++c) ebc[(size_t)l * nc + c] = eps_bar[(size_t)l * 9 + comp[c]];
+    const int ret = solve_core(s, n_load, ebc.data(), init, strain_out, iters, resid, mc.data(), mem_flags);
+    if (ret < 0 && ret != AHOM_E_DIVERGED) return ret;
+    if (mean_stress)
+        for (int l = 0; l < n_load; ++l) {
+            double* ms9 = mean_stress + (size_t)l * 9;
+            for (int q = 0; q < 9; ++q) ms9[q] = 0.0;
+            for (int c = 0; c < nc; ++c) {
+                const int pos = comp[c];
+                ms9[pos] = mc[(size_t)l * nc + c];
+                ms9[(pos % 3) * 3 + pos / 3] = mc[(size_t)l * nc + c];
+            }
+        }
+    return ret;
+}
+
+int ahom_solve_conductivity(ahom_solver* s, int n_load, const double* grad_bar, void* field_out, int* iters, double* resid,
+                            double* mean_flux, int mem_flags) {
+    if (!s || !grad_bar || n_load < 1) return fail(AHOM_E_ARG, "bad solve arguments");
+    if (s->phys != PHYS_THERMAL) return fail(AHOM_E_ARG, "an elasticity solver: use ahom_solve");
+    const int d = s->dim;
+    std::vector<double> ebc((size_t)n_load * d), mc((size_t)n_load * d);
+    for (int l = 0; l < n_load; ++l)
+        for (int c = 0; c < d; ++c) ebc[(size_t)l * d + c] = grad_bar[(size_t)l * 3 + c];
+    const int ret = solve_core(s, n_load, ebc.data(), nullptr, field_out, iters, resid, mc.data(), mem_flags);
+    if (ret < 0 && ret != AHOM_E_DIVERGED) return ret;
+    if (mean_flux)
+        for (int l = 0; l < n_load; ++l)
+            for (int c = 0; c < 3; ++c) mean_flux[(size_t)l * 3 + c] = c < d ? mc[(size_t)l * d + c] : 0.0;
+    return ret;
+}
+
+int ahom_effective_conductivity(ahom_solver* s, double* Keff, int* iters) {
+    if (!s || !Keff) return fail(AHOM_E_ARG, "null argument");
+    const int d = s->dim;
+    std::vector<double> g((size_t)d * 3, 0.0), q((size_t)d * 3);
+    for (int l = 0; l < d; ++l) g[(size_t)l * 3 + l] = 1.0;
+    const int rc = ahom_solve_conductivity(s, d, g.data(), nullptr, iters, nullptr, q.data(), AHOM_MEM_HOST);
+    if (rc < 0) return rc;
+    for (int col = 0; col < d; ++col)
+        for (int row = 0; row < d; ++row) Keff[row * d + col] = q[(size_t)col * 3 + row];
+    return rc;
 }
 
 int ahom_effective_stiffness(ahom_solver* s, double* Ceff, int* iters) {
@@ -1386,6 +1481,7 @@ int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes
     f.buf = s->d_buf0; f.eps_bar = s->d_epsbar; f.S = P.S; f.row = P.S / P.ax[0].slen; f.nfield = s->ncomp;
     if (ahom_launch_fill(s->prec, f, nload, st)) return fail(AHOM_E_DEVICE, "fill");
     ReduceArgs r{};
+    r.phys = s->phys;
     r.st = s->d_st; r.sig_part = s->d_sig; r.res_part = s->d_res; r.hist = s->d_hist;
     r.n_real = s->n_real_wg(); r.n_spec = s->n_spec_wg(); r.hist_cap = s->hist_cap; r.m = P.m;
     r.tol = -1.0; r.max_iter = 1 << 30; r.resid_period = s->cfg.resid_period;

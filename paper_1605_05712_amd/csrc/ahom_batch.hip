@@ -504,6 +504,7 @@ static int batch_create(int d, int n_members, const int64_t* M, const double* L,
     if (!(cfg->refine < 1.0)) return bfail(AHOM_E_ARG, "refine must be < 1");
     if (cfg->stop_rule != AHOM_STOP_RESIDUAL) return bfail(AHOM_E_ARG, "batches stop on the residual only");
     if (cfg->scheme != AHOM_SCHEME_BASIC) return bfail(AHOM_E_ARG, "batches run the Basic Scheme only");
+    if (cfg->physics != AHOM_ELASTICITY) return bfail(AHOM_E_ARG, "batches solve elasticity only");
     ahom_batch* b = new (std::nothrow) ahom_batch();
     if (!b) return bfail(AHOM_E_NOMEM, "host allocation failed");
     b->d = d;

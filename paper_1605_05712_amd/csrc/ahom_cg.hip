@@ -31,7 +31,7 @@ template <typename T> struct CT;
 template <> struct CT<double> { using t = double2; };
 template <> struct CT<float> { using t = float2; };
 
-template <int DIM> struct NComp { static constexpr int N = DIM == 3 ? 6 : 3; };
+template <int DIM, int PH> struct NComp { static constexpr int N = Fields<DIM, PH>::N; };
 
 // block-wide fixed-order sum of NV doubles per thread; result in thread 0
 template <int NV>
@@ -50,9 +50,9 @@ __device__ void cg_block_sum(double* vals, double* scratch) {
 
 // alpha = <r, r>_C0 / <p, C p> (1 for the start), and the mean stress
 // recurrence <sigma> += alpha <C p>
-template <int DIM>
+template <int DIM, int PH>
 __global__ void __launch_bounds__(kWG) k_cg_alpha(CgArgs a) {
-    constexpr int NC = NComp<DIM>::N;
+    constexpr int NC = NComp<DIM, PH>::N;
     __shared__ double scratch[(NC + 1) * kWG];
     const int load = blockIdx.x;
     LoadState& st = a.st[load];
@@ -79,10 +79,10 @@ __global__ void __launch_bounds__(kWG) k_cg_alpha(CgArgs a) {
 // Start: r = p = q (q = -Gamma0 C eps_bar, the operator output), no x update.
 // Update: x += alpha p, r += alpha q (q = -A p).  Both: partial sums of
 // <r, r>_C0 per workgroup.
-template <typename T, int DIM>
+template <typename T, int DIM, int PH>
 __global__ void __launch_bounds__(kWG) k_cg_update(CgArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NC = NComp<DIM>::N;
+    constexpr int NC = NComp<DIM, PH>::N;
     __shared__ double scratch[kWG];
     const int load = blockIdx.y;
     const LoadState& st = a.st[load];
@@ -114,22 +114,22 @@ __global__ void __launch_bounds__(kWG) k_cg_update(CgArgs a) {
                 r = C{r0.x + al * q.x, r0.y + al * q.y};
             }
             R[i] = r;
-            const bool diag = DIM == 3 ? c < 3 : c < 2;
-            e += (diag ? 1.0 : 2.0) * ((double)r.x * (double)r.x + (double)r.y * (double)r.y);
-            if (diag) { trx += (double)r.x; try_ += (double)r.y; }
+            e += field_weight(PH, DIM, c) * ((double)r.x * (double)r.x + (double)r.y * (double)r.y);
+            if (c < DIM) { trx += (double)r.x; try_ += (double)r.y; }
         }
         const int64_t k0 = s / a.I;
         const double w = (k0 == 0 || 2 * k0 == a.L0) ? 1.0 : 2.0;
-        acc += w * (two_mu0 * e + lam0 * (trx * trx + try_ * try_));
+        // r : C0 : r = lambda0 |tr r|^2 + 2 mu0 |r|^2 (elasticity), k0 |r|^2 (conductivity, k0 = mu0)
+        acc += w * (PH == PHYS_THERMAL ? a.mu0 * e : two_mu0 * e + lam0 * (trx * trx + try_ * try_));
     }
     cg_block_sum<1>(&acc, scratch);
     if (threadIdx.x == 0) a.rr_part[(int64_t)load * gridDim.x + blockIdx.x] = acc;
 }
 
 // <r, r>_C0, beta, the equilibrium residual of the iterate, stop decision
-template <int DIM>
+template <int DIM, int PH>
 __global__ void __launch_bounds__(kWG) k_cg_reduce(CgArgs a) {
-    constexpr int NC = NComp<DIM>::N;
+    constexpr int NC = NComp<DIM, PH>::N;
     __shared__ double scratch[2 * kWG];
     const int load = blockIdx.x;
     LoadState& st = a.st[load];
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kWG) k_cg_reduce(CgArgs a) {
     CgScalars& g = a.cg[load];
     const double rr = (double)a.L0 * v[0];
     double fro = 0.0;
-    for (int c = 0; c < NC; ++c) fro += ((DIM == 3 ? c < 3 : c < 2) ? 1.0 : 2.0) * st.mean[c] * st.mean[c];
+    for (int c = 0; c < NC; ++c) fro += field_weight(PH, DIM, c) * st.mean[c] * st.mean[c];
     const double r = sqrt(v[1]) / sqrt(fro);
     const int n = a.start ? 0 : st.iter + 1;
     if (a.start) {
@@ -163,10 +163,10 @@ __global__ void __launch_bounds__(kWG) k_cg_reduce(CgArgs a) {
 }
 
 // p(n) = r(n) + beta p(n - 1): from buf[(n - 1) & 1] into buf[n & 1]
-template <typename T, int DIM>
+template <typename T, int DIM, int PH>
 __global__ void __launch_bounds__(kWG) k_cg_direction(CgArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NC = NComp<DIM>::N;
+    constexpr int NC = NComp<DIM, PH>::N;
     const int load = blockIdx.y;
     const LoadState& st = a.st[load];
     if (st.done) return;
@@ -189,38 +189,31 @@ int ahom_cg_blocks(int64_t S) {
     return (int)(b < kMaxBlocks ? (b < 1 ? 1 : b) : kMaxBlocks);
 }
 
+// kernel of the given precision, dimension and physics
+#define AHOM_CG_PICK(K, ...)                                                                      \
+    (a.phys == PHYS_THERMAL ? (dim == 3 ? K<__VA_ARGS__ 3, PHYS_THERMAL> : K<__VA_ARGS__ 2, PHYS_THERMAL>) \
+                            : (dim == 3 ? K<__VA_ARGS__ 3, PHYS_ELASTIC> : K<__VA_ARGS__ 2, PHYS_ELASTIC>))
+
 int ahom_launch_cg_alpha(int dim, const CgArgs& a, int nload, hipStream_t s) {
-    if (dim == 3) hipLaunchKernelGGL(k_cg_alpha<3>, dim3(nload), dim3(kWG), 0, s, a);
-    else hipLaunchKernelGGL(k_cg_alpha<2>, dim3(nload), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_alpha, ), dim3(nload), dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int ahom_launch_cg_update(int prec, int dim, const CgArgs& a, int nload, hipStream_t s) {
     const dim3 grid(a.nblk, nload);
-    if (prec == 0) {
-        if (dim == 3) hipLaunchKernelGGL((k_cg_update<double, 3>), grid, dim3(kWG), 0, s, a);
-        else hipLaunchKernelGGL((k_cg_update<double, 2>), grid, dim3(kWG), 0, s, a);
-    } else {
-        if (dim == 3) hipLaunchKernelGGL((k_cg_update<float, 3>), grid, dim3(kWG), 0, s, a);
-        else hipLaunchKernelGGL((k_cg_update<float, 2>), grid, dim3(kWG), 0, s, a);
-    }
+    if (prec == 0) hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_update, double, ), grid, dim3(kWG), 0, s, a);
+    else hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_update, float, ), grid, dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int ahom_launch_cg_reduce(int dim, const CgArgs& a, int nload, hipStream_t s) {
-    if (dim == 3) hipLaunchKernelGGL(k_cg_reduce<3>, dim3(nload), dim3(kWG), 0, s, a);
-    else hipLaunchKernelGGL(k_cg_reduce<2>, dim3(nload), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_reduce, ), dim3(nload), dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int ahom_launch_cg_direction(int prec, int dim, const CgArgs& a, int nload, hipStream_t s) {
     const dim3 grid(a.nblk, nload);
-    if (prec == 0) {
-        if (dim == 3) hipLaunchKernelGGL((k_cg_direction<double, 3>), grid, dim3(kWG), 0, s, a);
-        else hipLaunchKernelGGL((k_cg_direction<double, 2>), grid, dim3(kWG), 0, s, a);
-    } else {
-        if (dim == 3) hipLaunchKernelGGL((k_cg_direction<float, 3>), grid, dim3(kWG), 0, s, a);
-        else hipLaunchKernelGGL((k_cg_direction<float, 2>), grid, dim3(kWG), 0, s, a);
-    }
+    if (prec == 0) hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_direction, double, ), grid, dim3(kWG), 0, s, a);
+    else hipLaunchKernelGGL(AHOM_CG_PICK(k_cg_direction, float, ), grid, dim3(kWG), 0, s, a);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -321,9 +321,7 @@ __device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __
     return C{(T)w.x, (T)w.y};
 }
 
-template <int DIM> struct Comp;
-template <> struct Comp<3> { static constexpr int N = 6, NP = 3, NT = 3; };
-template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
+template <int DIM, int PH = PHYS_ELASTIC> using Comp = Fields<DIM, PH>;
 
 template <typename T> __device__ __forceinline__ T* smem() {
     extern __shared__ __align__(16) unsigned char ahom_fast_smem[];
@@ -434,10 +432,10 @@ __device__ __forceinline__ int64_t uni(int64_t v) {
 // go through LDS.  (Per-point Lame fields are read in the law directly: a
 // slower path.)
 // =============================================================================
-template <typename T, int DIM, int L, int V>
-__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_real(RealArgs a) {
+template <typename T, int DIM, int L, int V, int PH>
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::NP, V>::THREADS)) kf_real(RealArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NCOMP = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    constexpr int NCOMP = Comp<DIM, PH>::N, NP = Comp<DIM, PH>::NP;
     using G = Geo<T, L, NP, V>;
     constexpr int NC = G::NC, CS = G::CS, H = L / 2 + 1, TH = G::THREADS, NW = TH / 64;
     constexpr int EPT = (H * NC + TH - 1) / TH;     // half-spectrum rows per thread
@@ -572,18 +570,27 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::NP, V>::THREADS)) kf_rea
                 eps[2 * p] = z.x;
                 if (2 * p + 1 < NCOMP) eps[2 * p + 1] = z.y;
             }
-            const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
-            const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
             T tau[NCOMP];
+            if constexpr (PH == PHYS_THERMAL) {
+                // flux q = k e, polarization (k - k0) e; k in the lambda slot
 #pragma unroll
-            for (int c = 0; c < NCOMP; ++c) {
-                const bool diag = DIM == 3 ? c < 3 : c < 2;
-                sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
-                tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+                for (int c = 0; c < NCOMP; ++c) {
+                    sig[c] += (double)(lam * eps[c]);
+                    tau[c] = (lam - lam0) * eps[c];
+                }
+            } else {
+                const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+                const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+#pragma unroll
+                for (int c = 0; c < NCOMP; ++c) {
+                    const bool diag = DIM == 3 ? c < 3 : c < 2;
+                    sig[c] += (double)((T)2 * mu * eps[c] + (diag ? lam * tr : (T)0));
+                    tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+                }
             }
             if (energy) {
 #pragma unroll
-                for (int c = 0; c < NCOMP; ++c) en += ((DIM == 3 ? c < 3 : c < 2) ? 1.0 : 2.0) * (double)eps[c] * (double)tau[c];
+                for (int c = 0; c < NCOMP; ++c) en += field_weight(PH, DIM, c) * (double)eps[c] * (double)tau[c];
             }
 #pragma unroll
             for (int p = 0; p < NP; ++p)
@@ -1099,10 +1106,10 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
 // =============================================================================
 // spectral turnaround along the last axis
 // =============================================================================
-template <typename T, int DIM, int L, int V>
-__global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec(SpecArgs a) {
+template <typename T, int DIM, int L, int V, int PH>
+__global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::N, V>::THREADS)) kf_spec(SpecArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NCOMP = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    constexpr int NCOMP = Comp<DIM, PH>::N, NT = Comp<DIM, PH>::NT;
     using G = Geo<T, L, NCOMP, V>;
     constexpr int NC = G::NC, CS = G::CS, TH = G::THREADS;
     constexpr int EPT = (NC * L + TH - 1) / TH;
@@ -1122,7 +1129,9 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
     twr.load(reinterpret_cast<const C*>(a.tw) + P.ax[D - 1].tw_off, tid);
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
-    const double cau_c1 = 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
+    // Cauchy step |eps_hat(n+1) - eps_hat(n)|^2: (|dt|^2 + c1 |xi . dt|^2) / (2 mu0^2)
+    // in elasticity, |dt|^2 / k0^2 for conductivity
+    const double cau_c1 = PH == PHYS_THERMAL ? 0.0 : 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
     const int last_snf = P.ax[D - 1].snf;
     const int64_t last_mult = P.ax[D - 1].mult;
     // Along a column only the last axis moves: kappa = kappa_b + l mult u_snf,
@@ -1359,7 +1368,11 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
 #pragma unroll
             for (int f = 0; f < NCOMP; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
             C tt[NT];
-            if constexpr (DIM == 3) {
+            if constexpr (PH == PHYS_THERMAL) {
+                tt[0] = C{(T)0, (T)0};
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) { tt[0].x += tv[i].x * xi[i]; tt[0].y += tv[i].y * xi[i]; }
+            } else if constexpr (DIM == 3) {
                 const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
                 tt[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
                 tt[1] = C{T01.x * xi[0] + T11.x * xi[1] + T12.x * xi[2], T01.y * xi[0] + T11.y * xi[1] + T12.y * xi[2]};
@@ -1412,24 +1425,30 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM>::N, V>::THREADS)) kf_spec
                     tt[c] = C{tt[c].x + o.x, tt[c].y + o.y};
                 }
             }
-            C xt = C{(T)0, (T)0};
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * tt[i].x; xt.y += xi[i] * tt[i].y; }
             const T im0 = (T)1 / mu0;
-            C v[DIM];
+            if constexpr (PH == PHYS_THERMAL) {
+                // e_hat = -xi (tau_hat . xi) / k0
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) v[i] = C{(tt[i].x - beta * xt.x * xi[i]) * im0, (tt[i].y - beta * xt.y * xi[i]) * im0};
-            if constexpr (DIM == 3) {
-                *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
-                *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
-                *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
-                *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
-                *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
-                *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+                for (int i = 0; i < DIM; ++i) *fp[i] = C{-xi[i] * tt[0].x * im0, -xi[i] * tt[0].y * im0};
             } else {
-                *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
-                *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
-                *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+                C xt = C{(T)0, (T)0};
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) { xt.x += xi[i] * tt[i].x; xt.y += xi[i] * tt[i].y; }
+                C v[DIM];
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) v[i] = C{(tt[i].x - beta * xt.x * xi[i]) * im0, (tt[i].y - beta * xt.y * xi[i]) * im0};
+                if constexpr (DIM == 3) {
+                    *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+                    *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+                    *fp[2] = C{-xi[2] * v[2].x, -xi[2] * v[2].y};
+                    *fp[3] = C{(T)-0.5 * (xi[1] * v[2].x + xi[2] * v[1].x), (T)-0.5 * (xi[1] * v[2].y + xi[2] * v[1].y)};
+                    *fp[4] = C{(T)-0.5 * (xi[0] * v[2].x + xi[2] * v[0].x), (T)-0.5 * (xi[0] * v[2].y + xi[2] * v[0].y)};
+                    *fp[5] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+                } else {
+                    *fp[0] = C{-xi[0] * v[0].x, -xi[0] * v[0].y};
+                    *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
+                    *fp[2] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
+                }
             }
         });
         // fixed-order residual and Cauchy sums: inside the wave, then waves in order
@@ -1506,9 +1525,16 @@ FastGeom geom_of(int kind) {
 // lengths with tile variants; shorter transforms use variant 0 only
 constexpr bool tuned_length(int L) { return L >= 32; }
 
+// fields held by a tile: packed transforms (real-space pass), components
+// (spectral pass) or one field (middle axes)
+inline int tile_fields(int kind, int dim, int phys) {
+    const int n = phys == PHYS_THERMAL ? dim : (dim == 3 ? 6 : 3);
+    return kind == FAST_REAL ? (n + 1) / 2 : (kind == FAST_SPEC ? n : 1);
+}
+
 template <typename T, int V>
-bool geom_TV(int kind, int dim, int L, FastGeom* g) {
-    const int nf = kind == FAST_REAL ? (dim == 3 ? 3 : 2) : (kind == FAST_SPEC ? (dim == 3 ? 6 : 3) : 1);
+bool geom_TV(int kind, int dim, int L, FastGeom* g, int phys = PHYS_ELASTIC) {
+    const int nf = tile_fields(kind, dim, phys);
 #define AHOM_G(LL)                                                     \
     case LL:                                                           \
         if (nf == 1) *g = geom_of<T, LL, 1, V>(kind);                  \
@@ -1527,8 +1553,8 @@ bool geom_TV(int kind, int dim, int L, FastGeom* g) {
 // shorter than the tuned lengths instantiate variant 0 only, so their launch
 // geometry (threads, LDS, grid) must be variant 0's as well.
 template <typename T, int V>
-bool geom_launch(int kind, int dim, int L, FastGeom* g) {
-    return tuned_length(L) ? geom_TV<T, V>(kind, dim, L, g) : geom_TV<T, 0>(kind, dim, L, g);
+bool geom_launch(int kind, int dim, int L, FastGeom* g, int phys) {
+    return tuned_length(L) ? geom_TV<T, V>(kind, dim, L, g, phys) : geom_TV<T, 0>(kind, dim, L, g, phys);
 }
 
 // Set the LDS attribute and return the grid: one workgroup per tile, or for
@@ -1554,17 +1580,17 @@ int go(F fn, const FastGeom& g, int64_t total, int ncu, hipStream_t s, const A& 
     return 0;
 }
 
-template <typename T, int V>
+template <typename T, int V, int PH>
 int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_launch<T, V>(FAST_REAL, dim, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_REAL, dim, L, &g, PH)) return -1;
     // the phase table (Lame pairs in the working precision) follows in LDS
     if (!a.lame_pts_t && (a.n_phase < 1 || a.n_phase > 256 || !a.lame_tab)) return -1;
     if (!a.lame_pts_t) g.lds += (size_t)a.n_phase * 2 * sizeof(T);
 #define AHOM_FR(LL)                                                                    \
     case LL:                                                                           \
-        return dim == 3 ? go(kf_real<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
-                        : go(kf_real<T, 2, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a);
+        return dim == 3 ? go(kf_real<T, 3, LL, (tuned_length(LL) ? V : 0), PH>, g, total, ncu, s, a) \
+                        : go(kf_real<T, 2, LL, (tuned_length(LL) ? V : 0), PH>, g, total, ncu, s, a);
     switch (L) {
         AHOM_FR(1) AHOM_FR(2) AHOM_FR(4) AHOM_FR(8) AHOM_FR(16) AHOM_FR(32) AHOM_FR(64) AHOM_FR(128) AHOM_FR(256)
         default: return -1;
@@ -1575,7 +1601,7 @@ int real_TV(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream
 template <typename T, int V>
 int axis_TV(int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_launch<T, V>(FAST_AXIS, 3, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_AXIS, 3, L, &g, PHYS_ELASTIC)) return -1;
 #define AHOM_FA(LL)                                                                    \
     case LL:                                                                           \
         return dir < 0 ? go(kf_axis<T, LL, -1, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
@@ -1587,14 +1613,14 @@ int axis_TV(int dir, int L, const AxisArgs& a, int64_t total, int ncu, hipStream
 #undef AHOM_FA
 }
 
-template <typename T, int V>
+template <typename T, int V, int PH>
 int spec_TV(int dim, int L, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
     FastGeom g;
-    if (!geom_launch<T, V>(FAST_SPEC, dim, L, &g)) return -1;
+    if (!geom_launch<T, V>(FAST_SPEC, dim, L, &g, PH)) return -1;
 #define AHOM_FS(LL)                                                                    \
     case LL:                                                                           \
-        return dim == 3 ? go(kf_spec<T, 3, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a) \
-                        : go(kf_spec<T, 2, LL, (tuned_length(LL) ? V : 0)>, g, total, ncu, s, a);
+        return dim == 3 ? go(kf_spec<T, 3, LL, (tuned_length(LL) ? V : 0), PH>, g, total, ncu, s, a) \
+                        : go(kf_spec<T, 2, LL, (tuned_length(LL) ? V : 0), PH>, g, total, ncu, s, a);
     switch (L) {
         AHOM_FS(1) AHOM_FS(2) AHOM_FS(4) AHOM_FS(8) AHOM_FS(16) AHOM_FS(32) AHOM_FS(64) AHOM_FS(128) AHOM_FS(256)
         default: return -1;
@@ -1636,41 +1662,51 @@ template <typename T>
 int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
 
 template <typename T>
-bool geom_T(int kind, int dim, int L, int v, FastGeom* g) {
-    if (v == kRRVariant) return kind == FAST_REAL && rr_length(L) && geom_rr_T<T>(dim, L, g);
+bool geom_T(int kind, int dim, int L, int v, FastGeom* g, int phys) {
+    if (v == kRRVariant) return kind == FAST_REAL && phys == PHYS_ELASTIC && rr_length(L) && geom_rr_T<T>(dim, L, g);
     if (v > kRRVariant) return false;
     if (!tuned_length(L)) v = 0;
     switch (v) {
-        case 0: return geom_TV<T, 0>(kind, dim, L, g);
-        case 1: return geom_TV<T, 1>(kind, dim, L, g);
-        case 2: return geom_TV<T, 2>(kind, dim, L, g);
-        default: return geom_TV<T, 3>(kind, dim, L, g);
+        case 0: return geom_TV<T, 0>(kind, dim, L, g, phys);
+        case 1: return geom_TV<T, 1>(kind, dim, L, g, phys);
+        case 2: return geom_TV<T, 2>(kind, dim, L, g, phys);
+        default: return geom_TV<T, 3>(kind, dim, L, g, phys);
     }
 }
 
 #define AHOM_DECL_TV(T, V)                                                                                          \
-    extern template int real_TV<T, V>(int, int, const RealArgs&, int64_t, int, hipStream_t);                     \
+    extern template int real_TV<T, V, PHYS_ELASTIC>(int, int, const RealArgs&, int64_t, int, hipStream_t);       \
+    extern template int real_TV<T, V, PHYS_THERMAL>(int, int, const RealArgs&, int64_t, int, hipStream_t);       \
     extern template int axis_TV<T, V>(int, int, const AxisArgs&, int64_t, int, hipStream_t);                     \
-    extern template int spec_TV<T, V>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
-#define AHOM_INST_REAL(T, V) template int real_TV<T, V>(int, int, const RealArgs&, int64_t, int, hipStream_t);
+    extern template int spec_TV<T, V, PHYS_ELASTIC>(int, int, const SpecArgs&, int64_t, int, hipStream_t);       \
+    extern template int spec_TV<T, V, PHYS_THERMAL>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+#define AHOM_INST_REAL(T, V, PH) template int real_TV<T, V, PH>(int, int, const RealArgs&, int64_t, int, hipStream_t);
 #define AHOM_INST_AXIS(T, V) template int axis_TV<T, V>(int, int, const AxisArgs&, int64_t, int, hipStream_t);
-#define AHOM_INST_SPEC(T, V) template int spec_TV<T, V>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+#define AHOM_INST_SPEC(T, V, PH) template int spec_TV<T, V, PH>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
 
 #if defined(AHOM_FAST_PART)
 #if AHOM_FAST_PART == 0
-AHOM_INST_REAL(double, 0) AHOM_INST_REAL(double, 1) AHOM_INST_REAL(double, 2) AHOM_INST_REAL(double, 3)
+AHOM_INST_REAL(double, 0, PHYS_ELASTIC) AHOM_INST_REAL(double, 1, PHYS_ELASTIC) AHOM_INST_REAL(double, 2, PHYS_ELASTIC) AHOM_INST_REAL(double, 3, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 1
-AHOM_INST_REAL(float, 0) AHOM_INST_REAL(float, 1) AHOM_INST_REAL(float, 2) AHOM_INST_REAL(float, 3)
+AHOM_INST_REAL(float, 0, PHYS_ELASTIC) AHOM_INST_REAL(float, 1, PHYS_ELASTIC) AHOM_INST_REAL(float, 2, PHYS_ELASTIC) AHOM_INST_REAL(float, 3, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 2
 AHOM_INST_AXIS(double, 0) AHOM_INST_AXIS(double, 1) AHOM_INST_AXIS(double, 2) AHOM_INST_AXIS(double, 3)
 #elif AHOM_FAST_PART == 3
 AHOM_INST_AXIS(float, 0) AHOM_INST_AXIS(float, 1) AHOM_INST_AXIS(float, 2) AHOM_INST_AXIS(float, 3)
 #elif AHOM_FAST_PART == 4
-AHOM_INST_SPEC(double, 0) AHOM_INST_SPEC(double, 1)
+AHOM_INST_SPEC(double, 0, PHYS_ELASTIC) AHOM_INST_SPEC(double, 1, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 5
-AHOM_INST_SPEC(double, 2) AHOM_INST_SPEC(double, 3)
+AHOM_INST_SPEC(double, 2, PHYS_ELASTIC) AHOM_INST_SPEC(double, 3, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 6
-AHOM_INST_SPEC(float, 0) AHOM_INST_SPEC(float, 1) AHOM_INST_SPEC(float, 2) AHOM_INST_SPEC(float, 3)
+AHOM_INST_SPEC(float, 0, PHYS_ELASTIC) AHOM_INST_SPEC(float, 1, PHYS_ELASTIC) AHOM_INST_SPEC(float, 2, PHYS_ELASTIC) AHOM_INST_SPEC(float, 3, PHYS_ELASTIC)
+#elif AHOM_FAST_PART == 8
+AHOM_INST_REAL(double, 0, PHYS_THERMAL) AHOM_INST_REAL(double, 1, PHYS_THERMAL) AHOM_INST_REAL(double, 2, PHYS_THERMAL) AHOM_INST_REAL(double, 3, PHYS_THERMAL)
+#elif AHOM_FAST_PART == 9
+AHOM_INST_REAL(float, 0, PHYS_THERMAL) AHOM_INST_REAL(float, 1, PHYS_THERMAL) AHOM_INST_REAL(float, 2, PHYS_THERMAL) AHOM_INST_REAL(float, 3, PHYS_THERMAL)
+#elif AHOM_FAST_PART == 10
+AHOM_INST_SPEC(double, 0, PHYS_THERMAL) AHOM_INST_SPEC(double, 1, PHYS_THERMAL) AHOM_INST_SPEC(double, 2, PHYS_THERMAL) AHOM_INST_SPEC(double, 3, PHYS_THERMAL)
+#elif AHOM_FAST_PART == 11
+AHOM_INST_SPEC(float, 0, PHYS_THERMAL) AHOM_INST_SPEC(float, 1, PHYS_THERMAL) AHOM_INST_SPEC(float, 2, PHYS_THERMAL) AHOM_INST_SPEC(float, 3, PHYS_THERMAL)
 #elif AHOM_FAST_PART == 7
 template <typename T>
 int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
@@ -1700,8 +1736,8 @@ extern template int real_RR<float>(int, int, const RealArgs&, int64_t, int, hipS
 #if !defined(AHOM_FAST_PART)
 using namespace ahom_fast_detail;
 
-bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g) {
-    return prec == 0 ? geom_T<double>(kind, dim, L, variant, g) : geom_T<float>(kind, dim, L, variant, g);
+bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g, int phys) {
+    return prec == 0 ? geom_T<double>(kind, dim, L, variant, g, phys) : geom_T<float>(kind, dim, L, variant, g, phys);
 }
 
 #define AHOM_VSWITCH(FN, ...)                                                  \
@@ -1721,14 +1757,36 @@ bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g
             default: return FN<float, 3>(__VA_ARGS__);                         \
         }                                                                      \
     } while (0)
+// the same with the physics as a third template argument
+#define AHOM_VPSWITCH(FN, PH, ...)                                             \
+    do {                                                                       \
+        if (prec == 0) {                                                       \
+            switch (variant) {                                                 \
+                case 0: return FN<double, 0, PH>(__VA_ARGS__);                 \
+                case 1: return FN<double, 1, PH>(__VA_ARGS__);                 \
+                case 2: return FN<double, 2, PH>(__VA_ARGS__);                 \
+                default: return FN<double, 3, PH>(__VA_ARGS__);                \
+            }                                                                  \
+        }                                                                      \
+        switch (variant) {                                                     \
+            case 0: return FN<float, 0, PH>(__VA_ARGS__);                      \
+            case 1: return FN<float, 1, PH>(__VA_ARGS__);                      \
+            case 2: return FN<float, 2, PH>(__VA_ARGS__);                      \
+            default: return FN<float, 3, PH>(__VA_ARGS__);                     \
+        }                                                                      \
+    } while (0)
 
 int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
     int rc;
     if (variant == kRRVariant) {
+        if (a.phys != PHYS_ELASTIC) return -1;   // the register-resident variant is elastic only
         rc = prec == 0 ? real_RR<double>(dim, L, a, total, ncu, s) : real_RR<float>(dim, L, a, total, ncu, s);
         return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    auto run = [&]() -> int { AHOM_VSWITCH(real_TV, dim, L, a, total, ncu, s); };
+    auto run = [&]() -> int {
+        if (a.phys == PHYS_THERMAL) AHOM_VPSWITCH(real_TV, PHYS_THERMAL, dim, L, a, total, ncu, s);
+        AHOM_VPSWITCH(real_TV, PHYS_ELASTIC, dim, L, a, total, ncu, s);
+    };
     rc = run();
     return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -1742,7 +1800,10 @@ int ahom_launch_fast_axis(int prec, int dir, int L, int variant, const AxisArgs&
 
 int ahom_launch_fast_spec(int prec, int dim, int L, int variant, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
     int rc;
-    auto run = [&]() -> int { AHOM_VSWITCH(spec_TV, dim, L, a, total, ncu, s); };
+    auto run = [&]() -> int {
+        if (a.phys == PHYS_THERMAL) AHOM_VPSWITCH(spec_TV, PHYS_THERMAL, dim, L, a, total, ncu, s);
+        AHOM_VPSWITCH(spec_TV, PHYS_ELASTIC, dim, L, a, total, ncu, s);
+    };
     rc = run();
     return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
 }

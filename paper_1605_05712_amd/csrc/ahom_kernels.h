@@ -7,6 +7,24 @@
 #include "ahom_internal.h"
 
 enum { REAL_TURN = 0, REAL_TO_REAL = 1, REAL_FROM_REAL = 2 };
+
+// Physics of the cell problem.  Elasticity: the strain field, components
+// (11,22,33,23,13,12) / (11,22,12), traction sigma_hat xi with d components.
+// Conductivity: the gradient field, components (1,2,3) / (1,2), flux q = k e,
+// the normal flux q_hat . xi (one component); the law's per-phase value k
+// sits in the first slot of the (lambda, mu) table, the reference k0 in both
+// reference constants.
+enum { PHYS_ELASTIC = 0, PHYS_THERMAL = 1 };
+template <int DIM, int PH> struct Fields {
+    static constexpr int N = PH == PHYS_ELASTIC ? (DIM == 3 ? 6 : 3) : DIM;   // real components per point
+    static constexpr int NP = (N + 1) / 2;                                     // packed complex transforms
+    static constexpr int NT = PH == PHYS_ELASTIC ? DIM : 1;                    // traction components
+};
+// weight of component c in a full contraction u : v (symmetric off-diagonal
+// strain components appear twice)
+__host__ __device__ constexpr double field_weight(int ph, int dim, int c) {
+    return (ph == PHYS_ELASTIC && c >= dim) ? 2.0 : 1.0;
+}
 enum { SPEC_TURN = 0, SPEC_INIT = 1 };
 
 // Device-side state of one load case.  iter = n of the iterate being
@@ -22,6 +40,7 @@ struct LoadState {
 };
 
 struct RealArgs {
+    int phys;                 // PHYS_ELASTIC or PHYS_THERMAL
     const Plan* plan;
     void* buf0;
     void* buf1;
@@ -62,6 +81,7 @@ struct AxisArgs {
 };
 
 struct SpecArgs {
+    int phys;                 // PHYS_ELASTIC or PHYS_THERMAL
     const Plan* plan;
     void* buf0;
     void* buf1;
@@ -100,6 +120,7 @@ __host__ __device__ inline bool ahom_write_traction(int n, int period, int max_i
 }
 
 struct ReduceArgs {
+    int phys;                 // PHYS_ELASTIC or PHYS_THERMAL
     LoadState* st;
     const double* sig_part;
     const double* res_part;
@@ -170,6 +191,7 @@ struct CgScalars {
 };
 
 struct CgArgs {
+    int phys;                 // PHYS_ELASTIC or PHYS_THERMAL
     LoadState* st;
     CgScalars* cg;
     double* alpha;            // [load] alpha, read by the spectral pass
@@ -255,7 +277,7 @@ struct FastGeom {
     size_t lds = 0;
 };
 constexpr int AHOM_FAST_VARIANTS = 5;   // tile width x schedule (+ register-resident real pass), chosen by the autotuner
-bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g);
+bool ahom_fast_geom(int prec, int kind, int dim, int L, int variant, FastGeom* g, int phys = PHYS_ELASTIC);
 // total = tiles of the pass (all loads/fields); the grid is sized from the occupancy API
 int ahom_launch_fast_real(int prec, int dim, int L, int variant, const RealArgs& a, int64_t total, int ncu, hipStream_t s);
 int ahom_launch_fast_axis(int prec, int dir, int L, int variant, const AxisArgs& a, int64_t total, int ncu, hipStream_t s);

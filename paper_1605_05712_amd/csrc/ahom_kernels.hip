@@ -244,9 +244,7 @@ __device__ void block_sum(double* vals, double* scratch) {
         for (int c = 0; c < NV; ++c) vals[c] = scratch[c * AHOM_WG];
 }
 
-template <int DIM> struct Comp;
-template <> struct Comp<3> { static constexpr int N = 6, NP = 3, NT = 3; };
-template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
+template <int DIM, int PH = PHYS_ELASTIC> using Comp = Fields<DIM, PH>;
 
 }  // namespace
 
@@ -257,10 +255,10 @@ template <> struct Comp<2> { static constexpr int N = 3, NP = 2, NT = 2; };
 // stress sums of REAL_TURN are added to sig[0..ncomp) (per thread), and with
 // a.en_part set the sum of eps : tau to sig[ncomp].  All threads of the
 // workgroup take part (LDS barriers inside).
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int PH = PHYS_ELASTIC>
 __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int64_t tile, double* sig) {
     using C = typename CT<T>::t;
-    constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    constexpr int NC_ = Comp<DIM, PH>::N, NP = Comp<DIM, PH>::NP;
     const Plan& P = *a.plan;
     const AxisDesc& ax = P.ax[0];
     const int L = ax.len, H = ax.slen;
@@ -368,20 +366,29 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
                 eps[2 * p] = z.x;
                 if (2 * p + 1 < NC_) eps[2 * p + 1] = z.y;
             }
-            const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
-            const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
             T tau[NC_];
+            if constexpr (PH == PHYS_THERMAL) {
+                // flux q = k e, polarization (k - k0) e; k in the lambda slot
 #pragma unroll
-            for (int c = 0; c < NC_; ++c) {
-                const bool diag = DIM == 3 ? c < 3 : c < 2;
-                const T s = (T)2 * mu * eps[c] + (diag ? lam * tr : (T)0);
-                sig[c] += (double)s;
-                tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+                for (int c = 0; c < NC_; ++c) {
+                    sig[c] += (double)(lam * eps[c]);
+                    tau[c] = (lam - lam0) * eps[c];
+                }
+            } else {
+                const T tr = DIM == 3 ? eps[0] + eps[1] + eps[2] : eps[0] + eps[1];
+                const T dl = lam - lam0, dm = (T)2 * (mu - mu0);
+#pragma unroll
+                for (int c = 0; c < NC_; ++c) {
+                    const bool diag = DIM == 3 ? c < 3 : c < 2;
+                    const T s = (T)2 * mu * eps[c] + (diag ? lam * tr : (T)0);
+                    sig[c] += (double)s;
+                    tau[c] = dm * eps[c] + (diag ? dl * tr : (T)0);
+                }
             }
             if (a.en_part) {
                 double en = 0.0;
 #pragma unroll
-                for (int c = 0; c < NC_; ++c) en += ((DIM == 3 ? c < 3 : c < 2) ? 1.0 : 2.0) * (double)eps[c] * (double)tau[c];
+                for (int c = 0; c < NC_; ++c) en += field_weight(PH, DIM, c) * (double)eps[c] * (double)tau[c];
                 sig[NC_] += en;
             }
 #pragma unroll
@@ -454,16 +461,16 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     }
 }
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int PH>
 __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NC_ = Comp<DIM>::N, NP = Comp<DIM>::NP;
+    constexpr int NC_ = Comp<DIM, PH>::N, NP = Comp<DIM, PH>::NP;
     const int load = blockIdx.y;
     if (MODE == REAL_TURN && a.st[load].done) return;
     double sig[NC_ + 1];
 #pragma unroll
     for (int c = 0; c <= NC_; ++c) sig[c] = 0.0;
-    real_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, sig);
+    real_tile<T, DIM, MODE, PH>(a, a.st[load], load, blockIdx.x, sig);
     if (MODE == REAL_TURN) {
         __syncthreads();
         double* red = reinterpret_cast<double*>(lds_base<C>() + (NP + 1) * a.NC * a.CS);
@@ -540,10 +547,10 @@ __global__ void __launch_bounds__(AHOM_WG) k_axis(AxisArgs a) {
 // last axis: spectral turnaround with Gamma0 and the residual terms
 // =============================================================================
 // One tile of the last-axis pass; the residual terms are added to res.
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int PH = PHYS_ELASTIC>
 __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int64_t tile, double& res, double& cau) {
     using C = typename CT<T>::t;
-    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    constexpr int NC_ = Comp<DIM, PH>::N, NT = Comp<DIM, PH>::NT;
     const Plan& P = *a.plan;
     const int par = MODE == SPEC_INIT ? 0 : (st.iter + 1) & 1;
     const int D = P.D;
@@ -576,7 +583,9 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     const double* eb = a.eps_bar + (int64_t)load * NC_;
     const T inv_m = (T)(1.0 / (double)P.m);
     const T mu0 = (T)a.mu0, beta = (T)a.beta;
-    const double cau_c1 = 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
+    // |eps_hat(n+1) - eps_hat(n)|^2 from the traction step: (|dt|^2 + c1 |xi . dt|^2) / (2 mu0^2)
+    // in elasticity, |dt|^2 / k0^2 for conductivity
+    const double cau_c1 = PH == PHYS_THERMAL ? 0.0 : 1.0 - 4.0 * a.beta + 2.0 * a.beta * a.beta;
     const int L0 = P.ax[0].len;
     // Centred numerators in exact doubles while emax <= 2^24 (A in [0, emax),
     // 0 <= kappa_s < e_s <= emax: products < 2^48, sums of three < 2^53), the
@@ -659,7 +668,16 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         hn = 1.0 / sqrt(hn);
         T xi[3];
         for (int i = 0; i < DIM; ++i) xi[i] = (T)(hd[i] * hn);
-        if (MODE == SPEC_INIT) {
+        if constexpr (MODE == SPEC_INIT && PH == PHYS_THERMAL) {
+            // e_hat(0) = value * L0 / m; t(0) = -k0 e_hat(0) . xi
+            const T sc = (T)((double)L0 / (double)P.m), k0 = (T)a.mu0;
+            C acc = C{(T)0, (T)0};
+#pragma unroll
+            for (int f = 0; f < NC_; ++f) { const C v = *fp[f]; acc.x += v.x * sc * xi[f]; acc.y += v.y * sc * xi[f]; }
+            tb[spos] = C{-k0 * acc.x, -k0 * acc.y};
+            continue;
+        }
+        if constexpr (MODE == SPEC_INIT && PH == PHYS_ELASTIC) {
             // eps_hat(0) = value * L0 / m; t(0) = -(C0 : eps_hat(0)) xi
             const T sc = (T)((double)L0 / (double)P.m);
             C ev[NC_];
@@ -688,7 +706,12 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
 #pragma unroll
         for (int f = 0; f < NC_; ++f) { C v = *fp[f]; tv[f] = C{v.x * inv_m, v.y * inv_m}; }
         C t[NT];
-        if constexpr (DIM == 3) {
+        if constexpr (PH == PHYS_THERMAL) {
+            // normal flux tau_hat . xi
+            t[0] = C{(T)0, (T)0};
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) { t[0].x += tv[i].x * xi[i]; t[0].y += tv[i].y * xi[i]; }
+        } else if constexpr (DIM == 3) {
             // components (11,22,33,23,13,12)
             const C T00 = tv[0], T11 = tv[1], T22 = tv[2], T12 = tv[3], T02 = tv[4], T01 = tv[5];
             t[0] = C{T00.x * xi[0] + T01.x * xi[1] + T02.x * xi[2], T00.y * xi[0] + T01.y * xi[1] + T02.y * xi[2]};
@@ -739,6 +762,12 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
 #pragma unroll
             for (int c = 0; c < NT; ++c) t[c] = cadd(t[c], to[(int64_t)c * P.S + spos]);
         }
+        if constexpr (PH == PHYS_THERMAL) {
+            // e_hat = -xi (tau_hat . xi) / k0
+            const T ik0 = (T)1 / mu0;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) *fp[i] = C{-xi[i] * t[0].x * ik0, -xi[i] * t[0].y * ik0};
+        } else {
         // v = (t - beta (xi . t) xi) / mu0 ; eps_hat = -sym(xi (x) v)
         C xt = C{(T)0, (T)0};
 #pragma unroll
@@ -759,6 +788,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
             *fp[1] = C{-xi[1] * v[1].x, -xi[1] * v[1].y};
             *fp[NC_ - 1] = C{(T)-0.5 * (xi[0] * v[1].x + xi[1] * v[0].x), (T)-0.5 * (xi[0] * v[1].y + xi[1] * v[0].y)};
         }
+        }
     }
     if (MODE == SPEC_INIT) return;
     __syncthreads();
@@ -773,14 +803,14 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     }
 }
 
-template <typename T, int DIM, int MODE>
+template <typename T, int DIM, int MODE, int PH>
 __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
     using C = typename CT<T>::t;
-    constexpr int NC_ = Comp<DIM>::N;
+    constexpr int NC_ = Comp<DIM, PH>::N;
     const int load = blockIdx.y;
     if (a.st[load].done) return;
     double res = 0.0, cau = 0.0;
-    spec_tile<T, DIM, MODE>(a, a.st[load], load, blockIdx.x, res, cau);
+    spec_tile<T, DIM, MODE, PH>(a, a.st[load], load, blockIdx.x, res, cau);
     if (MODE == SPEC_INIT) return;
     double rv[2] = {res, cau};
     block_sum<2>(rv, reinterpret_cast<double*>(lds_base<C>() + (NC_ + 1) * a.NC * a.CS));
@@ -793,9 +823,9 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
 // =============================================================================
 // residual / mean stress reduction and loop control (one block per load)
 // =============================================================================
-template <int DIM>
+template <int DIM, int PH>
 __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
-    constexpr int NC_ = Comp<DIM>::N;
+    constexpr int NC_ = Comp<DIM, PH>::N;
     __shared__ double scratch[(NC_ + 1) * AHOM_WG];
     const int load = blockIdx.x;
     LoadState& st = a.st[load];
@@ -819,8 +849,7 @@ __global__ void __launch_bounds__(AHOM_WG) k_reduce(ReduceArgs a) {
     double fro = 0.0;
     for (int c = 0; c < NC_; ++c) {
         mean[c] = v[c] * inv_m + (a.sig_base ? a.sig_base[(int64_t)load * NC_ + c] : 0.0);
-        const bool diag = DIM == 3 ? c < 3 : c < 2;
-        fro += (diag ? 1.0 : 2.0) * mean[c] * mean[c];
+        fro += field_weight(PH, DIM, c) * mean[c] * mean[c];
     }
     const int n = st.iter;
     for (int c = 0; c < NC_; ++c) st.mean[c] = mean[c];
@@ -1238,7 +1267,7 @@ int ahom_launch_real(int prec, int dim, int mode, const RealArgs& a, int nwg, in
     dim3 grid(nwg, nload), block(AHOM_WG);
 #define AHOM_REAL(T, D, M)                                                             \
     do {                                                                               \
-        auto fn = k_real<T, D, M>;                                                     \
+        auto fn = a.phys == PHYS_THERMAL ? k_real<T, D, M, PHYS_THERMAL> : k_real<T, D, M, PHYS_ELASTIC>; \
         if (set_lds<T>((const void*)fn, lds)) return -1;                               \
         hipLaunchKernelGGL(fn, grid, block, lds, s, a);                                \
     } while (0)
@@ -1268,7 +1297,7 @@ int ahom_launch_axis(int prec, int dir, const AxisArgs& a, int nwg, int nfield, 
 
 #define AHOM_SPEC(T, D, M)                                                             \
     do {                                                                               \
-        auto fn = k_spec<T, D, M>;                                                     \
+        auto fn = a.phys == PHYS_THERMAL ? k_spec<T, D, M, PHYS_THERMAL> : k_spec<T, D, M, PHYS_ELASTIC>; \
         if (set_lds<T>((const void*)fn, lds)) return -1;                               \
         hipLaunchKernelGGL(fn, grid, block, lds, s, a);                                \
     } while (0)
@@ -1287,8 +1316,9 @@ int ahom_launch_spec_init(int prec, int dim, const SpecArgs& a, int nwg, int nlo
 }
 
 int ahom_launch_reduce(int dim, const ReduceArgs& a, int nload, hipStream_t s) {
-    if (dim == 3) hipLaunchKernelGGL(k_reduce<3>, dim3(nload), dim3(AHOM_WG), 0, s, a);
-    else hipLaunchKernelGGL(k_reduce<2>, dim3(nload), dim3(AHOM_WG), 0, s, a);
+    auto fn = a.phys == PHYS_THERMAL ? (dim == 3 ? k_reduce<3, PHYS_THERMAL> : k_reduce<2, PHYS_THERMAL>)
+                                     : (dim == 3 ? k_reduce<3, PHYS_ELASTIC> : k_reduce<2, PHYS_ELASTIC>);
+    hipLaunchKernelGGL(fn, dim3(nload), dim3(AHOM_WG), 0, s, a);
     return AHOM_CHECK_LAUNCH();
 }
 

@@ -1,0 +1,177 @@
+"""GPU parity of the conductivity problem (AHOM_CONDUCTIVITY) against the oracle.
+
+Every case prints its name and shape before the GPU call.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import conductivity as K
+from oracle.dft import make_transform
+from tests.gpu_util import perm_between, rel_err
+
+pytestmark = pytest.mark.gpu
+ahom = pytest.importorskip("paper_1605_05712_amd.ahom")
+
+KV = np.array([1.0, 20.0, 4.0])
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rnd_phase(seed, n):
+    def f(pts, m):
+        key = (pts.astype(np.int64) * np.array([7919, 104729, 1299709][: pts.shape[1]])).sum(axis=1)
+        return (np.random.default_rng(seed).permutation(97)[np.abs(key) % 97] % n).astype(np.uint8)
+    return f
+
+
+def solver(P, kv, ph, **kw):
+    S = ahom.Solver(P, physics=ahom.CONDUCTIVITY, **kw)
+    S.set_conductivity(kv, ph)
+    return S
+
+
+CASES = [
+    ("2-D rank-1", [[8, -4], [2, 7]]),
+    ("2-D quincunx", [[16, 16], [-16, 16]]),
+    ("2-D odd 15x21", [[15, 0], [0, 21]]),
+    ("2-D 64x128 fast", [[64, 0], [0, 128]]),
+    ("3-D 8^3", [[8, 0, 0], [0, 8, 0], [0, 0, 8]]),
+    ("3-D sheared", [[12, 0, 0], [0, 6, 0], [3, 0, 4]]),
+    ("3-D rank-1 4096", synth.rank1_matrix(4096, [1, 77, (77 * 77) % 4096]).tolist()),
+    ("3-D 32x64x64 fast", [[32, 0, 0], [0, 64, 0], [0, 0, 64]]),
+    ("3-D 2x256x256 fast", [[2, 0, 0], [0, 256, 0], [0, 0, 256]]),
+    ("2-D rank-1 2^16 split", [[65536, 0], [1, 1]]),
+]
+
+
+@pytest.mark.parametrize("name,M", CASES, ids=[c[0] for c in CASES])
+def test_conductivity_fields_after_fixed_iterations(name, M):
+    """Gradient field after N updates, residual and Cauchy histories, mean flux:
+    FP64 <= 1e-10, FP32 fields 1e-5 of max|e| and residuals 1e-3 relative."""
+    d = len(M)
+    N = 5
+    pf = rnd_phase(43, 3)
+    gb = np.array([0.4, -0.7, 0.25])[:d]
+    T = make_transform(M)
+    r = K.basic_scheme_thermal(M, pf(T.points, T.m), KV, K.default_reference_conductivity(KV), gb, transform=T,
+                               fixed_iters=N)
+    P = ahom.Pattern(M)
+    ip = perm_between(T.points, P.points())
+    ref = r.eps[:, ip]
+    for prec in (ahom.FP64, ahom.FP32_MIXED):
+        say("conductivity fields", name, M, "N", N, "prec", prec)
+        S = solver(P, KV, pf(P.points(), P.m), precision=prec, tol=0.0, max_iter=N, check_period=4, refine=-1.0)
+        out = S.solve_conductivity(np.pad(gb, (0, 3 - d))[None], want_field=True)
+        assert int(out["iters"][0]) == N
+        err = rel_err(out["field"][0], ref)
+        hist = S.history(0)
+        print(f"  prec {prec}: field err {err:.2e}", flush=True)
+        if prec == ahom.FP64:
+            assert err < 1e-10
+            assert np.allclose(hist, r.history, rtol=1e-10, atol=1e-13 * r.history[0])
+            assert np.allclose(S.cauchy_history(0)[:N], r.cauchy, rtol=1e-9, atol=1e-13)
+            assert np.allclose(out["mean_flux"][0][:d], r.mean_stress, rtol=1e-10, atol=1e-13)
+        else:
+            assert err < 1e-5
+            assert np.allclose(hist, r.history, rtol=1e-3, atol=1e-7 * r.history[0])
+            assert np.allclose(out["mean_flux"][0][:d], r.mean_stress, rtol=1e-5, atol=1e-6)
+        del S
+
+
+@pytest.mark.parametrize("scheme", [ahom.SCHEME_BASIC, ahom.SCHEME_CG])
+def test_conductivity_converged_keff_matches_oracle(scheme):
+    M = [[24, 0], [6, 20]]
+    say("conductivity K_eff", M, "scheme", scheme)
+    pf = rnd_phase(47, 3)
+    T = make_transform(M)
+    Kref, runs = K.effective_conductivity(M, pf(T.points, T.m), KV, K.default_reference_conductivity(KV), tol=1e-10,
+                                          transform=T, scheme="basic" if scheme == ahom.SCHEME_BASIC else "cg")
+    P = ahom.Pattern(M)
+    S = solver(P, KV, pf(P.points(), P.m), tol=1e-10, max_iter=5000, scheme=scheme)
+    Ke, it = S.effective_conductivity()
+    print("iterations", list(it), "oracle", [r.iters for r in runs], flush=True)
+    assert list(it) == [r.iters for r in runs]
+    assert rel_err(Ke, Kref) < 1e-10
+    assert np.allclose(Ke, Ke.T, atol=1e-9 * np.abs(Ke).max())
+
+
+@pytest.mark.parametrize("prec", [ahom.FP64, ahom.FP32_MIXED])
+def test_conductivity_exact_laminates(prec):
+    """Arithmetic mean along the layers, harmonic mean across: the aligned rank-1
+    pattern and the grid with axis-normal layers solve the laminate exactly."""
+    kv = np.array([1.0, 10.0])
+    tol = 1e-10 if prec == ahom.FP64 else 1e-5
+    for M, normal in (([[4096, 8192], [0, 1]], [1, 2]), ([[64, 0, 0], [0, 32, 0], [0, 0, 16]], [1, 0, 0])):
+        say("conductivity laminate", M, "prec", prec)
+        P = ahom.Pattern(M)
+        pts = P.points()
+        ph = synth.laminate_phase(pts, P.m) if len(M) == 2 else (pts[:, 0] >= 0).astype(np.uint8)
+        S = solver(P, kv, ph, precision=prec, tol=1e-12 if prec == ahom.FP64 else 1e-6, max_iter=200)
+        Ke, it = S.effective_conductivity()
+        ex = K.laminate_conductivity(1.0, 10.0, float(np.mean(ph == 0)), normal)
+        assert rel_err(Ke, ex) < tol
+
+
+def test_conductivity_fp32_restarts_and_cg_on_a_contrast_100_cell():
+    """Contrast 100 spheres on 32^3: FP32 with FP64 restarts and CG reach tol 1e-6
+    with K_eff equal to the FP64 Basic Scheme's to 1e-5 of max|K|; CG needs a
+    fraction of the updates."""
+    M = [[32, 0, 0], [0, 32, 0], [0, 0, 32]]
+    say("conductivity spheres 32^3", M)
+    c, r = synth.spheres_rsa(seed=3)
+    P = ahom.Pattern(M)
+    ph = synth.spheres_phase(P.points(), P.m, c, r)
+    kv = np.array([1.0, 100.0])
+    out = {}
+    for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
+                               ("cg", ahom.FP64, ahom.SCHEME_CG)):
+        S = solver(P, kv, ph, precision=prec, tol=1e-6, max_iter=5000, scheme=scheme)
+        out[name] = S.effective_conductivity(allow=(ahom.AHOM_OK,))
+        del S
+    Kb = out["fp64"][0]
+    print({k: list(v[1]) for k, v in out.items()}, flush=True)
+    for name in ("fp32", "cg"):
+        assert np.abs(out[name][0] - Kb).max() < 1e-5 * np.abs(Kb).max()
+    assert max(out["cg"][1]) * 3 < min(out["fp64"][1])
+
+
+def test_conductivity_fast_path_matches_generic(monkeypatch):
+    M = [[64, 0, 0], [0, 64, 0], [0, 0, 128]]
+    say("conductivity fast-vs-generic", M)
+    P = ahom.Pattern(M)
+    ph = rnd_phase(53, 3)(P.points(), P.m)
+    gb = np.array([[1.0, 0.0, 0.0], [0.2, -0.5, 0.7]])
+    outs = []
+    for generic in ("1", "0"):
+        monkeypatch.setenv("AHOM_GENERIC_ONLY", generic)
+        S = solver(P, KV, ph, tol=0.0, max_iter=4)
+        outs.append(S.solve_conductivity(gb, want_field=True))
+        del S
+    assert rel_err(outs[1]["field"], outs[0]["field"]) < 1e-12
+    assert np.allclose(outs[1]["resid"], outs[0]["resid"], rtol=1e-10)
+
+
+def test_conductivity_argument_errors():
+    P = ahom.Pattern([[8, 0], [0, 8]])
+    say("conductivity errors")
+    S = ahom.Solver(P, physics=ahom.CONDUCTIVITY)
+    with pytest.raises(ahom.AhomError) as ex:
+        S.set_conductivity([1.0, -2.0], np.zeros(P.m, np.uint8))
+    assert ex.value.code == ahom.AHOM_E_MATERIAL
+    with pytest.raises(ahom.AhomError) as ex:
+        S.set_material([[1.0, 1.0]], np.zeros(P.m, np.uint8))
+    assert ex.value.code == ahom.AHOM_E_ARG
+    S.set_conductivity([1.0, 2.0], (np.arange(P.m) % 2).astype(np.uint8))
+    with pytest.raises(ahom.AhomError) as ex:
+        S.solve(np.eye(3)[None])
+    assert ex.value.code == ahom.AHOM_E_ARG
+    E = ahom.Solver(P)
+    with pytest.raises(ahom.AhomError) as ex:
+        E.set_conductivity([1.0], np.zeros(P.m, np.uint8))
+    assert ex.value.code == ahom.AHOM_E_ARG
