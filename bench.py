@@ -272,27 +272,99 @@ def rank1_workload(ahom, steps=20):
     geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
     ph = synth.hashin_phase(P.points(), P.m, geom)
     lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
-    out = _throughput(ahom, P, lame, ph, steps, "rank-1 2^21")
+    out = _throughput(ahom, P, lame, ph, steps, "rank-1 2^21", roofline=True)
     return dict(workload="Hashin structure on the rank-1 lattice det M = 2^21, 6 loads", M=M.tolist(), **out)
 
 
-def _throughput(ahom, P, lame, ph, steps, label):
-    """FP64 and FP32 updates/s of `steps` fixed iterations with the 6 Mandel loads."""
-    loads = mandel_loads()
+def pass_roofline(S, n_iter=5):
+    """Per-pass device time (HIP events around every pass on the solver's stream,
+    profiling mode over n_iter iterations) against the algorithmic bytes of
+    each pass; the dominant pass gives the roofline record."""
+    import numpy as np
+    ms, by = S.pass_times(n_iter)
+    n_ax = (len(ms) - 3) // 2
+    names = ["k_real"] + ["k_axis_fwd"] * n_ax + ["k_spec"] + ["k_axis_inv"] * n_ax + ["k_reduce"]
+    dom = int(np.argmax(ms))
+    achieved = by[dom] / (ms[dom] * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), kernel=names[dom], kernel_ms=round(float(ms[dom]), 4),
+                algorithmic_bytes=float(by[dom]),
+                all_passes={f"{i}:{n}": dict(ms=round(float(t), 4), GBs=round(float(b / (t * 1e-3) / 1e9), 1),
+                                             frac=round(float(b / (t * 1e-3) / 1e9) / HBM_PEAK_GBS, 4))
+                            for i, (n, t, b) in enumerate(zip(names, ms, by))})
+
+
+def _throughput(ahom, P, lame, ph, steps, label, precs=None, physics=0, loads=None, roofline=False):
+    """updates/s of `steps` fixed iterations (6 Mandel loads, or the given
+    loads), FP64 and FP32; with roofline, the per-pass record of pass_roofline."""
+    precs = precs or (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED))
+    if loads is None:
+        loads = mandel_loads()
     out = {}
-    for name, prec in (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED)):
-        Sw = ahom.Solver(P, precision=prec, tol=0.0, max_iter=2, check_period=3)
-        Sw.set_material(lame, ph)
-        Sw.solve(loads)
+
+    def make(prec, max_iter, check):
+        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=max_iter, check_period=check, physics=physics)
+        if physics == ahom.CONDUCTIVITY:
+            S.set_conductivity(lame, ph)
+        else:
+            S.set_material(lame, ph)
+        return S
+
+    def run(S):
+        return S.solve_conductivity(loads) if physics == ahom.CONDUCTIVITY else S.solve(loads)
+
+    for name, prec in precs:
+        Sw = make(prec, 2, 3)
+        run(Sw)
         del Sw
-        S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=steps - 1, check_period=steps)
-        S.set_material(lame, ph)
+        S = make(prec, steps - 1, steps)
         t0 = time.perf_counter()
-        S.solve(loads)
+        run(S)
         ms = (time.perf_counter() - t0) * 1e3 / steps
         out[name] = dict(value=round(P.m * loads.shape[0] / (ms * 1e-3), 1), ms_per_step=round(ms, 4))
+        if roofline:
+            out[name]["roofline"] = pass_roofline(S)
         print(f"[bench] {label} {name}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
         del S
+    return out
+
+
+def spheres_inputs(ahom, n):
+    import numpy as np
+    import synth
+    c, r = synth.spheres_rsa(seed=3)
+    P = ahom.Pattern([[n, 0, 0], [0, n, 0], [0, 0, n]])
+    ph = synth.spheres_phase(P.points(), P.m, c, r)
+    return P, ph, np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
+
+
+def conductivity_workload(ahom, n=128, steps=20, ttt=True):
+    """The conductivity problem (Sec. 3) on the Hashin structure of the main
+    workload: conductivities core 10, coating 0.5, matrix 1 on diag(n,n,n),
+    the 3 unit mean gradients together.  Fixed-iteration throughput with the
+    per-pass roofline (FP64, FP32), and the time to r <= 1e-6 of the Basic
+    Scheme (FP64, FP32 with restarts) and of CG (FP64)."""
+    import numpy as np
+    P, ph, _, g = workload(n)
+    kv = np.array([10.0, 0.5, 1.0])
+    loads = np.eye(3)
+    out = dict(workload=f"conductivity, Hashin structure on diag({n},{n},{n}), k = (10, 0.5, 1), 3 unit gradients")
+    out.update(_throughput(ahom, P, kv, ph, steps, f"conductivity {n}^3", physics=ahom.CONDUCTIVITY, loads=loads,
+                           roofline=True))
+    if ttt:
+        t = {}
+        for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
+                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+            S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=3000, check_period=16, resid_period=4, scheme=scheme,
+                            physics=ahom.CONDUCTIVITY)
+            S.set_conductivity(kv, ph)
+            Ke, it = S.effective_conductivity()
+            ms, _ = S.last_timing()
+            t[name] = dict(ms=round(ms, 2), iters=[int(v) for v in it], keff_diag=[round(float(v), 6) for v in np.diag(Ke)])
+            print(f"[bench] conductivity time-to-1e-6 {name}: {ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
+            del S
+        t["speedup_cg_vs_fp64"] = round(t["fp64"]["ms"] / t["cg_fp64"]["ms"], 3)
+        out["time_to_1e6"] = t
     return out
 
 
@@ -322,12 +394,8 @@ def precision_workload(ahom, n=256):
     FP64 scheme and of FP32 with FP64 restarts (device time, inputs resident),
     and the per-entry C_eff difference between the two."""
     import numpy as np
-    import synth
-    M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
-    c, r = synth.spheres_rsa(seed=3)
-    P = ahom.Pattern(M)
-    ph = synth.spheres_phase(P.points(), P.m, c, r)
-    lame = np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
+    P, ph, lame = spheres_inputs(ahom, n)
+    thr = _throughput(ahom, P, lame, ph, 10, f"spheres {n}^3", roofline=True)
     out = {}
     Cs = {}
     for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
@@ -345,7 +413,7 @@ def precision_workload(ahom, n=256):
     err = np.abs(Cs["fp32"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
     err_cg = np.abs(Cs["cg_fp64"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
     return dict(workload=f"spheres diag({n},{n},{n}), vf 0.3, contrast 100, 6 loads, tol 1e-6",
-                fp64=out["fp64"], fp32=out["fp32"], cg_fp64=out["cg_fp64"],
+                throughput=thr, fp64=out["fp64"], fp32=out["fp32"], cg_fp64=out["cg_fp64"],
                 speedup_fp32_vs_fp64=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
                 speedup_cg_vs_fp64=round(out["fp64"]["ms"] / out["cg_fp64"]["ms"], 3),
                 ceff_max_entry_err_fp32_vs_fp64_over_max_abs=float(err.max()),
@@ -384,27 +452,39 @@ def learned_workload(ahom, ntrain, steps, n=64, ntest=4):
     print(f"[bench] learned: {steps} steps in {t_train:.1f} s, loss {losses[:10].mean():.3f} -> {losses[-10:].mean():.3f}",
           file=sys.stderr, flush=True)
     rows = []
+    kept = 0
     for s in range(200000, 200000 + ntest):
         ph, lame, lam0, mu0 = member(s)
         row = {}
-        for name, prec, guess in (("fp64", ahom.FP64, False), ("fp32", ahom.FP32_MIXED, False), ("fp32_guess", ahom.FP32_MIXED, True)):
-            S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4)
+        for name, prec, guess, scheme in (("fp64", ahom.FP64, False, ahom.SCHEME_BASIC),
+                                          ("fp32", ahom.FP32_MIXED, False, ahom.SCHEME_BASIC),
+                                          ("fp32_guess", ahom.FP32_MIXED, True, ahom.SCHEME_BASIC),
+                                          ("cg_fp64", ahom.FP64, False, ahom.SCHEME_CG)):
+            S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4, scheme=scheme,
+                            guess_probe=17 if guess else 0)
             S.set_material(lame, ph)
-            S.solve(loads[:1])                       # warm (tuning)
             d_init = ahom.DeviceArray((6, 6, P.m), np.float64) if guess else None
+            if guess:
+                g.infer(ph, lame, lam0, mu0, loads, out=d_init)
+            S.solve_device(loads, init=d_init)       # warm: tuning and every buffer of the 6-load solve
             t0 = time.perf_counter()
             if guess:
                 g.infer(ph, lame, lam0, mu0, loads, out=d_init)     # device to device, no host copies
             o = S.solve_device(loads, init=d_init)
             row[name] = dict(ms=round((time.perf_counter() - t0) * 1e3, 2), iters=float(o["iters"].mean()))
+            if guess:
+                kept += int(S.last_starts(6).sum())
+            del S
         rows.append(row)
     mean = {k: float(np.mean([r[k]["ms"] for r in rows])) for k in rows[0]}
     its = {k: float(np.mean([r[k]["iters"] for r in rows])) for k in rows[0]}
     return dict(n=n, train_solves=ntrain, steps=steps, data_s=round(t_data, 1), train_s=round(t_train, 1),
                 loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean()),
-                held_out=ntest, mean_ms=mean, mean_iters=its,
+                held_out=ntest, mean_ms=mean, mean_iters=its, guess_probe=17,
+                guess_kept_loads=f"{kept}/{6 * ntest}",
                 speedup_guess_fp32_vs_fp64=round(mean["fp64"] / mean["fp32_guess"], 3),
-                speedup_fp32_vs_fp64=round(mean["fp64"] / mean["fp32"], 3))
+                speedup_fp32_vs_fp64=round(mean["fp64"] / mean["fp32"], 3),
+                speedup_cg_fp64_vs_fp64=round(mean["fp64"] / mean["cg_fp64"], 3))
 
 
 def main():
@@ -428,6 +508,11 @@ def main():
                     help="residual evaluated every k iterations in the time-to-tolerance solves")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
+    ap.add_argument("--no-cond", action="store_true", help="skip the conductivity workload")
+    ap.add_argument("--leg", choices=["hashin128", "spheres256", "rank1", "cond128"],
+                    help="profiling runs: only the fixed-iteration throughput of one workload (--steps iterations, "
+                         "FP64 then FP32 unless --fp64-only or --fp32-only), one JSON line, then exit")
+    ap.add_argument("--fp32-only", action="store_true", help="with --leg: FP32 only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -446,6 +531,34 @@ def main():
         for _ in range(3):
             dst.copy_from(src)
         print(json.dumps(dict(calib_copy_bytes=n, dispatches=3)))
+        return
+
+    if args.leg:
+        precs = (("fp64", ahom.FP64), ("fp32", ahom.FP32_MIXED))
+        if args.fp64_only:
+            precs = precs[:1]
+        if args.fp32_only:
+            precs = precs[1:]
+        if args.leg == "hashin128":
+            P, ph, lame, _ = workload(128)
+            res = _throughput(ahom, P, lame, ph, args.steps, "hashin 128^3", precs=precs)
+        elif args.leg == "spheres256":
+            P, ph, lame = spheres_inputs(ahom, 256)
+            res = _throughput(ahom, P, lame, ph, args.steps, "spheres 256^3", precs=precs)
+        elif args.leg == "rank1":
+            g = json.load(open(os.path.join(ROOT, "tests", "golden", "hashin_c2.json")))
+            M = np.array(json.load(open(os.path.join(ROOT, "tests", "golden", "rank1_c2.json")))["M"], dtype=np.int64)
+            P = ahom.Pattern(M)
+            import synth
+            geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
+            ph = synth.hashin_phase(P.points(), P.m, geom)
+            lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
+            res = _throughput(ahom, P, lame, ph, args.steps, "rank-1 2^21", precs=precs)
+        else:
+            P, ph, _, _ = workload(128)
+            res = _throughput(ahom, P, np.array([10.0, 0.5, 1.0]), ph, args.steps, "conductivity 128^3", precs=precs,
+                              physics=ahom.CONDUCTIVITY, loads=np.eye(3))
+        print(json.dumps(dict(leg=args.leg, steps=args.steps, **res)))
         return
 
     print(f"[bench] building workload diag({args.size},{args.size},{args.size})", file=sys.stderr, flush=True)
@@ -527,6 +640,9 @@ def main():
     sweep = None
     if not args.no_sweep and not args.no_batch:
         sweep = sweep_workload(ahom)
+    conductivity = None
+    if not args.no_cond and not args.fp64_only:
+        conductivity = conductivity_workload(ahom, args.size, ttt=not args.no_ttt)
     learned = None
     if not args.no_learned and not args.no_ttt and not args.fp64_only:
         learned = learned_workload(ahom, args.learned_train, args.learned_steps)
@@ -553,6 +669,7 @@ def main():
         paper_5_2=subsampling,
         batch_2d=batch,
         shear_sweep=sweep,
+        conductivity_128=conductivity,
         learned_guess=learned,
     )
     print(json.dumps(line))

@@ -108,6 +108,17 @@ typedef struct ahom_config {
                            ahom_solver_set_conductivity, solve with ahom_solve_conductivity /
                            ahom_effective_conductivity.  Single-pattern solver; both schemes,
                            both precisions (FP32 restarts as for elasticity). */
+    int guess_probe;    /* with an initial guess (ahom_solve init): 0 (default) starts every load
+                           from it.  k > 0: the plain start eps_bar runs beside the guessed one
+                           (as n_load more loads in the same launches) for the first k updates;
+                           per load the start that met the tolerance first is kept (with FP32
+                           restarts: the first stage's tolerance), or if neither has, the guessed
+                           start if it is predicted to reach tol in
+                           at most 90 % of the plain start's updates (from the contraction of the
+                           evaluated residuals over the second half of the probe); else the plain
+                           start's iterate,
+                           traction and history are kept (the fallback to a zero guess).
+                           ahom_solver_last_starts reports the choice.  0 <= k <= max_iter. */
 } ahom_config;
 
 #define AHOM_STOP_RESIDUAL 0
@@ -295,6 +306,13 @@ int ahom_effective_conductivity(ahom_solver* s, double* Keff, int* iters);
  * solver's stream), and the number of iterations enqueued.
  */
 int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* iterations_enqueued);
+
+/*
+ * Start kept per load in the last ahom_solve (ahom_config.guess_probe):
+ * which[l] = 1 for the initial guess, 0 for the plain start eps_bar (also 0
+ * for every load of a solve without init).  Writes min(cap, n_load) ints.
+ */
+int ahom_solver_last_starts(const ahom_solver* s, int* which, int cap);
 
 /*
  * Number of FP64 defect-correction restarts in the last ahom_solve (0 for

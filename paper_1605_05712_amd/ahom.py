@@ -50,7 +50,7 @@ EXPORTS = [
     "ahom_pattern_points", "ahom_pattern_freqs", "ahom_dft", "ahom_dft_noalloc", "ahom_solver_create", "ahom_solver_destroy",
     "ahom_solver_set_material", "ahom_solver_set_stiffness_field", "ahom_solver_set_reference", "ahom_solve",
     "ahom_solver_set_conductivity", "ahom_solver_set_reference_conductivity", "ahom_solve_conductivity",
-    "ahom_effective_conductivity",
+    "ahom_effective_conductivity", "ahom_solver_last_starts",
     "ahom_effective_stiffness", "ahom_solver_last_timing", "ahom_solver_last_restarts", "ahom_solver_history",
     "ahom_solver_pass_times", "ahom_solver_cauchy_history", "ahom_batch_create", "ahom_batch_create_transformed",
     "ahom_batch_destroy", "ahom_batch_member_info",
@@ -66,7 +66,8 @@ EXPORTS = [
 class Config(ct.Structure):
     _fields_ = [("precision", ct.c_int), ("tol", ct.c_double), ("max_iter", ct.c_int),
                 ("check_period", ct.c_int), ("nyquist", ct.c_int), ("stream", ct.c_void_p),
-                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int), ("scheme", ct.c_int), ("physics", ct.c_int)]
+                ("resid_period", ct.c_int), ("refine", ct.c_double), ("stop_rule", ct.c_int), ("scheme", ct.c_int), ("physics", ct.c_int),
+                ("guess_probe", ct.c_int)]
 
 
 _P = ct.c_void_p
@@ -99,6 +100,7 @@ _lib.ahom_solve_conductivity.argtypes = [_P, ct.c_int, _dp, _P, _ip, _dp, _dp, c
 _lib.ahom_effective_conductivity.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_timing.argtypes = [_P, _dp, _ip]
 _lib.ahom_solver_last_restarts.argtypes = [_P, _ip]
+_lib.ahom_solver_last_starts.argtypes = [_P, _ip, ct.c_int]
 _lib.ahom_solver_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_cauchy_history.argtypes = [_P, ct.c_int, _dp, ct.c_int, _ip]
 _lib.ahom_solver_pass_times.argtypes = [_P, ct.c_int, _dp, _dp, ct.c_int, _ip]
@@ -290,15 +292,16 @@ class Solver:
     """Algorithm 1 on a pattern (device buffers owned by the library)."""
 
     def __init__(self, pattern, precision=FP64, tol=1e-8, max_iter=1000, check_period=8, stream=None, resid_period=1,
-                 refine=0.0, stop_rule=0, scheme=SCHEME_BASIC, physics=ELASTICITY):
+                 refine=0.0, stop_rule=0, scheme=SCHEME_BASIC, physics=ELASTICITY, guess_probe=0):
         """stop_rule: STOP_RESIDUAL (r(n) <= tol) or STOP_CAUCHY (the Sec. 5.2 criterion);
         scheme: SCHEME_BASIC (Algorithm 1) or SCHEME_CG (conjugate gradients);
-        physics: ELASTICITY or CONDUCTIVITY."""
+        physics: ELASTICITY or CONDUCTIVITY; guess_probe: updates run from both the
+        initial guess and the plain start before keeping the better one (0: off)."""
         self.pattern = pattern
         self.physics = physics
         self.ncomp = (6 if pattern.d == 3 else 3) if physics == ELASTICITY else pattern.d
         self.cfg = Config(precision, tol, max_iter, check_period, NYQUIST_HERMITIAN, stream, resid_period, refine,
-                          stop_rule, scheme, physics)
+                          stop_rule, scheme, physics, guess_probe)
         h = _P()
         _check(_lib.ahom_solver_create(pattern._h, ct.byref(self.cfg), ct.byref(h)))
         self._h = h
@@ -395,6 +398,12 @@ class Solver:
         enq = ct.c_int()
         _check(_lib.ahom_solver_last_timing(self._h, ct.byref(ms), ct.byref(enq)))
         return ms.value, enq.value
+
+    def last_starts(self, n):
+        """Per load of the last solve: 1 if the initial guess was kept, 0 for the plain start."""
+        w = np.zeros(n, np.int32)
+        _check(_lib.ahom_solver_last_starts(self._h, _ptr(w, ct.c_int), n))
+        return w
 
     def last_restarts(self):
         """FP64 defect-correction restarts of the last solve."""

@@ -260,6 +260,7 @@ struct ahom_solver {
     int last_enqueued = 0;
     int last_nload = 0;
     int last_restarts = 0;
+    std::vector<int> last_start;       // per load of the last solve: 1 guessed start kept, 0 plain start
 
     size_t es() const { return prec == AHOM_FP64 ? 16 : 8; }
 
@@ -782,6 +783,7 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
     s->last_enqueued = enq;
     s->last_nload = n_load;
     s->last_restarts = 0;
+    s->last_start.assign(n_load, 0);
     if (strain_out) {
         if (mem_flags != AHOM_MEM_DEVICE && (rc = s->ensure_real_staging())) return rc;
         RealArgs ra = s->real_args(REAL_TO_REAL);
@@ -1024,6 +1026,7 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
         return fail(AHOM_E_ARG, "the Cauchy stop rule in FP32 needs refine < 0 (no restarts)");
     if (cfg->scheme != AHOM_SCHEME_BASIC && cfg->scheme != AHOM_SCHEME_CG) return fail(AHOM_E_ARG, "unknown scheme");
     if (cfg->physics != AHOM_ELASTICITY && cfg->physics != AHOM_CONDUCTIVITY) return fail(AHOM_E_ARG, "unknown physics");
+    if (cfg->guess_probe < 0 || cfg->guess_probe > cfg->max_iter) return fail(AHOM_E_ARG, "guess_probe must be in [0, max_iter]");
     if (cfg->scheme == AHOM_SCHEME_CG && (cfg->precision != AHOM_FP64 || cfg->stop_rule != AHOM_STOP_RESIDUAL))
         return fail(AHOM_E_ARG, "the conjugate-gradient scheme runs in AHOM_FP64 with the residual stop rule");
     return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
@@ -1172,7 +1175,11 @@ int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, 
         if (init) return fail(AHOM_E_ARG, "the conjugate-gradient scheme starts from eps_bar (no init)");
         return solve_cg(s, n_load, ebc, strain_out, iters, resid, mean_out, mem_flags);
     }
-    int rc = s->ensure_capacity(n_load);
+    // guess probe: the plain start runs beside the guessed one as loads
+    // n_load .. 2 n_load - 1 for the first guess_probe iterations
+    const bool probe = init && s->cfg.guess_probe > 0;
+    const int nl2 = probe ? 2 * n_load : n_load;
+    int rc = s->ensure_capacity(nl2);
     if (rc) return rc;
     s->spec_toff = nullptr;
     s->spec_dout = s->spec_dneg = nullptr;
@@ -1186,19 +1193,21 @@ int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, 
     if (refine) s->cur_tol = std::max(s->cfg.tol, s->cfg.refine);
     // set up the FP64 companion ahead of the timed region when a restart is expected
     if (refine && s->cfg.tol < s->cur_tol && (rc = ensure_ref64(s, n_load))) return rc;
-    const std::vector<double> eb(ebc, ebc + (size_t)n_load * nc);
+    std::vector<double> eb(ebc, ebc + (size_t)n_load * nc);
+    if (probe) eb.insert(eb.end(), ebc, ebc + (size_t)n_load * nc);
     HIPCHK(hipMemcpyAsync(s->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
     // denominator of the Cauchy measure: |eps(0)| = sqrt(m) |eps_bar|_F for the
     // plain start (kept with a user initial guess)
-    std::vector<double> norm0(n_load);
-    for (int l = 0; l < n_load; ++l) {
+    std::vector<double> norm0(nl2);
+    for (int l = 0; l < nl2; ++l) {
         double f = 0.0;
         for (int c = 0; c < nc; ++c) f += field_weight(s->phys, s->dim, c) * eb[(size_t)l * nc + c] * eb[(size_t)l * nc + c];
         norm0[l] = std::sqrt((double)P.m * f);
     }
     HIPCHK(hipMemcpyAsync(s->d_norm0, norm0.data(), norm0.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
-    if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    if (ahom_launch_reset(s->d_st, nl2, st)) return fail(AHOM_E_DEVICE, "reset");
+    if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)nl2 * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    s->last_start.assign(n_load, init ? 1 : 0);
     auto fill = [&](void* buf) -> int {
         FillArgs f{};
         f.buf = buf;
@@ -1238,9 +1247,79 @@ int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, 
         sa.lam0_init = s->lam0;
         if (ahom_launch_spec_init(s->prec, s->dim, sa, s->g_spec.nwg, n_load, s->g_spec.lds, st))
             return fail(AHOM_E_DEVICE, "launch init traction");
+        if (probe) {   // the plain starts of the probe
+            FillArgs f{};
+            f.buf = static_cast<char*>(s->d_buf0) + (size_t)n_load * nc * P.S * s->es();
+            f.eps_bar = s->d_epsbar + (size_t)n_load * nc;
+            f.S = P.S;
+            f.row = P.S / P.ax[0].slen;
+            f.nfield = nc;
+            if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+        }
     }
     HIPCHK(hipEventRecord(s->ev0, st));
     int enq = 0;
+    if (probe) {
+        // Both starts for guess_probe iterations in the same launches; per load
+        // keep the start that met the tolerance (of the first FP32 stage with
+        // restarts) first, or if neither has, the guessed start if
+        // it is predicted to reach tol in at most 90 % of the plain start's
+        // updates; for the plain start carry its state (fields, traction,
+        // history) over.
+        for (int i = 0; i < s->cfg.guess_probe; ++i) {
+            if ((rc = s->enqueue_iteration(nl2))) return rc;
+            ++enq;
+        }
+        const int kp = s->cfg.guess_probe;
+        std::vector<double> hh((size_t)nl2 * s->hist_cap);
+        HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, nl2 * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hh.data(), s->d_hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        // updates still needed from a start, predicted from its residuals over the
+        // probe's second half: the last evaluated r(i2) and r(i1) with i1 near
+        // i2 / 2 give the contraction per update rho, and log(r(i2) / tol) /
+        // log(1 / rho) more updates reach tol
+        auto predicted = [&](int load) -> double {
+            const double* h = hh.data() + (size_t)load * s->hist_cap;
+            int i2 = -1, i1 = -1;
+            for (int i = std::min(kp, s->hist_cap) - 1; i >= 0; --i)
+                if (h[i] > 0.0) { i2 = i; break; }
+            for (int i = 0; i < i2; ++i)
+                if (h[i] > 0.0 && 2 * i >= i2) { i1 = i; break; }
+            if (i2 < 0) return 1e300;
+            if (h[i2] <= s->cfg.tol) return i2;
+            if (i1 < 0 || !(h[i2] < h[i1])) return 1e300;
+            const double rate = std::log(h[i1] / h[i2]) / (double)(i2 - i1);
+            return i2 + std::log(h[i2] / s->cfg.tol) / rate;
+        };
+        const size_t fbytes = (size_t)nc * P.S * s->es(), tbytes = (size_t)s->nt * P.S * s->es();
+        for (int l = 0; l < n_load; ++l) {
+            const LoadState& g = s->h_st[l];
+            const LoadState& z = s->h_st[l + n_load];
+            const bool gc = g.done && g.status == 0, zc = z.done && z.status == 0;
+            bool keep_guess;
+            if (gc && zc) keep_guess = g.iter <= z.iter;     // both met the (stage) tolerance: the earlier one
+            else if (gc) keep_guess = true;
+            else if (zc) keep_guess = false;
+            else if (g.status == 2) keep_guess = false;
+            else keep_guess = predicted(l) <= 0.9 * predicted(l + n_load);   // a guess must promise 10 % fewer updates
+            s->last_start[l] = keep_guess ? 1 : 0;
+            if (keep_guess) continue;
+            char* b0 = static_cast<char*>(s->d_buf0);
+            char* b1 = static_cast<char*>(s->d_buf1);
+            char* tb = static_cast<char*>(s->d_tbuf);
+            HIPCHK(hipMemcpyAsync(b0 + l * fbytes, b0 + (l + n_load) * fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(b1 + l * fbytes, b1 + (l + n_load) * fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(tb + l * tbytes, tb + (l + n_load) * tbytes, tbytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->d_hist + (size_t)l * s->hist_cap, s->d_hist + (size_t)(l + n_load) * s->hist_cap,
+                                  s->hist_cap * sizeof(double), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->d_chist + (size_t)l * s->hist_cap, s->d_chist + (size_t)(l + n_load) * s->hist_cap,
+                                  s->hist_cap * sizeof(double), hipMemcpyDeviceToDevice, st));
+            s->h_st[l] = z;
+        }
+        HIPCHK(hipMemcpyAsync(s->d_st, s->h_st, n_load * sizeof(LoadState), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     // iterate until every load case has stopped (device-side loop control);
     // the host reads the load states every check_period iterations
     auto run_stage = [&]() -> int {
@@ -1285,7 +1364,7 @@ int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, 
         if (stop || !need) break;
         if ((rc = ensure_ref64(s, n_load))) return rc;
         ahom_solver* r = s->ref64;
-        HIPCHK(hipMemcpyAsync(r->d_epsbar, eb.data(), eb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(r->d_epsbar, eb.data(), (size_t)n_load * nc * sizeof(double), hipMemcpyHostToDevice, st));
         GatherArgs g{};
         g.out = static_cast<double2*>(r->d_buf0);
         g.base = nrestart ? static_cast<const double2*>(r->d_buf1) : nullptr;
@@ -1530,6 +1609,13 @@ int ahom_solver_last_timing(const ahom_solver* s, double* ms, int* enq) {
     if (!s) return fail(AHOM_E_ARG, "null solver");
     if (ms) *ms = s->last_ms;
     if (enq) *enq = s->last_enqueued;
+    return AHOM_OK;
+}
+
+int ahom_solver_last_starts(const ahom_solver* s, int* which, int cap) {
+    if (!s || !which || cap < 1) return fail(AHOM_E_ARG, "bad arguments");
+    const int n = std::min<int>(cap, (int)s->last_start.size());
+    for (int l = 0; l < n; ++l) which[l] = s->last_start[l];
     return AHOM_OK;
 }
 
