@@ -13,12 +13,20 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/ahom.h"
 #include "ahom_internal.h"
 #include "ahom_kernels.h"
 
 namespace {
 thread_local std::string g_err;
+
+// a roctx range over the enclosing scope (shown by rocprofv3 --marker-trace)
+struct RoctxRange {
+    explicit RoctxRange(const char* name) { roctxRangePushA(name); }
+    ~RoctxRange() { roctxRangePop(); }
+};
 
 constexpr int kLmax = 256;          // longest transform held by one pass
 constexpr size_t kLdsCap = 150 * 1024;
@@ -1168,6 +1176,7 @@ namespace {
 // (nullable) receives the mean stress (flux) components the same way.
 int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, void* strain_out,
                int* iters, double* resid, double* mean_out, int mem_flags) {
+    RoctxRange range(s->cg ? "ahom_solve (conjugate gradients)" : "ahom_solve (Basic Scheme)");
     if (!s->has_material) return fail(AHOM_E_MATERIAL, "no material set");
     if (init && s->cfg.stop_rule == AHOM_STOP_CAUCHY)
         return fail(AHOM_E_ARG, "the Cauchy stop rule measures against sqrt(m) |eps_bar|, not a guessed start: no init");

@@ -5,6 +5,7 @@
 // (member, load) pair is an item with its own state buffers.  The plan and
 // tile widths of each distinct Smith shape are picked by timing the
 // candidates on the device (per-process cache).
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -607,6 +608,8 @@ int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double m
 
 int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iters, double* resid, double* mean_stress,
                      int* status, int use_graph) {
+    roctxRangePushA("ahom_batch_solve");
+    struct PopRange { ~PopRange() { roctxRangePop(); } } pop_range;
     if (!b || !eps_bar || n_load < 1) return bfail(AHOM_E_ARG, "bad batch solve arguments");
     for (size_t i = 0; i < b->mem.size(); ++i)
         if (!b->mem[i].has_material) return bfail(AHOM_E_MATERIAL, "member " + std::to_string(i) + ": no material set");
