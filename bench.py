@@ -235,6 +235,10 @@ def subsampling_workload(ahom):
     import synth
     paper = {"a": (94, 41.2), "b": (9, 4.5), "c": (89, 46.1)}
     lame = np.array(synth.LAMINATE_LAME)
+    # reference 1.1 x the mean of the extreme phases: with the mean itself the
+    # Basic Scheme solves M_b and M_c exactly in one update, which times nothing
+    lam0 = 0.55 * (lame[:, 0].min() + lame[:, 0].max())
+    mu0 = 0.55 * (lame[:, 1].min() + lame[:, 1].max())
     e11 = np.zeros((1, 3, 3))
     e11[0, 0, 0] = 1.0
     out = {}
@@ -245,6 +249,7 @@ def subsampling_workload(ahom):
         for rule, key in ((ahom.STOP_RESIDUAL, "resid"), (ahom.STOP_CAUCHY, "cauchy")):
             S = ahom.Solver(P, precision=ahom.FP64, tol=1e-9, max_iter=3000, stop_rule=rule)
             S.set_material(lame, ph)
+            S.set_reference(lam0, mu0)
             S.solve(e11)
             res = S.solve(e11)
             ms, _ = S.last_timing()
@@ -255,7 +260,8 @@ def subsampling_workload(ahom):
         out[f"M_{name}"] = row
         print(f"[bench] subsampling M_{name}: {row['iters_cauchy_1e9']} updates to the Cauchy stop, "
               f"{row['device_ms_cauchy']:.2f} ms", file=sys.stderr, flush=True)
-    return dict(workload="Sec. 5.2 subsampling of the laminate, FP64", paper_hardware=(
+    return dict(workload="Sec. 5.2 subsampling of the laminate, FP64, reference 1.1 x the phase mean",
+                paper_hardware=(
         "MATLAB R2016a + MPAWL over fftn, MacBook Pro Core i5 2.6 GHz (context only)"), **out)
 
 

@@ -310,16 +310,41 @@ __device__ __forceinline__ int64_t mod_fast(int64_t x, int64_t d) {
     return r;
 }
 
-template <typename C>
-__device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
+__device__ __forceinline__ double2 split_tw64(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
     int64_t hi, lo;
     divmod_fast(j, ax.spB, hi, lo);
     const double2 a = tw64[ax.sp_off1 + lo];
     const double2 b = tw64[ax.sp_off2 + hi];
-    const double2 w = cmul(a, b);
+    return cmul(a, b);
+}
+
+template <typename C>
+__device__ __forceinline__ C split_twiddle(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t j) {
+    const double2 w = split_tw64(ax, tw64, j);
     using T = decltype(C{}.x);
     return C{(T)w.x, (T)w.y};
 }
+
+// Four-step twiddles W^(Q l) along the positions l = l0, l0 + dl, ... that
+// one thread visits in a column of fixed Q: the first one and the step from
+// the two-level FP64 table, then a running FP64 product (one complex
+// multiply per element instead of two table reads and an index division;
+// the rounding grows by ~1e-16 per step over at most a few tens of steps).
+struct TwiddleWalk {
+    double2 w, step;
+    __device__ __forceinline__ void start(const AxisDesc& ax, const double2* __restrict__ tw64, int64_t Q, int64_t l0,
+                                          int64_t dl) {
+        w = split_tw64(ax, tw64, Q * l0);
+        step = split_tw64(ax, tw64, Q * dl);
+    }
+    // the twiddle of the current position, then advance
+    template <typename C> __device__ __forceinline__ C next() {
+        using T = decltype(C{}.x);
+        const C out = C{(T)w.x, (T)w.y};
+        w = cmul(w, step);
+        return out;
+    }
+};
 
 template <int DIM, int PH = PHYS_ELASTIC> using Comp = Fields<DIM, PH>;
 
@@ -531,14 +556,18 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::NP, V>::THREADS)) kf
     };
 
     // packed full spectra Z_p = A + i B from the half spectra in pre[]
+    // thread tid visits column j = tid % NC at rows k = tid / NC + q TH / NC
+    static_assert(TH % NC == 0, "a thread keeps its column");
+    TwiddleWalk walk;
     auto pack = [&](const Tile& x) __attribute__((always_inline)) {
+        if (ax.split) walk.start(ax, a.tw64, div_fast(x.c0 + tid % NC, ax.qdiv), tid / NC, TH / NC);
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
             const int k = e / NC, j = e % NC;
-            if (e >= H * NC || j >= x.ncol) return;
             C w = C{(T)1, (T)0};
-            if (ax.split) w = split_twiddle<C>(ax, a.tw64, div_fast(x.c0 + j, ax.qdiv) * (int64_t)k);
+            if (ax.split) w = walk.next<C>();
+            if (e >= H * NC || j >= x.ncol) return;
             sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
                 constexpr int p = pc;
                 C A = pre[q][2 * p];
@@ -647,13 +676,14 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::NP, V>::THREADS)) kf
     // half spectra of the transformed tile into out[]
     C out[EPT][NCOMP];
     auto unpack = [&](const Tile& x) __attribute__((always_inline)) {
+        if (ax.split) walk.start(ax, a.tw64, div_fast(x.c0 + tid % NC, ax.qdiv), tid / NC, TH / NC);
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
             const bool ok = e < H * NC && e % NC < x.ncol;
             const int k = ok ? e / NC : 0, j = e % NC;
             C w = C{(T)1, (T)0};
-            if (ax.split && ok) w = split_twiddle<C>(ax, a.tw64, div_fast(x.c0 + j, ax.qdiv) * (int64_t)k);
+            if (ax.split) w = walk.next<C>();
             const int km = k == 0 ? 0 : L - k;
             sfor<0, NP>([&](auto pc) __attribute__((always_inline)) {
                 constexpr int p = pc;
@@ -1015,16 +1045,25 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
     // of t, and the wait for the next tile's loads never waits for stores
     // issued just before it)
     C out[EPT];
+    // rows of a tile (row-major tiles): thread tid keeps column j = tid % NC
+    // at positions l = tid / NC + q TH / NC, so its four-step twiddles walk
+    static_assert(TH % NC == 0, "a thread keeps its column");
+    const bool walk_ok = ax.split && rowmajor;
+    TwiddleWalk walk;
     auto unpack = [&](int64_t c0, int ncol) __attribute__((always_inline)) {
+        if (DIR < 0 && walk_ok) walk.start(ax, a.tw64, div_fast(mod_fast(c0 + tid % NC, I), ax.qdiv), tid / NC, TH / NC);
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
             int j, l;
             map(e, j, l);
             const bool ok = e < NC * L && j < ncol;
+            C w = C{(T)1, (T)0};
+            if (DIR < 0 && walk_ok) w = walk.next<C>();
             if (!ok) { j = 0; l = 0; }
             C v = X[j * CS + (l ^ lsw<L, C>(j))];
-            if (DIR < 0 && ax.split && ok) v = cmul(v, split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
+            if (DIR < 0 && ax.split && ok)
+                v = cmul(v, walk_ok ? w : split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
             out[q] = v;
         });
     };
@@ -1040,14 +1079,18 @@ __global__ void __launch_bounds__((Geo<T, L, 1, V>::THREADS)) kf_axis(AxisArgs a
         });
     };
     auto pack = [&](int64_t c0, int ncol) __attribute__((always_inline)) {
+        if (DIR > 0 && walk_ok) walk.start(ax, a.tw64, div_fast(mod_fast(c0 + tid % NC, I), ax.qdiv), tid / NC, TH / NC);
         sfor<0, EPT>([&](auto qc) __attribute__((always_inline)) {
             constexpr int q = qc;
             const int e = tid + q * TH;
             int j, l;
             map(e, j, l);
+            C w = C{(T)1, (T)0};
+            if (DIR > 0 && walk_ok) w = walk.next<C>();
             if (e >= NC * L || j >= ncol) return;
             C v = pre[q];
-            if (DIR > 0 && ax.split) v = cmulc(v, split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
+            if (DIR > 0 && ax.split)
+                v = cmulc(v, walk_ok ? w : split_twiddle<C>(ax, a.tw64, div_fast(mod_fast(c0 + j, I), ax.qdiv) * (int64_t)l));
             X[j * CS + (l ^ lsw<L, C>(j))] = v;
         });
     };
