@@ -161,11 +161,13 @@ def test_cg_fast_path_and_variants_match_generic(variant, monkeypatch):
     assert np.allclose(outs[1]["resid"], outs[0]["resid"], rtol=1e-10)
 
 
-def test_cg_spheres_32_contrast_100_matches_oracle_golden():
-    """The precision workload's recipe at 32^3 (contrast 100): CG C_eff at tol 1e-9
-    against the oracle's converged C_eff, with a fraction of the Basic Scheme's updates."""
-    gold = json.load(open(os.path.join(GOLD, "spheres_c3_32.json")))
-    n = gold["n"]
+@pytest.mark.parametrize("n,bound", [(32, 1e-8), (64, 1e-7)])
+def test_cg_spheres_contrast_100_matches_oracle_golden(n, bound):
+    """The precision workload's recipe at 32^3 and 64^3 (contrast 100): CG C_eff at
+    tol 1e-9 against the oracle's converged C_eff (Algorithm 1 to 1e-10 / 1e-8),
+    per entry within bound x max|C|, with a fraction of the Basic Scheme's updates."""
+    gold = json.load(open(os.path.join(GOLD, f"spheres_c3_{n}.json")))
+    assert gold["n"] == n
     M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
     say("cg spheres 32^3", M)
     c, r = synth.spheres_rsa(seed=3)
@@ -176,5 +178,5 @@ def test_cg_spheres_32_contrast_100_matches_oracle_golden():
     Cref = np.array(gold["ceff"])
     err = np.abs(C - Cref) / np.abs(Cref).max()
     print("CG iterations", list(it), "oracle Basic Scheme", gold["iters"], "max err", err.max(), flush=True)
-    assert err.max() < 1e-8
+    assert err.max() < bound
     assert max(it) * 3 < min(gold["iters"])
