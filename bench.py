@@ -426,68 +426,123 @@ def precision_workload(ahom, n=256):
                 ceff_max_entry_diff_cg_vs_fp64_over_max_abs=float(err_cg.max()), volume_fraction=float(ph.mean()))
 
 
-def learned_workload(ahom, ntrain, steps, n=64, ntest=4):
-    """Learned initial guess on 64^3 ellipsoid microstructures: train on solves of
-    the scheme, then time-to-1e-6 on held-out seeds from the zero guess (FP64 and
-    FP32) and from the learned guess (FP32, inference included)."""
+_MEMBER_PTS = None
+
+
+def _member_init(pts):
+    global _MEMBER_PTS
+    _MEMBER_PTS = pts
+
+
+def _member(seed):
+    """Phase ids and materials of the ellipsoid microstructure of a seed (worker process)."""
     import numpy as np
     import synth
+    mb = synth.ellipsoids_member(seed)
+    ph = synth.ellipsoids_phase(_MEMBER_PTS, len(_MEMBER_PTS), mb)
+    lame = np.array(mb["lame"])
+    return seed, ph, lame
+
+
+def learned_workload(ahom, ntrain, steps, n=64, ntest=4, chunk=512, workers=12, first_seed=100000, load=None, save=None):
+    """Learned initial guess on 64^3 ellipsoid microstructures (1-20 ellipsoids,
+    contrast 2-100, volume fraction 0.1-0.4): train on solves of the scheme
+    (FP32 to 1e-6, the 6 Mandel loads, strains kept on the device), streamed in
+    chunks of `chunk` solves with `steps` Adam steps spread over the chunks;
+    then, on `ntest` held-out seeds, time to 1e-6 from the zero guess (FP64,
+    FP32), from the learned guess with the fallback probe (FP32, inference
+    included) and of CG (FP64).  Microstructures are generated by a pool of
+    host processes while the device solves."""
+    import multiprocessing as mp
+
+    import numpy as np
     P = ahom.Pattern([[n, 0, 0], [0, n, 0], [0, 0, n]])
     pts = P.points()
     loads = mandel_loads()
     g = ahom.Guess(n, batch=4, seed=1)
-
-    def member(seed):
-        mb = synth.ellipsoids_member(seed)
-        ph = synth.ellipsoids_phase(pts, P.m, mb)
-        lame = np.array(mb["lame"])
-        return ph, lame, lame[:, 0].mean(), lame[:, 1].mean()
-
-    t0 = time.perf_counter()
-    for s in range(100000, 100000 + ntrain):
-        ph, lame, lam0, mu0 = member(s)
-        S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
-        S.set_material(lame, ph)
-        out = S.solve(loads, want_strain=True)
-        g.add_sample(ph, lame, lam0, mu0, out["strain"])
-    t_data = time.perf_counter() - t0
-    print(f"[bench] learned: {ntrain} training solves in {t_data:.1f} s", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    losses = g.train(steps, 4, 1e-3)
-    t_train = time.perf_counter() - t0
-    print(f"[bench] learned: {steps} steps in {t_train:.1f} s, loss {losses[:10].mean():.3f} -> {losses[-10:].mean():.3f}",
-          file=sys.stderr, flush=True)
+    if load:
+        g.load(load)              # continue from saved weights (Adam moments restart)
+    ctx = mp.get_context("spawn")
+    pool = ctx.Pool(processes=max(1, min(workers, (os.cpu_count() or 2) - 1)), initializer=_member_init, initargs=(pts,))
+    S = ahom.Solver(P, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000, resid_period=4)
+    d_strain = ahom.DeviceArray((6, 6, P.m), np.float64)
+    nchunks = max(1, -(-ntrain // chunk))
+    t_data = t_train = 0.0
+    losses = []
+    iters_train = []
+    seeds = list(range(first_seed, first_seed + ntrain))
+    for c in range(nchunks):
+        part = seeds[c * chunk:(c + 1) * chunk]
+        g.clear_samples()
+        t0 = time.perf_counter()
+        for seed, ph, lame in pool.imap(_member, part, chunksize=4):
+            d_ph = ahom.DeviceArray.from_numpy(ph)
+            S.set_material(lame, d_ph)
+            o = S.solve_device(loads, strain_out=d_strain)
+            iters_train.append(float(o["iters"].mean()))
+            g.add_sample(d_ph, lame, lame[:, 0].mean(), lame[:, 1].mean(), d_strain)
+        t_data += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        k = steps // nchunks + (1 if c < steps % nchunks else 0)
+        if k:
+            losses.extend(g.train(k, 4, 1e-3).tolist())
+        t_train += time.perf_counter() - t0
+        print(f"[bench] learned: chunk {c + 1}/{nchunks}: {len(part)} solves, {k} steps, "
+              f"loss {np.mean(losses[-10:]) if losses else float('nan'):.3f}", file=sys.stderr, flush=True)
+    del S
+    if save:
+        g.save(save)
+    losses = np.array(losses) if losses else np.full(10, np.nan)
     rows = []
+    if ntest < 1:
+        pool.close()
+        pool.join()
+        return dict(n=n, train_solves=ntrain, first_seed=first_seed, chunk=chunk, steps=int(len(losses)),
+                    data_s=round(t_data, 1), train_s=round(t_train, 1),
+                    train_solve_iters_mean=round(float(np.mean(iters_train)), 1) if iters_train else None,
+                    loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean()), held_out=0)
     kept = 0
-    for s in range(200000, 200000 + ntest):
-        ph, lame, lam0, mu0 = member(s)
+    solvers = {}
+    for name, prec, guess, scheme in (("fp64", ahom.FP64, False, ahom.SCHEME_BASIC),
+                                      ("fp32", ahom.FP32_MIXED, False, ahom.SCHEME_BASIC),
+                                      ("fp32_guess", ahom.FP32_MIXED, True, ahom.SCHEME_BASIC),
+                                      ("cg_fp64", ahom.FP64, False, ahom.SCHEME_CG)):
+        solvers[name] = (ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4, scheme=scheme,
+                                     guess_probe=17 if guess else 0), guess)
+    d_init = ahom.DeviceArray((6, 6, P.m), np.float64)
+    warm = True
+    for seed, ph, lame in pool.imap(_member, range(200000, 200000 + ntest), chunksize=4):
+        lam0, mu0 = lame[:, 0].mean(), lame[:, 1].mean()
+        d_ph = ahom.DeviceArray.from_numpy(ph)
         row = {}
-        for name, prec, guess, scheme in (("fp64", ahom.FP64, False, ahom.SCHEME_BASIC),
-                                          ("fp32", ahom.FP32_MIXED, False, ahom.SCHEME_BASIC),
-                                          ("fp32_guess", ahom.FP32_MIXED, True, ahom.SCHEME_BASIC),
-                                          ("cg_fp64", ahom.FP64, False, ahom.SCHEME_CG)):
-            S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4, scheme=scheme,
-                            guess_probe=17 if guess else 0)
-            S.set_material(lame, ph)
-            d_init = ahom.DeviceArray((6, 6, P.m), np.float64) if guess else None
-            if guess:
-                g.infer(ph, lame, lam0, mu0, loads, out=d_init)
-            S.solve_device(loads, init=d_init)       # warm: tuning and every buffer of the 6-load solve
+        for name, (Sx, guess) in solvers.items():
+            Sx.set_material(lame, d_ph)
+            if warm:           # tuning and every buffer of the 6-load solve, outside the timed window
+                if guess:
+                    g.infer(ph, lame, lam0, mu0, loads, out=d_init)
+                Sx.solve_device(loads, init=d_init if guess else None)
             t0 = time.perf_counter()
             if guess:
                 g.infer(ph, lame, lam0, mu0, loads, out=d_init)     # device to device, no host copies
-            o = S.solve_device(loads, init=d_init)
-            row[name] = dict(ms=round((time.perf_counter() - t0) * 1e3, 2), iters=float(o["iters"].mean()))
+            o = Sx.solve_device(loads, init=d_init if guess else None)
+            row[name] = dict(ms=(time.perf_counter() - t0) * 1e3, iters=float(o["iters"].mean()))
             if guess:
-                kept += int(S.last_starts(6).sum())
-            del S
+                kept += int(Sx.last_starts(6).sum())
+        warm = False
         rows.append(row)
+    pool.close()
+    pool.join()
     mean = {k: float(np.mean([r[k]["ms"] for r in rows])) for k in rows[0]}
     its = {k: float(np.mean([r[k]["iters"] for r in rows])) for k in rows[0]}
-    return dict(n=n, train_solves=ntrain, steps=steps, data_s=round(t_data, 1), train_s=round(t_train, 1),
+    better = int(sum(r["fp32_guess"]["iters"] < r["fp32"]["iters"] for r in rows))
+    worse = int(sum(r["fp32_guess"]["iters"] > r["fp32"]["iters"] for r in rows))
+    return dict(n=n, train_solves=ntrain, first_seed=first_seed, chunk=chunk, steps=int(len(losses)), data_s=round(t_data, 1),
+                train_s=round(t_train, 1),
+                train_solve_iters_mean=round(float(np.mean(iters_train)), 1) if iters_train else None,
                 loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean()),
-                held_out=ntest, mean_ms=mean, mean_iters=its, guess_probe=17,
-                guess_kept_loads=f"{kept}/{6 * ntest}",
+                held_out=ntest, mean_ms={k: round(v, 3) for k, v in mean.items()},
+                mean_iters={k: round(v, 2) for k, v in its.items()}, guess_probe=17,
+                guess_kept_loads=f"{kept}/{6 * ntest}", seeds_guess_fewer_iters=better, seeds_guess_more_iters=worse,
                 speedup_guess_fp32_vs_fp64=round(mean["fp64"] / mean["fp32_guess"], 3),
                 speedup_fp32_vs_fp64=round(mean["fp64"] / mean["fp32"], 3),
                 speedup_cg_fp64_vs_fp64=round(mean["fp64"] / mean["cg_fp64"], 3))
@@ -509,6 +564,12 @@ def main():
                     help="skip training the learned initial guess on 64^3 ellipsoid solves and timing it (~40 s)")
     ap.add_argument("--learned-train", type=int, default=64, help="training solves of the learned-guess leg")
     ap.add_argument("--learned-steps", type=int, default=400, help="Adam steps of the learned-guess leg")
+    ap.add_argument("--learned-test", type=int, default=4, help="held-out seeds of the learned-guess leg")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the learned-guess leg (with --learned-train/steps/test) and print its JSON")
+    ap.add_argument("--learned-first-seed", type=int, default=100000, help="first training seed")
+    ap.add_argument("--learned-load", help="start from network weights saved by a previous run")
+    ap.add_argument("--learned-save", help="save the trained network weights to this file")
     ap.add_argument("--fp64-only", action="store_true", help="throughput of the FP64 path only (profiling runs)")
     ap.add_argument("--ttt-resid-period", type=int, default=4,
                     help="residual evaluated every k iterations in the time-to-tolerance solves")
@@ -565,6 +626,12 @@ def main():
             res = _throughput(ahom, P, np.array([10.0, 0.5, 1.0]), ph, args.steps, "conductivity 128^3", precs=precs,
                               physics=ahom.CONDUCTIVITY, loads=np.eye(3))
         print(json.dumps(dict(leg=args.leg, steps=args.steps, **res)))
+        return
+
+    if args.learned_only:
+        print(json.dumps(dict(learned_guess=learned_workload(
+            ahom, args.learned_train, args.learned_steps, ntest=args.learned_test, first_seed=args.learned_first_seed,
+            load=args.learned_load, save=args.learned_save))))
         return
 
     print(f"[bench] building workload diag({args.size},{args.size},{args.size})", file=sys.stderr, flush=True)
@@ -651,7 +718,7 @@ def main():
         conductivity = conductivity_workload(ahom, args.size, ttt=not args.no_ttt)
     learned = None
     if not args.no_learned and not args.no_ttt and not args.fp64_only:
-        learned = learned_workload(ahom, args.learned_train, args.learned_steps)
+        learned = learned_workload(ahom, args.learned_train, args.learned_steps, ntest=args.learned_test)
     if not args.no_cpu:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline()

@@ -459,6 +459,9 @@ int ahom_guess_set_params(ahom_guess* g, const float* in);
 int ahom_guess_add_sample(ahom_guess* g, const uint8_t* phase, int n_phase, const double* lame, double lam0, double mu0,
                           const double* strain, int mem_flags);
 int ahom_guess_num_samples(const ahom_guess* g, int* n);
+/* Drop every training sample (the storage is kept for the next ones): training
+ * on more solves than device memory holds streams them in chunks. */
+int ahom_guess_clear_samples(ahom_guess* g);
 
 /* Loss and its gradient (flat, as the parameters) over the given samples. */
 int ahom_guess_gradients(ahom_guess* g, const int* samples, int count, float* grad, double* loss);

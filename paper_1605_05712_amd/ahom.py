@@ -57,7 +57,8 @@ EXPORTS = [
     "ahom_batch_member_points", "ahom_batch_set_material", "ahom_batch_set_reference", "ahom_batch_solve",
     "ahom_batch_strain", "ahom_batch_history", "ahom_batch_cauchy_history", "ahom_batch_last_timing", "ahom_batch_member_variant",
     "ahom_guess_create", "ahom_guess_destroy", "ahom_guess_num_params", "ahom_guess_get_params", "ahom_guess_set_params",
-    "ahom_guess_add_sample", "ahom_guess_num_samples", "ahom_guess_gradients", "ahom_guess_train",
+    "ahom_guess_add_sample", "ahom_guess_num_samples", "ahom_guess_clear_samples", "ahom_guess_gradients",
+    "ahom_guess_train",
     "ahom_guess_adam_step", "ahom_guess_infer", "ahom_guess_predict_sample", "ahom_guess_save", "ahom_guess_load",
     "ahom_conv3d",
 ]
@@ -127,6 +128,7 @@ _lib.ahom_guess_get_params.argtypes = [_P, _fp]
 _lib.ahom_guess_set_params.argtypes = [_P, _fp]
 _lib.ahom_guess_add_sample.argtypes = [_P, _P, ct.c_int, _dp, ct.c_double, ct.c_double, _P, ct.c_int]
 _lib.ahom_guess_num_samples.argtypes = [_P, _ip]
+_lib.ahom_guess_clear_samples.argtypes = [_P]
 _lib.ahom_guess_gradients.argtypes = [_P, _ip, ct.c_int, _fp, _dp]
 _lib.ahom_guess_train.argtypes = [_P, ct.c_int, ct.c_int, ct.c_double, _dp]
 _lib.ahom_guess_adam_step.argtypes = [_P, _fp, ct.c_double]
@@ -591,6 +593,9 @@ class Guess:
         n = ct.c_int()
         _check(_lib.ahom_guess_num_samples(self._h, ct.byref(n)))
         return n.value
+
+    def clear_samples(self):
+        _check(_lib.ahom_guess_clear_samples(self._h))
 
     def gradients(self, samples):
         idx = np.ascontiguousarray(np.asarray(samples, dtype=np.int32))

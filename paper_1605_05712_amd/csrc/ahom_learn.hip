@@ -842,6 +842,14 @@ int ahom_guess_add_sample(ahom_guess* g, const uint8_t* phase, int n_phase, cons
     return AHOM_OK;
 }
 
+int ahom_guess_clear_samples(ahom_guess* g) {
+    if (!g) return lfail(AHOM_E_ARG, "null argument");
+    LCHK(hipStreamSynchronize(g->stream));
+    g->n_samples = 0;
+    g->h_info.clear();
+    return AHOM_OK;
+}
+
 int ahom_guess_num_samples(const ahom_guess* g, int* n) {
     if (!g || !n) return lfail(AHOM_E_ARG, "null argument");
     *n = g->n_samples;
