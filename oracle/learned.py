@@ -132,74 +132,88 @@ def net_input(phase, lame, lam0, mu0, n):
     return np.stack([(phase != 0).astype(np.float64), mu / mu0 - 1.0, (lam / lam0 - 1.0) if lam0 != 0 else 0.0 * lam])
 
 
-def forward(params, x):
-    """Network output (36, n, n, n) and the cache for backward."""
+def _keep(a):
+    return a
+
+
+def forward(params, x, store=None):
+    """Network output (36, n, n, n) and the cache for backward.
+
+    ``store`` (optional) rounds every tensor the network keeps between layers
+    (input, activations, skip sums, pooled maps) to a storage format, e.g.
+    BF16; the output layer stays unrounded.  Without it everything is FP64."""
+    q = store or _keep
     c = {}
 
     def conv(k, inp, act=True):
         w, b = params[k]
         z = conv3d(inp, w, b)
-        return relu(z) if act else z
+        return q(relu(z)) if act else z
 
-    c["x0"] = x
-    c["e0a"] = conv(0, x)
+    c["x0"] = q(x)
+    c["e0a"] = conv(0, c["x0"])
     c["e0"] = conv(1, c["e0a"])
-    c["p1"] = avgpool2(c["e0"])
+    c["p1"] = q(avgpool2(c["e0"]))
     c["e1a"] = conv(2, c["p1"])
     c["e1"] = conv(3, c["e1a"])
-    c["p2"] = avgpool2(c["e1"])
+    c["p2"] = q(avgpool2(c["e1"]))
     c["e2a"] = conv(4, c["p2"])
     c["e2"] = conv(5, c["e2a"])
-    c["p3"] = avgpool2(c["e2"])
+    c["p3"] = q(avgpool2(c["e2"]))
     c["e3a"] = conv(6, c["p3"])
     c["e3"] = conv(7, c["e3a"])
     c["u2"] = upsample2(c["e3"])
     c["d2a"] = conv(8, c["u2"])
-    c["s2"] = c["d2a"] + c["e2"]
+    c["s2"] = q(c["d2a"] + c["e2"])
     c["d2"] = conv(9, c["s2"])
     c["u1"] = upsample2(c["d2"])
     c["d1a"] = conv(10, c["u1"])
-    c["s1"] = c["d1a"] + c["e1"]
+    c["s1"] = q(c["d1a"] + c["e1"])
     c["d1"] = conv(11, c["s1"])
     c["u0"] = upsample2(c["d1"])
     c["d0a"] = conv(12, c["u0"])
-    c["s0"] = c["d0a"] + c["e0"]
+    c["s0"] = q(c["d0a"] + c["e0"])
     c["d0"] = conv(13, c["s0"])
     out = conv(14, c["d0"], act=False)
     return out, c
 
 
-def backward(params, c, dout):
-    """Gradients [(dw, db)] of the 15 convolutions for output gradient dout."""
+def backward(params, c, dout, store=None):
+    """Gradients [(dw, db)] of the 15 convolutions for output gradient dout.
+
+    ``store`` rounds the gradients kept between layers (the output gradient,
+    each layer's input gradient, the pooling/upsampling adjoints with their
+    skip sums) as ``forward``'s does; weight and bias gradients stay exact."""
+    q = store or _keep
     grads = [None] * 15
 
     def conv_back(k, inp, dz):
         w, _ = params[k]
         grads[k] = (conv3d_wgrad(inp, dz), dz.sum(axis=(1, 2, 3)))
-        return conv3d_adjoint(dz, w)
+        return q(conv3d_adjoint(dz, w))
 
     def rb(da, a):   # through ReLU, given its output a
         return da * (a > 0)
 
-    g = conv_back(14, c["d0"], dout)
+    g = conv_back(14, c["d0"], q(dout))
     ds0 = conv_back(13, c["s0"], rb(g, c["d0"]))
     g = conv_back(12, c["u0"], rb(ds0, c["d0a"]))
-    g = upsample2_adjoint(g)
+    g = q(upsample2_adjoint(g))
     ds1 = conv_back(11, c["s1"], rb(g, c["d1"]))
     g = conv_back(10, c["u1"], rb(ds1, c["d1a"]))
-    g = upsample2_adjoint(g)
+    g = q(upsample2_adjoint(g))
     ds2 = conv_back(9, c["s2"], rb(g, c["d2"]))
     g = conv_back(8, c["u2"], rb(ds2, c["d2a"]))
-    g = upsample2_adjoint(g)
+    g = q(upsample2_adjoint(g))
     g = conv_back(7, c["e3a"], rb(g, c["e3"]))
     g = conv_back(6, c["p3"], rb(g, c["e3a"]))
-    g = avgpool2_adjoint(g) + ds2
+    g = q(avgpool2_adjoint(g) + ds2)
     g = conv_back(5, c["e2a"], rb(g, c["e2"]))
     g = conv_back(4, c["p2"], rb(g, c["e2a"]))
-    g = avgpool2_adjoint(g) + ds1
+    g = q(avgpool2_adjoint(g) + ds1)
     g = conv_back(3, c["e1a"], rb(g, c["e1"]))
     g = conv_back(2, c["p1"], rb(g, c["e1a"]))
-    g = avgpool2_adjoint(g) + ds0
+    g = q(avgpool2_adjoint(g) + ds0)
     g = conv_back(1, c["e0a"], rb(g, c["e0"]))
     conv_back(0, c["x0"], rb(g, c["e0a"]))
     return grads
