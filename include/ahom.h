@@ -98,7 +98,15 @@ typedef struct ahom_config {
                            sweep of the passes plus two vector kernels; the stop test, the
                            history and the outputs are those of the Basic Scheme (r(n) of
                            eps(n) = eps_bar + x_n; n = updates performed).  Single-pattern
-                           solver, AHOM_FP64, AHOM_STOP_RESIDUAL, no init. */
+                           solver, AHOM_STOP_RESIDUAL, no init.  In AHOM_FP32_MIXED: defect
+                           correction — one FP64 sweep gives the exact residual field and
+                           equilibrium residual of the FP64 iterate, an FP32 CG solve of the
+                           correction runs until its residual has dropped by `refine` (C0
+                           norm), the FP64 iterate takes the correction's projection onto
+                           compatible zero-mean fields (one more FP64 sweep); n counts the FP32
+                           updates, ahom_solver_last_restarts the corrections, the history holds
+                           the FP64 residual where a sweep evaluated it.  Needs refine >= 0
+                           (0 selects 1e-3). */
     int physics;        /* AHOM_ELASTICITY (0, default): quasi-static linear elasticity (Sec. 3.1).
                            AHOM_CONDUCTIVITY (1): the steady-state heat (conductivity) equation that
                            Sec. 3 names beside it: unknown the gradient e = grad theta of a

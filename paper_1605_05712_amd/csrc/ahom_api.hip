@@ -211,7 +211,12 @@ struct ahom_solver {
     double* d_en = nullptr;
     double* d_rr = nullptr;
     double* d_zero6 = nullptr;     // [load][ncomp] zeros: the mean of the operator output
+    // mixed-precision CG: the homogeneous reference medium (all points phase
+    // 0, table entry C0) that the FP64 companion projects corrections with
+    uint8_t* d_zero_phase = nullptr;
+    double* d_c0tab = nullptr;
     int cg_nblk = 1;
+    double cg_rr_stop = 0.0;       // > 0: inner solves of the mixed-precision scheme
     // per-stage settings read by the launches
     double cur_tol = 0.0;
     const void* spec_toff = nullptr;
@@ -337,6 +342,7 @@ struct ahom_solver {
             d_lame_tab = d_lame_pts = d_lame_pts_t = nullptr;
         }
         dfree(d_phase); dfree(d_lame_tab); dfree(d_lame_pts); dfree(d_phase_t); dfree(d_lame_pts_t);
+        dfree(d_zero_phase); dfree(d_c0tab);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -515,6 +521,15 @@ int cg_sweep(ahom_solver* s, int nload, int start) {
     c.tol = s->cfg.tol;
     c.max_iter = s->cfg.max_iter;
     c.start = start;
+    c.rr_stop = s->cg_rr_stop;
+    if (start == 2) {
+        // start of an inner solve from a given residual field r(0), stored
+        // in buf1: r = p = r(0), <r, r>_C0 (no operator sweep)
+        c.start = 1;
+        if (ahom_launch_cg_update(s->prec, s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_update failed");
+        if (ahom_launch_cg_reduce(s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_reduce failed");
+        return AHOM_OK;
+    }
     if (s->launch_real_turn(nload, st)) return fail(AHOM_E_DEVICE, "launch real-space pass failed");
     if (ahom_launch_cg_alpha(s->dim, c, nload, st)) return fail(AHOM_E_DEVICE, "launch k_cg_alpha failed");
     for (int a = 1; a <= P.D - 2; ++a)
@@ -740,9 +755,13 @@ int ensure_ref64(ahom_solver* s, int nload) {
     return r->autotune(nload);
 }
 
+int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
+                   double* mean_out, int mem_flags);
+
 // Conjugate gradients for n_load strains (cfg.scheme == AHOM_SCHEME_CG).
 int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
              double* mean_out, int mem_flags) {
+    if (s->prec == AHOM_FP32_MIXED) return solve_cg_mixed(s, n_load, ebc, strain_out, iters, resid, mean_out, mem_flags);
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;
@@ -806,6 +825,181 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
     int ret = AHOM_OK;
     for (int l = 0; l < n_load; ++l) {
         const LoadState& ls = s->h_st[l];
+        if (iters) iters[l] = ls.iter;
+        if (resid) resid[l] = ls.resid;
+        if (mean_out)
+            for (int c = 0; c < nc; ++c) mean_out[(size_t)l * nc + c] = ls.mean[c];
+        if (ls.status == 2) ret = AHOM_E_DIVERGED;
+        else if (ls.status == 1 && ret == AHOM_OK) ret = AHOM_W_NOT_CONVERGED;
+    }
+    if (ret == AHOM_E_DIVERGED) g_err = "residual diverged";
+    return ret;
+}
+
+// Mixed precision CG (AHOM_FP32_MIXED): defect correction with FP32 inner
+// CG solves.  The FP64 iterate eps_b (the FP64 companion's x buffer) gets
+// its exact residual field r_b = -A eps_b, equilibrium residual and mean
+// stress from one FP64 operator sweep (the companion's CG start on eps_b);
+// an FP32 CG solve of A e = r_b from e = 0, stopped when its residual has
+// dropped by `refine` in the C0 norm, gives the correction, eps_b += P e with
+// P the projection onto compatible zero-mean fields (one more FP64 sweep);
+// until the FP64 equilibrium residual of eps_b meets tol.  n counts the FP32
+// updates; the FP64 sweeps are the restarts.
+int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
+                   double* mean_out, int mem_flags) {
+    int rc = s->ensure_capacity(n_load);
+    if (rc) return rc;
+    s->spec_toff = nullptr;
+    s->spec_dout = s->spec_dneg = nullptr;
+    s->red_sig_base = nullptr;
+    if ((rc = s->autotune(n_load))) return rc;
+    if ((rc = ensure_ref64(s, n_load))) return rc;
+    ahom_solver* r = s->ref64;
+    const Plan& P = s->pat->plan;
+    const int nc = s->ncomp;
+    const size_t per = (size_t)nc * P.S;
+    // the reference medium C0 of this solve (stiffness or conductivity)
+    if (!s->d_zero_phase) {
+        HIPCHK(hipMalloc((void**)&s->d_zero_phase, (size_t)s->pat->sf.m));
+        HIPCHK(hipMemset(s->d_zero_phase, 0, (size_t)s->pat->sf.m));
+        HIPCHK(hipMalloc((void**)&s->d_c0tab, 2 * sizeof(double)));
+    }
+    {
+        const double c0[2] = {s->lam0, s->mu0};
+        HIPCHK(hipMemcpy(s->d_c0tab, c0, sizeof c0, hipMemcpyHostToDevice));
+    }
+    hipStream_t st = s->stream;
+    HIPCHK(hipMemcpyAsync(r->d_epsbar, ebc, (size_t)n_load * nc * sizeof(double), hipMemcpyHostToDevice, st));
+    FillArgs f{};
+    f.eps_bar = r->d_epsbar;
+    f.S = P.S;
+    f.row = P.S / P.ax[0].slen;
+    f.nfield = nc;
+    f.buf = r->d_x;                    // eps_b = eps_bar
+    if (ahom_launch_fill(AHOM_FP64, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    std::vector<LoadState> fin(n_load);            // FP64 result per load (resid, mean, status)
+    std::vector<int> done(n_load, 0), nupd(n_load, 0);
+    std::vector<std::vector<std::pair<int, double>>> hrec(n_load);   // (updates so far, FP64 residual) per sweep
+    int nrestart = 0, total = 0;
+    HIPCHK(hipEventRecord(s->ev0, st));
+    for (;;) {
+        // FP64 sweep on eps_b: r_b, its traction, residual and mean stress
+        HIPCHK(hipMemcpyAsync(r->d_buf0, r->d_x, (size_t)n_load * per * 16, hipMemcpyDeviceToDevice, st));
+        if (ahom_launch_reset(r->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+        if (ahom_launch_zero(AHOM_FP64, r->d_tbuf, (int64_t)n_load * r->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+        if ((rc = cg_sweep(r, n_load, 1))) return rc;
+        HIPCHK(hipMemcpyAsync(r->h_st, r->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool all = true;
+        for (int l = 0; l < n_load; ++l) {
+            if (done[l]) continue;
+            LoadState ls = r->h_st[l];
+            hrec[l].emplace_back(nupd[l], ls.resid);
+            const bool bad = !(ls.resid == ls.resid) || std::isinf(ls.resid);
+            ls.iter = nupd[l];
+            if (bad) { ls.status = 2; done[l] = 1; }
+            else if (ls.resid <= s->cfg.tol) { ls.status = 0; done[l] = 1; }
+            else if (nupd[l] >= s->cfg.max_iter) { ls.status = 1; done[l] = 1; }
+            fin[l] = ls;
+            all = all && done[l];
+        }
+        if (all) break;
+        ++nrestart;
+        // FP32 inner CG on A e = r_b for the loads still running
+        if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+        HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int l = 0; l < n_load; ++l) s->h_st[l].done = done[l];
+        HIPCHK(hipMemcpyAsync(s->d_st, s->h_st, n_load * sizeof(LoadState), hipMemcpyHostToDevice, st));
+        if (ahom_launch_cg_demote(static_cast<const double2*>(r->d_r), static_cast<float2*>(s->d_buf1),
+                                  (int64_t)n_load * per, st))
+            return fail(AHOM_E_DEVICE, "demote");
+        if (ahom_launch_zero(s->prec, s->d_x, (int64_t)n_load * per, st)) return fail(AHOM_E_DEVICE, "zero");
+        if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+        s->cg_rr_stop = s->cfg.refine;
+        rc = cg_sweep(s, n_load, 2);
+        int local = 0;
+        while (!rc) {
+            HIPCHK(hipMemcpyAsync(s->h_st, s->d_st, n_load * sizeof(LoadState), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool inner_done = true;
+            for (int l = 0; l < n_load; ++l) inner_done = inner_done && s->h_st[l].done;
+            if (inner_done) break;
+            if (local > s->cfg.max_iter + 2 * s->cfg.check_period) { rc = fail(AHOM_E_DEVICE, "loop control did not terminate"); break; }
+            for (int i = 0; i < s->cfg.check_period && !rc; ++i, ++local) rc = cg_sweep(s, n_load, 0);
+        }
+        s->cg_rr_stop = 0.0;
+        if (rc) return rc;
+        for (int l = 0; l < n_load; ++l)
+            if (!done[l]) { nupd[l] += s->h_st[l].iter; total += s->h_st[l].iter; }
+        // eps_b += P e (loads that are done have e = 0).  The FP32 updates
+        // leave rounding noise in e also where the operator never looks: the
+        // mean and the classes the Hermitian rule zeroes.  No later residual
+        // sees it, yet it shifts <sigma> (~1e-7 relative), so e enters the
+        // iterate only through its C0-orthogonal projection P onto compatible
+        // zero-mean fields, taken in FP64: the companion's CG start sweep on
+        // e in the homogeneous reference medium gives r = -Gamma0 C0 e = -P e.
+        GatherArgs ga{};
+        ga.out = static_cast<double2*>(r->d_buf0);     // e in FP64
+        ga.base = nullptr;
+        ga.in0 = ga.in1 = static_cast<const float2*>(s->d_x);
+        ga.st = s->d_st;
+        ga.per_load = (int64_t)per;
+        if (ahom_launch_refine_gather(ga, n_load, st)) return fail(AHOM_E_DEVICE, "launch refine gather");
+        uint8_t* sv_ph = r->d_phase;
+        uint8_t* sv_pht = r->d_phase_t;
+        double* sv_tab = r->d_lame_tab;
+        double* sv_pts = r->d_lame_pts;
+        double* sv_ptst = r->d_lame_pts_t;
+        const int sv_np = r->n_phase;
+        r->d_phase = r->d_phase_t = s->d_zero_phase;
+        r->d_lame_tab = s->d_c0tab;
+        r->d_lame_pts = r->d_lame_pts_t = nullptr;
+        r->n_phase = 1;
+        rc = ahom_launch_reset(r->d_st, n_load, st) ||
+                     ahom_launch_zero(AHOM_FP64, r->d_tbuf, (int64_t)n_load * r->nt * P.S, st)
+                 ? fail(AHOM_E_DEVICE, "reset")
+                 : cg_sweep(r, n_load, 1);
+        r->d_phase = sv_ph;
+        r->d_phase_t = sv_pht;
+        r->d_lame_tab = sv_tab;
+        r->d_lame_pts = sv_pts;
+        r->d_lame_pts_t = sv_ptst;
+        r->n_phase = sv_np;
+        if (rc) return rc;
+        if (ahom_launch_cg_sub(static_cast<double2*>(r->d_x), static_cast<const double2*>(r->d_r), (int64_t)n_load * per, st))
+            return fail(AHOM_E_DEVICE, "launch cg sub");
+    }
+    float ms = 0.f;
+    HIPCHK(hipEventRecord(s->ev1, st));
+    HIPCHK(hipEventSynchronize(s->ev1));
+    HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->last_ms = ms;
+    s->last_enqueued = total + nrestart + 1;
+    s->last_nload = n_load;
+    s->last_restarts = nrestart;
+    s->last_start.assign(n_load, 0);
+    // history: the FP64 residual at the update counts where a sweep evaluated it, -1 between
+    std::vector<double> hh((size_t)n_load * s->hist_cap, -1.0);
+    for (int l = 0; l < n_load; ++l)
+        for (const auto& pr : hrec[l])
+            if (pr.first < s->hist_cap) hh[(size_t)l * s->hist_cap + pr.first] = pr.second;
+    HIPCHK(hipMemcpyAsync(s->d_hist, hh.data(), hh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int l = 0; l < n_load; ++l) s->h_st[l] = fin[l];
+    if (strain_out) {
+        if (mem_flags != AHOM_MEM_DEVICE && (rc = s->ensure_real_staging())) return rc;
+        RealArgs ra = r->real_args(REAL_TO_REAL);
+        ra.buf0 = ra.buf1 = r->d_x;
+        ra.real_io = mem_flags == AHOM_MEM_DEVICE ? static_cast<double*>(strain_out) : s->d_real;
+        if (ahom_launch_real(AHOM_FP64, r->dim, REAL_TO_REAL, ra, r->g_real.nwg, n_load, r->g_real.lds, st))
+            return fail(AHOM_E_DEVICE, "launch to_real");
+        if (mem_flags != AHOM_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(strain_out, s->d_real, (size_t)n_load * nc * P.m * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    int ret = AHOM_OK;
+    for (int l = 0; l < n_load; ++l) {
+        const LoadState& ls = fin[l];
         if (iters) iters[l] = ls.iter;
         if (resid) resid[l] = ls.resid;
         if (mean_out)
@@ -1035,8 +1229,10 @@ int ahom_solver_create(const ahom_pattern* pc, const ahom_config* cfg, ahom_solv
     if (cfg->scheme != AHOM_SCHEME_BASIC && cfg->scheme != AHOM_SCHEME_CG) return fail(AHOM_E_ARG, "unknown scheme");
     if (cfg->physics != AHOM_ELASTICITY && cfg->physics != AHOM_CONDUCTIVITY) return fail(AHOM_E_ARG, "unknown physics");
     if (cfg->guess_probe < 0 || cfg->guess_probe > cfg->max_iter) return fail(AHOM_E_ARG, "guess_probe must be in [0, max_iter]");
-    if (cfg->scheme == AHOM_SCHEME_CG && (cfg->precision != AHOM_FP64 || cfg->stop_rule != AHOM_STOP_RESIDUAL))
-        return fail(AHOM_E_ARG, "the conjugate-gradient scheme runs in AHOM_FP64 with the residual stop rule");
+    if (cfg->scheme == AHOM_SCHEME_CG && cfg->stop_rule != AHOM_STOP_RESIDUAL)
+        return fail(AHOM_E_ARG, "the conjugate-gradient scheme stops on the residual");
+    if (cfg->scheme == AHOM_SCHEME_CG && cfg->precision == AHOM_FP32_MIXED && !(cfg->refine >= 0.0))
+        return fail(AHOM_E_ARG, "the conjugate-gradient scheme in FP32 runs with FP64 corrections (refine >= 0)");
     return create_solver(const_cast<ahom_pattern*>(pc), cfg, out);
 }
 

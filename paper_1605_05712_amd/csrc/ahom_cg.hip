@@ -142,9 +142,17 @@ __global__ void __launch_bounds__(kWG) k_cg_reduce(CgArgs a) {
     if (tid != 0) return;
     CgScalars& g = a.cg[load];
     const double rr = (double)a.L0 * v[0];
-    double fro = 0.0;
-    for (int c = 0; c < NC; ++c) fro += field_weight(PH, DIM, c) * st.mean[c] * st.mean[c];
-    const double r = sqrt(v[1]) / sqrt(fro);
+    const bool inner = a.rr_stop > 0.0;
+    if (a.start) g.rr0 = rr;
+    double r;
+    if (inner) {
+        // inner solve: the C0 norm of the CG residual relative to its start
+        r = g.rr0 > 0.0 ? sqrt(rr / g.rr0) : 0.0;
+    } else {
+        double fro = 0.0;
+        for (int c = 0; c < NC; ++c) fro += field_weight(PH, DIM, c) * st.mean[c] * st.mean[c];
+        r = sqrt(v[1]) / sqrt(fro);
+    }
     const int n = a.start ? 0 : st.iter + 1;
     if (a.start) {
         g.beta = 0.0;
@@ -158,7 +166,7 @@ __global__ void __launch_bounds__(kWG) k_cg_reduce(CgArgs a) {
     st.iter = n;
     const bool bad = !(r == r) || isinf(r) || (st.r0 > 0.0 && r > 1e3 * st.r0);
     if (bad) { st.done = 1; st.status = 2; return; }
-    if (r <= a.tol) { st.done = 1; st.status = 0; return; }
+    if (r <= (inner ? a.rr_stop : a.tol)) { st.done = 1; st.status = 0; return; }
     if (n >= a.max_iter) { st.done = 1; st.status = 1; return; }
 }
 
@@ -182,7 +190,35 @@ __global__ void __launch_bounds__(kWG) k_cg_direction(CgArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(kWG) k_cg_demote(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG)
+        out[i] = float2{(float)in[i].x, (float)in[i].y};
+}
+
+__global__ void __launch_bounds__(kWG) k_cg_sub(double2* __restrict__ x, const double2* __restrict__ d, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+        const double2 v = x[i], w = d[i];
+        x[i] = double2{v.x - w.x, v.y - w.y};
+    }
+}
+
 }  // namespace
+
+int ahom_launch_cg_sub(double2* x, const double2* d, int64_t n, hipStream_t s) {
+    int64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_cg_sub, dim3((unsigned)blocks), dim3(kWG), 0, s, x, d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int ahom_launch_cg_demote(const double2* in, float2* out, int64_t n, hipStream_t s) {
+    int64_t blocks = (n + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_cg_demote, dim3((unsigned)blocks), dim3(kWG), 0, s, in, out, n);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
 
 int ahom_cg_blocks(int64_t S) {
     const int64_t b = (S + kWG - 1) / kWG;

@@ -188,6 +188,7 @@ struct CgScalars {
     double alpha;     // step length of the current update (1 for the start)
     double beta;      // direction update after the current step
     double pcp;       // <p, C p> of the current direction
+    double rr0;       // <r, r>_C0 of the start (inner solves of the mixed-precision scheme)
 };
 
 struct CgArgs {
@@ -213,6 +214,9 @@ struct CgArgs {
     double tol;
     int max_iter;
     int start;                // 1: the start (r(0), p_0 = r_0), 0: an update
+    // > 0: an inner solve of the mixed-precision scheme: the recorded residual
+    // is sqrt(<r, r>_C0 / <r(0), r(0)>_C0) and the stop is that ratio <= rr_stop
+    double rr_stop;
 };
 
 int ahom_launch_cg_alpha(int dim, const CgArgs& a, int nload, hipStream_t s);
@@ -221,6 +225,10 @@ int ahom_launch_cg_reduce(int dim, const CgArgs& a, int nload, hipStream_t s);
 int ahom_launch_cg_direction(int prec, int dim, const CgArgs& a, int nload, hipStream_t s);
 // workgroups per load of the update kernel (size of rr_part)
 int ahom_cg_blocks(int64_t S);
+// out[i] = (float) in[i] for n complex values
+int ahom_launch_cg_demote(const double2* in, float2* out, int64_t n, hipStream_t s);
+// x[i] -= d[i], i < n
+int ahom_launch_cg_sub(double2* x, const double2* d, int64_t n, hipStream_t s);
 
 // ---- batched solves: one persistent launch over many (pattern, load) items.
 // A workgroup takes an item from the queue and runs Algorithm 1 for it to the

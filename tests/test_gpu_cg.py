@@ -125,8 +125,8 @@ def test_cg_homogeneous_and_argument_errors():
     C, it = S.effective_stiffness()
     assert list(it) == [0] * 6
     assert np.allclose(C, E.tensor4_to_mandel(E.iso_tensor(1.2, 0.7, 3)), atol=1e-13)
-    with pytest.raises(ahom.AhomError) as ex:
-        ahom.Solver(P, precision=ahom.FP32_MIXED, scheme=ahom.SCHEME_CG)
+    with pytest.raises(ahom.AhomError) as ex:       # FP32 CG needs its FP64 corrections
+        ahom.Solver(P, precision=ahom.FP32_MIXED, scheme=ahom.SCHEME_CG, refine=-1.0)
     assert ex.value.code == ahom.AHOM_E_ARG
     with pytest.raises(ahom.AhomError) as ex:
         ahom.Solver(P, scheme=ahom.SCHEME_CG, stop_rule=ahom.STOP_CAUCHY)
@@ -180,3 +180,43 @@ def test_cg_spheres_contrast_100_matches_oracle_golden(n, bound):
     print("CG iterations", list(it), "oracle Basic Scheme", gold["iters"], "max err", err.max(), flush=True)
     assert err.max() < bound
     assert max(it) * 3 < min(gold["iters"])
+
+
+@pytest.mark.parametrize("physics", [ahom.ELASTICITY, ahom.CONDUCTIVITY])
+def test_cg_fp32_with_fp64_corrections(physics):
+    """CG in FP32 with FP64 defect correction on contrast-100 spheres (32^3):
+    the FP64 residual reaches 1e-9, below the FP32 rounding floor; the field and
+    C_eff (K_eff) equal the FP64 CG solve's to the tolerance, the elastic C_eff
+    the oracle golden's; the updates are those of FP64 CG up to the restarts."""
+    gold = json.load(open(os.path.join(GOLD, "spheres_c3_32.json")))
+    n = gold["n"]
+    M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
+    say("cg fp32 + fp64 corrections", M, "physics", physics)
+    c, r = synth.spheres_rsa(seed=3)
+    P = ahom.Pattern(M)
+    ph = synth.spheres_phase(P.points(), P.m, c, r)
+    lame = np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
+    out = {}
+    for prec in (ahom.FP64, ahom.FP32_MIXED):
+        S = ahom.Solver(P, precision=prec, tol=1e-9, max_iter=3000, scheme=ahom.SCHEME_CG, physics=physics)
+        if physics == ahom.CONDUCTIVITY:
+            S.set_conductivity([1.0, 100.0], ph)
+            C, it = S.effective_conductivity(allow=(ahom.AHOM_OK,))
+            f = S.solve_conductivity(np.eye(3)[:1], want_field=True, allow=(ahom.AHOM_OK,))
+            field = f["field"][0]
+        else:
+            S.set_material(lame, ph)
+            C, it = S.effective_stiffness(allow=(ahom.AHOM_OK,))
+            f = S.solve(np.eye(3)[None] * 0.01, want_strain=True, allow=(ahom.AHOM_OK,))
+            field = f["strain"][0]
+        assert np.all(f["resid"] <= 1e-9)
+        out[prec] = (C, it, field, S.last_restarts())
+        del S
+    C64, it64, f64, _ = out[ahom.FP64]
+    C32, it32, f32, nr = out[ahom.FP32_MIXED]
+    print("updates FP64", list(it64), "FP32 + corrections", list(it32), "restarts", nr, flush=True)
+    assert nr >= 1
+    assert np.abs(C32 - C64).max() < 1e-8 * np.abs(C64).max()
+    assert rel_err(f32, f64) < 1e-7
+    if physics == ahom.ELASTICITY:
+        assert np.abs(C32 - np.array(gold["ceff"])).max() < 1e-8 * np.abs(C64).max()
