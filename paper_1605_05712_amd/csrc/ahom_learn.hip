@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <string>
@@ -111,6 +112,103 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 z[j] = acc[q][c][j] + (a.bias ? a.bias[co + j] : 0.f);
+                if (a.relu) z[j] = fmaxf(z[j], 0.f);
+            }
+            if (a.zf) *reinterpret_cast<f32x4*>(a.zf + row + co) = f32x4{z[0], z[1], z[2], z[3]};
+            if (a.a) {
+                bf16x4 v;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = (bf16)z[j];
+                *reinterpret_cast<bf16x4*>(a.a + row + co) = v;
+                if (a.y) {
+                    const bf16x4 s = *reinterpret_cast<const bf16x4*>(a.skip + row + co);
+                    bf16x4 o;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) o[j] = (bf16)((float)v[j] + (float)s[j]);
+                    *reinterpret_cast<bf16x4*>(a.y + row + co) = o;
+                }
+            }
+        }
+    }
+}
+
+// Brick tiling for grids with n a multiple of 16: a workgroup computes a
+// 4 (z) x 4 (y) x 16 (x) brick of output points for one block of 16 NCT
+// output channels.  Per 32-channel slice of the input, the brick's periodic
+// halo (6 x 6 x 18 points x 32 channels = 41.5 KB) is staged in LDS once and
+// read by all 27 taps, instead of one global gather per tap.  Wave w owns
+// z-slice w: four rows of 16 points, one MFMA column block each.  LDS holds a
+// halo point's four 16 B channel chunks with the chunk index XORed by bits
+// 2-3 of the point index, so the 16 consecutive points that a quarter-wave
+// reads for one chunk fall on distinct banks.
+constexpr int kBX = 16, kBY = 4, kBZ = 4;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+
+__device__ __forceinline__ int halo_slot(int q, int chunk) { return 4 * q + (chunk ^ ((q >> 2) & 3)); }
+
+template <int NCT>
+__global__ void __launch_bounds__(256) k_conv_brick(ConvArgs a) {
+    __shared__ bf16x8 halo[kHalo * 4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kg = lane >> 4;
+    const int b = blockIdx.z;
+    const int co0 = blockIdx.y * 16 * NCT;
+    const int n = a.n;
+    const int nbx = n / kBX, nby = n / kBY;
+    const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+    const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+    f32x4 acc[4][NCT];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[g][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16* xb = a.x + (size_t)b * a.P * a.cin;
+    for (int ci0 = 0; ci0 < a.cin; ci0 += 32) {
+        __syncthreads();                      // the previous slice's reads are done
+        for (int i = threadIdx.x; i < kHalo * 4; i += 256) {
+            const int q = i >> 2, c = i & 3;
+            const int hx = q % kHX, hy = (q / kHX) % kHY, hz = q / (kHX * kHY);
+            int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            gx += gx < 0 ? n : 0; gx -= gx >= n ? n : 0;
+            gy += gy < 0 ? n : 0; gy -= gy >= n ? n : 0;
+            gz += gz < 0 ? n : 0; gz -= gz >= n ? n : 0;
+            const int p = (gz * n + gy) * n + gx;
+            halo[halo_slot(q, c)] = *reinterpret_cast<const bf16x8*>(xb + (size_t)p * a.cin + ci0 + 8 * c);
+        }
+        __syncthreads();
+        const bf16* wrow[NCT];
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) wrow[c] = a.w + (size_t)(co0 + 16 * c + col) * 27 * a.cin + ci0 + 8 * kg;
+        for (int tz = 0; tz < 3; ++tz)
+            for (int ty = 0; ty < 3; ++ty) {
+#pragma unroll
+                for (int tx = 0; tx < 3; ++tx) {
+                    const int t = (tz * 3 + ty) * 3 + tx;
+                    bf16x8 aw[NCT];
+#pragma unroll
+                    for (int c = 0; c < NCT; ++c) aw[c] = *reinterpret_cast<const bf16x8*>(wrow[c] + (size_t)t * a.cin);
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int q = ((wave + tz) * kHY + (g + ty)) * kHX + (col + tx);
+                        const bf16x8 xv = halo[halo_slot(q, kg)];
+#pragma unroll
+                        for (int c = 0; c < NCT; ++c) acc[g][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[c], xv, acc[g][c], 0, 0, 0);
+                    }
+                }
+            }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int p = ((z0 + wave) * n + (y0 + g)) * n + (x0 + col);
+        const size_t row = ((size_t)b * a.P + p) * a.cout;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            const int co = co0 + 16 * c + 4 * kg;
+            float z[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                z[j] = acc[g][c][j] + (a.bias ? a.bias[co + j] : 0.f);
                 if (a.relu) z[j] = fmaxf(z[j], 0.f);
             }
             if (a.zf) *reinterpret_cast<f32x4*>(a.zf + row + co) = f32x4{z[0], z[1], z[2], z[3]};
@@ -443,9 +541,24 @@ struct Layer {
 };
 
 int conv_launch(const ConvArgs& a, int B, hipStream_t s) {
+    if (a.cin % 32 || a.cout % 16 || a.cin < 32 || a.cout < 16 || a.P != a.n * a.n * a.n) return lfail(AHOM_E_ARG, "conv shape");
     int nct = 1;
     for (int c : {4, 3, 2, 1})
         if (a.cout % (16 * c) == 0) { nct = c; break; }
+    // AHOM_CONV_GATHER=1 keeps every grid on the per-tap gather kernel (parity tests of both)
+    const char* ge = getenv("AHOM_CONV_GATHER");
+    const bool gather_only = ge && ge[0] == '1';
+    if (a.n % kBX == 0 && !gather_only) {
+        // bricks tile the grid exactly (n multiple of 16)
+        dim3 grid((unsigned)((a.n / kBX) * (a.n / kBY) * (a.n / kBZ)), (unsigned)(a.cout / (16 * nct)), (unsigned)B);
+        switch (nct) {
+            case 4: hipLaunchKernelGGL(k_conv_brick<4>, grid, dim3(256), 0, s, a); break;
+            case 3: hipLaunchKernelGGL(k_conv_brick<3>, grid, dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(k_conv_brick<2>, grid, dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL(k_conv_brick<1>, grid, dim3(256), 0, s, a); break;
+        }
+        return LLAUNCH();
+    }
     dim3 grid((unsigned)((a.P + 127) / 128), (unsigned)(a.cout / (16 * nct)), (unsigned)B);
     switch (nct) {
         case 4: hipLaunchKernelGGL(k_conv<4>, grid, dim3(256), 0, s, a); break;
