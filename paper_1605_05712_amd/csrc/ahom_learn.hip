@@ -234,16 +234,24 @@ struct WgradArgs {
     const bf16* dz;   // [B][P][cout]  gradient at the layer output (pre-activation)
     float* part;      // [nchunk][cout][27][cin] partial sums
     int n, P, cin, cout, B;
-    int chunk;        // points per workgroup (multiple of 32)
+    int chunk;        // points per workgroup (multiple of the staging round)
 };
 
 // dW[co][t][ci] = sum_{b,p} dz[b][p][co] x[b][nbr(p,t)][ci] over one chunk of
-// (sample, point) pairs per workgroup; operands staged in LDS transposed to
-// [channel][32 points] so that each lane reads 8 consecutive points.
+// (sample, point) pairs per workgroup (a multiple of kWS points).  KS points
+// at a time (128, or 64 where 128 would pass 64 KB of LDS: cin + cout = 256)
+// are staged in LDS transposed to [channel][KS + 8]: each thread loads 8
+// channels of one point (16 B) and spreads them over 8 rows, so that each
+// MFMA lane then reads 8 consecutive points of one channel; the padded row
+// pitch puts the 16 rows a quarter-wave reads on distinct banks.
+constexpr int kWS = 128;
+
+template <int KS>
 __global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
+    constexpr int kWP = KS + 8;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    bf16* sdz = reinterpret_cast<bf16*>(smem_raw);           // [cout][32]
-    bf16* sx = sdz + (size_t)a.cout * 32;                    // [cin][32]
+    bf16* sdz = reinterpret_cast<bf16*>(smem_raw);           // [cout][kWP]
+    bf16* sx = sdz + (size_t)a.cout * kWP;                   // [cin][kWP]
     const int t = blockIdx.y;
     const int chunk_id = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -256,24 +264,32 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
     for (int i = 0; i < MAXT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int64_t total = (int64_t)a.B * a.P;
     const int64_t g0 = (int64_t)chunk_id * a.chunk;
-    for (int64_t g = g0; g < g0 + a.chunk && g < total; g += 32) {
-        // stage 32 points: dz[.][co] and x[nbr][ci], transposed
-        for (int e = threadIdx.x; e < 32 * a.cout; e += 256) {
-            const int pp = e / a.cout, c = e % a.cout;
+    const int vco = a.cout / 8, vci = a.cin / 8;     // 16 B vectors per point
+    for (int64_t g = g0; g < g0 + a.chunk && g < total; g += KS) {
+        for (int e = threadIdx.x; e < KS * vco; e += 256) {
+            const int pp = e / vco, v = e % vco;
             const int64_t gi = g + pp;
-            bf16 v = (bf16)0.f;
-            if (gi < total) v = a.dz[gi * a.cout + c];
-            sdz[c * 32 + pp] = v;
+            bf16x8 val;
+            if (gi < total) val = *reinterpret_cast<const bf16x8*>(a.dz + gi * a.cout + 8 * v);
+            else
+#pragma unroll
+                for (int j = 0; j < 8; ++j) val[j] = (bf16)0.f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sdz[(8 * v + j) * kWP + pp] = val[j];
         }
-        for (int e = threadIdx.x; e < 32 * a.cin; e += 256) {
-            const int pp = e / a.cin, c = e % a.cin;
+        for (int e = threadIdx.x; e < KS * vci; e += 256) {
+            const int pp = e / vci, v = e % vci;
             const int64_t gi = g + pp;
-            bf16 v = (bf16)0.f;
+            bf16x8 val;
             if (gi < total) {
                 const int bb = (int)(gi / a.P), p = (int)(gi % a.P);
-                v = a.x[((int64_t)bb * a.P + nbr(p, a.n, t)) * a.cin + c];
+                val = *reinterpret_cast<const bf16x8*>(a.x + ((int64_t)bb * a.P + nbr(p, a.n, t)) * a.cin + 8 * v);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) val[j] = (bf16)0.f;
             }
-            sx[c * 32 + pp] = v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sx[(8 * v + j) * kWP + pp] = val[j];
         }
         __syncthreads();
         // C[co][ci] += sum_k A[co][k] B[k][ci], k = point
@@ -282,9 +298,12 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(WgradArgs a) {
             const int tile = wave + 4 * i;
             if (tile >= ntile) break;
             const int co0 = (tile / tci) * 16, ci0 = (tile % tci) * 16;
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(sdz + (co0 + col) * 32 + 8 * kg);
-            const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sx + (ci0 + col) * 32 + 8 * kg);
-            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+#pragma unroll
+            for (int k0 = 0; k0 < KS; k0 += 32) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(sdz + (co0 + col) * kWP + k0 + 8 * kg);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(sx + (ci0 + col) * kWP + k0 + 8 * kg);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
@@ -310,13 +329,29 @@ __global__ void k_sum_parts(const float* part, int nchunk, int64_t n, float* out
     }
 }
 
-// per-chunk channel sums of dz (bias gradient partials): part[chunk][c]
-__global__ void k_bias_parts(const bf16* dz, int64_t total, int cout, int chunk, float* part) {
+// per-chunk channel sums of dz (bias gradient partials): part[chunk][c].
+// Thread t reads 8 channels (16 B) of every R-th point of the chunk, R = 256 /
+// (cout / 8); the R row sums are then added in row order (fixed order).
+__global__ void __launch_bounds__(256) k_bias_parts(const bf16* dz, int64_t total, int cout, int chunk, float* part) {
+    __shared__ float red[256 * 8];
     const int64_t g0 = (int64_t)blockIdx.x * chunk;
-    for (int c = threadIdx.x; c < cout; c += blockDim.x) {
-        float s = 0.f;
-        for (int64_t g = g0; g < g0 + chunk && g < total; ++g) s += (float)dz[g * cout + c];
-        part[(size_t)blockIdx.x * cout + c] = s;
+    const int nv = cout / 8, R = 256 / nv;
+    const int v = threadIdx.x % nv, r = threadIdx.x / nv;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (r < R)
+        for (int64_t g = g0 + r; g < g0 + chunk && g < total; g += R) {
+            const bf16x8 x = *reinterpret_cast<const bf16x8*>(dz + g * cout + 8 * v);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] += (float)x[j];
+        }
+    if (r < R)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[r * cout + 8 * v + j] = s[j];
+    __syncthreads();
+    for (int c = threadIdx.x; c < cout; c += 256) {
+        float t = 0.f;
+        for (int q = 0; q < R; ++q) t += red[q * cout + c];
+        part[(size_t)blockIdx.x * cout + c] = t;
     }
 }
 
@@ -516,9 +551,17 @@ __global__ void k_from_bf16(const bf16* s, float* d, int64_t n) {
 void wgrad_chunks(int64_t total, size_t nw, int* chunk, int* nchunk) {
     int64_t nc = std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)((16u << 20) / std::max<size_t>(nw, 1))));
     int64_t c = (total + nc - 1) / nc;
-    c = std::max<int64_t>(32, (c + 31) / 32 * 32);
+    c = std::max<int64_t>(kWS, (c + kWS - 1) / kWS * kWS);   // whole staging rounds per chunk
     *chunk = (int)c;
     *nchunk = (int)((total + c - 1) / c);
+}
+
+void wgrad_launch(const WgradArgs& w, int nchunk, hipStream_t s) {
+    const size_t lds128 = (size_t)(w.cin + w.cout) * (128 + 8) * 2;
+    if (lds128 <= 65536)
+        hipLaunchKernelGGL(k_conv_wgrad<128>, dim3(nchunk, 27), dim3(256), lds128, s, w);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad<64>, dim3(nchunk, 27), dim3(256), (size_t)(w.cin + w.cout) * (64 + 8) * 2, s, w);
 }
 
 unsigned grid_for(int64_t n, int bs = 256) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + bs - 1) / bs, 8192)); }
@@ -765,8 +808,7 @@ int conv_bwd(ahom_guess* g, int li, const bf16* x, const bf16* dz, int lvl, int 
     }
     WgradArgs w{};
     w.x = x; w.dz = dz; w.part = g->part; w.n = g->n >> lvl; w.P = P; w.cin = l.cin; w.cout = l.cout; w.B = B; w.chunk = chunk;
-    const size_t lds = (size_t)(l.cin + l.cout) * 32 * 2;
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunk, 27), dim3(256), lds, g->stream, w);
+    wgrad_launch(w, nchunk, g->stream);
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(nw)), dim3(256), 0, g->stream, g->part, nchunk, (int64_t)nw, g->g32 + l.w_off);
     // bias
     hipLaunchKernelGGL(k_bias_parts, dim3(nchunk), dim3(256), 0, g->stream, dz, total, l.cout, chunk, g->part);
@@ -1175,7 +1217,7 @@ int ahom_conv3d(int n, int batch, int cin, int cout, int mode, int relu, const f
     } else if (!rc && mode == 2) {
         WgradArgs wa{};
         wa.x = bx; wa.dz = by; wa.part = part; wa.n = n; wa.P = (int)P; wa.cin = cin; wa.cout = cout; wa.B = batch; wa.chunk = chunk;
-        hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunk, 27), dim3(256), (size_t)(cin + cout) * 32 * 2, 0, wa);
+        wgrad_launch(wa, nchunk, 0);
         hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(nw)), dim3(256), 0, 0, part, nchunk, (int64_t)nw, fo);
         if (hipGetLastError() != hipSuccess) rc = AHOM_E_DEVICE;
         if (!rc && hipMemcpy(out, fo, nw * 4, hipMemcpyDeviceToHost) != hipSuccess) rc = AHOM_E_DEVICE;

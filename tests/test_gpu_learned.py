@@ -1,8 +1,9 @@
 """GPU: learned initial guess (BF16 matrix-core network) against the FP64 oracle.
 
 Layer parity uses BF16-rounded inputs on both sides (the kernels accumulate in
-FP32); the whole network runs BF16 activations through 15 layers, so its loss
-and gradients are compared in norm at 5e-2.  The last test trains a network
+FP32); the whole network keeps BF16 activations and gradients between its 15
+layers, so its loss and gradients are compared in norm with the oracle taking
+the same BF16 storage and with the all-FP64 oracle.  The last test trains a network
 on solves the scheme itself produced and reports what the guess saves.
 """
 import sys
@@ -44,7 +45,9 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30))
 
 
-@pytest.mark.parametrize("n,cin,cout,batch", [(8, 32, 32, 1), (6, 64, 48, 2), (4, 32, 16, 1), (5, 96, 64, 1)])
+# n a multiple of 16 runs the LDS brick kernel, other n the per-tap gather kernel
+@pytest.mark.parametrize("n,cin,cout,batch", [(8, 32, 32, 1), (6, 64, 48, 2), (4, 32, 16, 1), (5, 96, 64, 1),
+                                              (16, 32, 32, 2), (16, 96, 48, 1), (32, 64, 64, 1), (16, 128, 16, 1)])
 def test_conv3d_forward_matches_oracle(n, cin, cout, batch):
     say("conv fwd", n, cin, cout, batch)
     r = np.random.default_rng(n * 1000 + cin)
@@ -61,7 +64,7 @@ def test_conv3d_forward_matches_oracle(n, cin, cout, batch):
             assert rel(y[s], cf_to_cl(ref)) < 1e-4, (relu, s)
 
 
-@pytest.mark.parametrize("n,cin,cout", [(8, 32, 32), (6, 64, 96), (4, 96, 64)])
+@pytest.mark.parametrize("n,cin,cout", [(8, 32, 32), (6, 64, 96), (4, 96, 64), (16, 64, 96), (32, 32, 32)])
 def test_conv3d_adjoint_and_weight_gradient_match_oracle(n, cin, cout):
     say("conv bwd", n, cin, cout)
     r = np.random.default_rng(7 * n + cout)
@@ -78,6 +81,26 @@ def test_conv3d_adjoint_and_weight_gradient_match_oracle(n, cin, cout):
     assert rel(db, dy[0].astype(np.float64).sum(axis=0)) < 1e-5
 
 
+def test_conv3d_brick_and_gather_kernels_agree(monkeypatch):
+    """32^3, 64 -> 32 channels, two samples, bias, ReLU and the adjoint: the
+    brick kernel and the per-tap gather kernel give the same FP32 results up to
+    summation order."""
+    n, cin, cout = 32, 64, 32
+    say("conv brick vs gather", n, cin, cout)
+    r = np.random.default_rng(3)
+    x = to_bf16(r.standard_normal((2, n ** 3, cin)))
+    w = to_bf16(r.standard_normal((cout, 27, cin)) * 0.1)
+    b = r.standard_normal(cout).astype(np.float32)
+    dy = to_bf16(r.standard_normal((2, n ** 3, cout)))
+    outs = []
+    for gather in ("0", "1"):
+        monkeypatch.setenv("AHOM_CONV_GATHER", gather)
+        outs.append((ahom.conv3d(n, cin, cout, 0, x=x, w=w, b=b, relu=True, batch=2),
+                     ahom.conv3d(n, cin, cout, 1, w=w, dy=dy, batch=2)))
+    for k in range(2):
+        assert rel(outs[0][k], outs[1][k]) < 1e-6, k
+
+
 def unit_strain_from_fluct(fl):
     """fluctuation (6, 6, P) -> total strain of the Mandel unit loads"""
     st = np.array(fl, dtype=np.float64)
@@ -86,8 +109,18 @@ def unit_strain_from_fluct(fl):
     return st
 
 
+def bf16_store(a):
+    return to_bf16(a).astype(np.float64)
+
+
 def test_network_loss_and_gradients_match_oracle():
-    """Whole network on 8^3 (levels 8, 4, 2, 1), two samples: loss and every layer's gradient."""
+    """Whole network on 8^3 (levels 8, 4, 2, 1), two samples: loss and every
+    layer's gradient.  Against the oracle with BF16 storage of what the network
+    keeps between layers (as the device does; labels BF16 too): 1e-3 loss,
+    3e-2 per layer and 2e-2 for the whole gradient, in norm.  Against the
+    all-FP64 oracle (BF16 weights only): 1e-2 loss, 5e-2 per layer; a stored
+    tensor carries up to 2^-9 relative rounding, and a gradient passes some 30
+    of them."""
     n = 8
     P = n ** 3
     say("network gradients", n)
@@ -106,24 +139,40 @@ def test_network_loss_and_gradients_match_oracle():
         g.add_sample(ph, lame, lam0, mu0, unit_strain_from_fluct(fl))
         samples.append((ph, lame, lam0, mu0, fl))
     loss, grad = g.gradients([0, 1])
-    ref_loss = 0.0
-    ref_grads = None
-    for ph, lame, lam0, mu0, fl in samples:
-        x = NN.net_input(ph, lame, lam0, mu0, n)
-        out, cache = NN.forward(params_b, x)
-        lab = NN.label_from_strain(fl, n)
-        L, dout = NN.energy_loss(out, lab, lam0, mu0, batch=2)
-        ref_loss += L
-        gr = NN.backward(params_b, cache, dout)
-        ref_grads = gr if ref_grads is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(ref_grads, gr)]
-    print("loss", loss, "oracle", ref_loss, flush=True)
-    assert abs(loss - ref_loss) / ref_loss < 2e-2
     mine = NN.unflatten(grad)
-    for k, ((gw, gb), (rw, rb)) in enumerate(zip(mine, ref_grads)):
-        ew = np.linalg.norm(gw - rw) / np.linalg.norm(rw)
-        eb = np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)
-        print(f"layer {k}: weight-gradient error {ew:.2e}, bias {eb:.2e}", flush=True)
-        assert ew < 5e-2 and eb < 5e-2, k
+    worst = {}
+    for store, lb in ((bf16_store, 1e-3), (None, 1e-2)):
+        ref_loss = 0.0
+        ref_grads = None
+        for ph, lame, lam0, mu0, fl in samples:
+            x = NN.net_input(ph, lame, lam0, mu0, n)
+            out, cache = NN.forward(params_b, x, store=store)
+            lab = NN.label_from_strain(fl, n)
+            if store:
+                lab = store(lab)
+            L, dout = NN.energy_loss(out, lab, lam0, mu0, batch=2)
+            ref_loss += L
+            gr = NN.backward(params_b, cache, dout, store=store)
+            ref_grads = gr if ref_grads is None else [(a[0] + b[0], a[1] + b[1]) for a, b in zip(ref_grads, gr)]
+        kind = "BF16 storage" if store else "FP64"
+        print(f"loss {loss} oracle ({kind}) {ref_loss}", flush=True)
+        assert abs(loss - ref_loss) / ref_loss < lb
+        errs = []
+        for k, ((gw, gb), (rw, rb)) in enumerate(zip(mine, ref_grads)):
+            ew = np.linalg.norm(gw - rw) / np.linalg.norm(rw)
+            eb = np.linalg.norm(gb - rb) / max(np.linalg.norm(rb), 1e-30)
+            errs.append(max(ew, eb))
+            print(f"layer {k} ({kind}): weight-gradient error {ew:.2e}, bias {eb:.2e}", flush=True)
+        flat_m = np.concatenate([np.concatenate([gw.ravel(), gb.ravel()]) for gw, gb in mine])
+        flat_r = np.concatenate([np.concatenate([rw.ravel(), rb.ravel()]) for rw, rb in ref_grads])
+        tot = np.linalg.norm(flat_m - flat_r) / np.linalg.norm(flat_r)
+        print(f"whole gradient ({kind}): error {tot:.2e}", flush=True)
+        worst[kind] = (max(errs), tot)
+    # with the device's storage format the remaining differences are roundings
+    # that FP32 accumulation (device) and FP64 (oracle) decide differently, one
+    # BF16 ulp each, compounded over the ~30 stages between output and layer 0
+    assert worst["BF16 storage"][0] < 3e-2 and worst["BF16 storage"][1] < 2e-2, worst
+    assert worst["FP64"][0] < 5e-2, worst
 
 
 def test_adam_steps_match_oracle():
