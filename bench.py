@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lattice-point updates/s per iteration; time-to-1e-6 residual vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+MANDEL_IJ = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
 
 
 def mandel_loads():
@@ -360,7 +361,7 @@ def conductivity_workload(ahom, n=128, steps=20, ttt=True):
     if ttt:
         t = {}
         for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
-                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG), ("cg_fp32", ahom.FP32_MIXED, ahom.SCHEME_CG)):
             S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=3000, check_period=16, resid_period=4, scheme=scheme,
                             physics=ahom.CONDUCTIVITY)
             S.set_conductivity(kv, ph)
@@ -405,25 +406,28 @@ def precision_workload(ahom, n=256):
     out = {}
     Cs = {}
     for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
-                               ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+                               ("cg_fp64", ahom.FP64, ahom.SCHEME_CG), ("cg_fp32", ahom.FP32_MIXED, ahom.SCHEME_CG)):
         S = ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, check_period=16, resid_period=4, scheme=scheme)
         S.set_material(lame, ph)
         C, it = S.effective_stiffness()
         dev_ms, _ = S.last_timing()
         out[name] = dict(ms=round(dev_ms, 1), iters=[int(v) for v in it])
-        if name == "fp32":
+        if prec == ahom.FP32_MIXED:
             out[name]["restarts"] = int(S.last_restarts())
         Cs[name] = C
         print(f"[bench] precision {n}^3 {name}: {dev_ms:.1f} ms, iters {list(it)}", file=sys.stderr, flush=True)
         del S
     err = np.abs(Cs["fp32"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
     err_cg = np.abs(Cs["cg_fp64"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
+    err_cg32 = np.abs(Cs["cg_fp32"] - Cs["fp64"]) / np.abs(Cs["fp64"]).max()
     return dict(workload=f"spheres diag({n},{n},{n}), vf 0.3, contrast 100, 6 loads, tol 1e-6",
-                throughput=thr, fp64=out["fp64"], fp32=out["fp32"], cg_fp64=out["cg_fp64"],
+                throughput=thr, fp64=out["fp64"], fp32=out["fp32"], cg_fp64=out["cg_fp64"], cg_fp32=out["cg_fp32"],
                 speedup_fp32_vs_fp64=round(out["fp64"]["ms"] / out["fp32"]["ms"], 3),
                 speedup_cg_vs_fp64=round(out["fp64"]["ms"] / out["cg_fp64"]["ms"], 3),
+                speedup_cg_fp32_vs_fp64=round(out["fp64"]["ms"] / out["cg_fp32"]["ms"], 3),
                 ceff_max_entry_err_fp32_vs_fp64_over_max_abs=float(err.max()),
-                ceff_max_entry_diff_cg_vs_fp64_over_max_abs=float(err_cg.max()), volume_fraction=float(ph.mean()))
+                ceff_max_entry_diff_cg_vs_fp64_over_max_abs=float(err_cg.max()),
+                ceff_max_entry_diff_cg_fp32_vs_fp64_over_max_abs=float(err_cg32.max()), volume_fraction=float(ph.mean()))
 
 
 _MEMBER_PTS = None
@@ -506,7 +510,8 @@ def learned_workload(ahom, ntrain, steps, n=64, ntest=4, chunk=512, workers=12, 
     for name, prec, guess, scheme in (("fp64", ahom.FP64, False, ahom.SCHEME_BASIC),
                                       ("fp32", ahom.FP32_MIXED, False, ahom.SCHEME_BASIC),
                                       ("fp32_guess", ahom.FP32_MIXED, True, ahom.SCHEME_BASIC),
-                                      ("cg_fp64", ahom.FP64, False, ahom.SCHEME_CG)):
+                                      ("cg_fp64", ahom.FP64, False, ahom.SCHEME_CG),
+                                      ("cg_fp32", ahom.FP32_MIXED, False, ahom.SCHEME_CG)):
         solvers[name] = (ahom.Solver(P, precision=prec, tol=1e-6, max_iter=5000, resid_period=4, scheme=scheme,
                                      guess_probe=17 if guess else 0), guess)
     d_init = ahom.DeviceArray((6, 6, P.m), np.float64)
@@ -525,15 +530,22 @@ def learned_workload(ahom, ntrain, steps, n=64, ntest=4, chunk=512, workers=12, 
             if guess:
                 g.infer(ph, lame, lam0, mu0, loads, out=d_init)     # device to device, no host copies
             o = Sx.solve_device(loads, init=d_init if guess else None)
-            row[name] = dict(ms=(time.perf_counter() - t0) * 1e3, iters=float(o["iters"].mean()))
+            row[name] = dict(ms=(time.perf_counter() - t0) * 1e3, iters=float(o["iters"].mean()),
+                             C=np.array([[o["mean_stress"][k][i, j] for k in range(6)] for i, j in MANDEL_IJ]))
             if guess:
                 kept += int(Sx.last_starts(6).sum())
         warm = False
+        Cref = row["fp64"]["C"]
+        for name in row:
+            row[name]["cerr"] = float(np.abs(row[name].pop("C") - Cref).max() / np.abs(Cref).max())
         rows.append(row)
+        if len(rows) % 50 == 0:
+            print(f"[bench] learned: {len(rows)}/{ntest} held-out seeds", file=sys.stderr, flush=True)
     pool.close()
     pool.join()
     mean = {k: float(np.mean([r[k]["ms"] for r in rows])) for k in rows[0]}
     its = {k: float(np.mean([r[k]["iters"] for r in rows])) for k in rows[0]}
+    cerr = {k: float(np.max([r[k]["cerr"] for r in rows])) for k in rows[0] if k != "fp64"}
     better = int(sum(r["fp32_guess"]["iters"] < r["fp32"]["iters"] for r in rows))
     worse = int(sum(r["fp32_guess"]["iters"] > r["fp32"]["iters"] for r in rows))
     return dict(n=n, train_solves=ntrain, first_seed=first_seed, chunk=chunk, steps=int(len(losses)), data_s=round(t_data, 1),
@@ -542,10 +554,12 @@ def learned_workload(ahom, ntrain, steps, n=64, ntest=4, chunk=512, workers=12, 
                 loss_first=float(losses[:10].mean()), loss_last=float(losses[-10:].mean()),
                 held_out=ntest, mean_ms={k: round(v, 3) for k, v in mean.items()},
                 mean_iters={k: round(v, 2) for k, v in its.items()}, guess_probe=17,
+                ceff_max_entry_diff_vs_fp64_over_max_abs=cerr,
                 guess_kept_loads=f"{kept}/{6 * ntest}", seeds_guess_fewer_iters=better, seeds_guess_more_iters=worse,
                 speedup_guess_fp32_vs_fp64=round(mean["fp64"] / mean["fp32_guess"], 3),
                 speedup_fp32_vs_fp64=round(mean["fp64"] / mean["fp32"], 3),
-                speedup_cg_fp64_vs_fp64=round(mean["fp64"] / mean["cg_fp64"], 3))
+                speedup_cg_fp64_vs_fp64=round(mean["fp64"] / mean["cg_fp64"], 3),
+                speedup_cg_fp32_vs_fp64=round(mean["fp64"] / mean["cg_fp32"], 3))
 
 
 def main():
@@ -576,7 +590,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     ap.add_argument("--no-cond", action="store_true", help="skip the conductivity workload")
-    ap.add_argument("--leg", choices=["hashin128", "spheres256", "rank1", "cond128"],
+    ap.add_argument("--leg", choices=["hashin128", "spheres256", "rank1", "cond128", "cg128"],
                     help="profiling runs: only the fixed-iteration throughput of one workload (--steps iterations, "
                          "FP64 then FP32 unless --fp64-only or --fp32-only), one JSON line, then exit")
     ap.add_argument("--fp32-only", action="store_true", help="with --leg: FP32 only")
@@ -608,10 +622,10 @@ def main():
             precs = precs[1:]
         if args.leg == "hashin128":
             P, ph, lame, _ = workload(128)
-            res = _throughput(ahom, P, lame, ph, args.steps, "hashin 128^3", precs=precs)
+            res = _throughput(ahom, P, lame, ph, args.steps, "hashin 128^3", precs=precs, roofline=True)
         elif args.leg == "spheres256":
             P, ph, lame = spheres_inputs(ahom, 256)
-            res = _throughput(ahom, P, lame, ph, args.steps, "spheres 256^3", precs=precs)
+            res = _throughput(ahom, P, lame, ph, args.steps, "spheres 256^3", precs=precs, roofline=True)
         elif args.leg == "rank1":
             g = json.load(open(os.path.join(ROOT, "tests", "golden", "hashin_c2.json")))
             M = np.array(json.load(open(os.path.join(ROOT, "tests", "golden", "rank1_c2.json")))["M"], dtype=np.int64)
@@ -620,11 +634,25 @@ def main():
             geom = dict(c=np.array(g["c"]), rho_c=g["rho_c"], rho_e=g["rho_e"], R=np.array(g["R"]))
             ph = synth.hashin_phase(P.points(), P.m, geom)
             lame = np.array([g["lame_core"], g["lame_coating"], g["lame_matrix"]])
-            res = _throughput(ahom, P, lame, ph, args.steps, "rank-1 2^21", precs=precs)
-        else:
+            res = _throughput(ahom, P, lame, ph, args.steps, "rank-1 2^21", precs=precs, roofline=True)
+        elif args.leg == "cond128":
             P, ph, _, _ = workload(128)
             res = _throughput(ahom, P, np.array([10.0, 0.5, 1.0]), ph, args.steps, "conductivity 128^3", precs=precs,
-                              physics=ahom.CONDUCTIVITY, loads=np.eye(3))
+                              physics=ahom.CONDUCTIVITY, loads=np.eye(3), roofline=True)
+        else:
+            # conjugate gradients: `steps` FP64 updates of the 6 Mandel loads (the inner FP32
+            # solves of the mixed scheme run the same kernels in float)
+            P, ph, lame, _ = workload(128)
+            res = {}
+            for name, prec in precs:
+                for rep in range(2):      # the first solve tunes, the second is timed
+                    S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=args.steps, check_period=args.steps,
+                                    scheme=ahom.SCHEME_CG, refine=1e-30)
+                    S.set_material(lame, ph)
+                    S.solve(mandel_loads())
+                    ms, _ = S.last_timing()
+                    del S
+                res[name] = dict(ms_per_update=round(ms / args.steps, 4))
         print(json.dumps(dict(leg=args.leg, steps=args.steps, **res)))
         return
 
@@ -683,7 +711,7 @@ def main():
         ttt = {}
         Cs = {}
         for name, prec, scheme in (("fp64", ahom.FP64, ahom.SCHEME_BASIC), ("fp32", ahom.FP32_MIXED, ahom.SCHEME_BASIC),
-                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG)):
+                                   ("cg_fp64", ahom.FP64, ahom.SCHEME_CG), ("cg_fp32", ahom.FP32_MIXED, ahom.SCHEME_CG)):
             S = make(prec, 1e-6, 3000, 16, resid_period=args.ttt_resid_period, scheme=scheme)
             C, it = S.effective_stiffness()
             dev_ms, enq = S.last_timing()
@@ -694,7 +722,9 @@ def main():
             del S
         ttt["speedup_fp32_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["fp32"]["ms"], 3)
         ttt["speedup_cg_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["cg_fp64"]["ms"], 3)
+        ttt["speedup_cg_fp32_vs_fp64"] = round(ttt["fp64"]["ms"] / ttt["cg_fp32"]["ms"], 3)
         ttt["ceff_max_entry_diff_cg_vs_fp64"] = float(np.abs(Cs["cg_fp64"] - Cs["fp64"]).max() / np.abs(Cs["fp64"]).max())
+        ttt["ceff_max_entry_diff_cg_fp32_vs_fp64"] = float(np.abs(Cs["cg_fp32"] - Cs["fp64"]).max() / np.abs(Cs["fp64"]).max())
 
     cpu = None
     batch = None
