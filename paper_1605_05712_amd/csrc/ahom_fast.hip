@@ -1426,19 +1426,22 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::N, V>::THREADS)) kf_
                 tt[1] = C{T01.x * xi[0] + T11.x * xi[1], T01.y * xi[0] + T11.y * xi[1]};
             }
             const int64_t spos = c0 * L + e;
+            // residual and Cauchy terms of this frequency; accumulated once
+            // below, outside the branches (per-branch updates of the two sums
+            // were merged by the compiler into a store through a selected
+            // address, which put both sums in scratch memory)
+            double r2 = 0.0, c2 = 0.0;
             if (a.cg_alpha) {
                 // conjugate gradients: traction of the updated iterate t + alpha t_p
                 const T cg_a = (T)a.cg_alpha[load];
-                double r2 = 0.0;
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
                     const C nt = C{oldv[q][c].x + cg_a * tt[c].x, oldv[q][c].y + cg_a * tt[c].y};
                     r2 += (double)nt.x * (double)nt.x + (double)nt.y * (double)nt.y;
                     stg(tb + (int64_t)c * P.S + spos, nt);
                 }
-                res += (double)kb[j * 4 + 3] * r2;
             } else if (chk) {
-                double r2 = 0.0, xdx = 0.0, xdy = 0.0;
+                double xdx = 0.0, xdy = 0.0;
 #pragma unroll
                 for (int c = 0; c < NT; ++c) {
                     const double dx = (double)tt[c].x - (double)oldv[q][c].x, dy = (double)tt[c].y - (double)oldv[q][c].y;
@@ -1451,10 +1454,12 @@ __global__ void __launch_bounds__((Geo<T, L, Comp<DIM, PH>::N, V>::THREADS)) kf_
                         reinterpret_cast<float2*>(a.dneg)[o] = float2{(float)-dx, (float)-dy};
                     }
                 }
-                res += (double)kb[j * 4 + 3] * r2;
                 // Cauchy term |eps_hat(n+1) - eps_hat(n)|^2 up to 1 / (2 mu0^2)
-                cau += (double)kb[j * 4 + 3] * (r2 + cau_c1 * (xdx * xdx + xdy * xdy));
+                c2 = r2 + cau_c1 * (xdx * xdx + xdy * xdy);
             }
+            const double wk = (double)kb[j * 4 + 3];
+            res += wk * r2;
+            cau += wk * c2;
             if (wrt && !a.cg_alpha) {
 #pragma unroll
                 for (int c = 0; c < NT; ++c) stg(tb + (int64_t)c * P.S + spos, tt[c]);
