@@ -98,8 +98,11 @@ typedef struct ahom_config {
                            positive definite on compatible fields.  Each update costs one
                            sweep of the passes plus two vector kernels; the stop test, the
                            history and the outputs are those of the Basic Scheme (r(n) of
-                           eps(n) = eps_bar + x_n; n = updates performed).  Single-pattern
-                           solver, AHOM_STOP_RESIDUAL, no init.  In AHOM_FP32_MIXED: defect
+                           eps(n) = eps_bar + x_n; n = updates performed).  The residual
+                           and <sigma> follow their own recurrences, so a FP64 solve with
+                           no field output (strain_out NULL, ahom_effective_stiffness) does
+                           not form x at all.  Single-pattern solver, AHOM_STOP_RESIDUAL,
+                           no init.  In AHOM_FP32_MIXED: defect
                            correction — one FP64 sweep gives the exact residual field and
                            equilibrium residual of the FP64 iterate, an FP32 CG solve of the
                            correction runs until its residual has dropped by `refine` (C0

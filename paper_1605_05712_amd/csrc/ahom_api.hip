@@ -217,6 +217,7 @@ struct ahom_solver {
     double* d_c0tab = nullptr;
     int cg_nblk = 1;
     double cg_rr_stop = 0.0;       // > 0: inner solves of the mixed-precision scheme
+    bool cg_no_x = false;          // the current CG solve returns no field: x is not formed
     // per-stage settings read by the launches
     double cur_tol = 0.0;
     const void* spec_toff = nullptr;
@@ -522,6 +523,7 @@ int cg_sweep(ahom_solver* s, int nload, int start) {
     c.max_iter = s->cfg.max_iter;
     c.start = start;
     c.rr_stop = s->cg_rr_stop;
+    c.no_x = s->cg_no_x ? 1 : 0;
     if (start == 2) {
         // start of an inner solve from a given residual field r(0), stored
         // in buf1: r = p = r(0), <r, r>_C0 (no operator sweep)
@@ -787,8 +789,11 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
     if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
     f.buf = s->d_x;                    // x(0) = 0: the iterate eps_bar
     if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    // C_eff alone (no field asked) needs only the residual and mean-stress
+    // recurrences: the iterate is then not formed
+    s->cg_no_x = strain_out == nullptr;
     HIPCHK(hipEventRecord(s->ev0, st));
-    if ((rc = cg_sweep(s, n_load, 1))) return rc;
+    if ((rc = cg_sweep(s, n_load, 1))) { s->cg_no_x = false; return rc; }
     int enq = 1;
     const int limit = s->cfg.max_iter + 1;
     bool all_done = false;
@@ -801,10 +806,11 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
         if (enq > limit + 2 * s->cfg.check_period) return fail(AHOM_E_DEVICE, "loop control did not terminate");
         const int k = std::min(s->cfg.check_period, std::max(1, limit - enq + 1));
         for (int i = 0; i < k; ++i) {
-            if ((rc = cg_sweep(s, n_load, 0))) return rc;
+            if ((rc = cg_sweep(s, n_load, 0))) { s->cg_no_x = false; return rc; }
             ++enq;
         }
     }
+    s->cg_no_x = false;
     float ms = 0.f;
     HIPCHK(hipEventRecord(s->ev1, st));
     HIPCHK(hipEventSynchronize(s->ev1));

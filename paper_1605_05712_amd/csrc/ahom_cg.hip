@@ -78,7 +78,9 @@ __global__ void __launch_bounds__(kWG) k_cg_alpha(CgArgs a) {
 
 // Start: r = p = q (q = -Gamma0 C eps_bar, the operator output), no x update.
 // Update: x += alpha p, r += alpha q (q = -A p).  Both: partial sums of
-// <r, r>_C0 per workgroup.
+// <r, r>_C0 per workgroup.  The iteration itself never reads x (the residual
+// and the mean stress follow their own recurrences), so with no_x the x
+// update and its 3 of the update's 6 field streams are left out.
 template <typename T, int DIM, int PH>
 __global__ void __launch_bounds__(kWG) k_cg_update(CgArgs a) {
     using C = typename CT<T>::t;
@@ -107,9 +109,11 @@ __global__ void __launch_bounds__(kWG) k_cg_update(CgArgs a) {
                 r = q;
                 P[i] = q;
             } else {
-                const C p = P[i];
-                const C x = X[i];
-                X[i] = C{x.x + al * p.x, x.y + al * p.y};
+                if (!a.no_x) {
+                    const C p = P[i];
+                    const C x = X[i];
+                    X[i] = C{x.x + al * p.x, x.y + al * p.y};
+                }
                 const C r0 = R[i];
                 r = C{r0.x + al * q.x, r0.y + al * q.y};
             }

@@ -214,6 +214,7 @@ struct CgArgs {
     double tol;
     int max_iter;
     int start;                // 1: the start (r(0), p_0 = r_0), 0: an update
+    int no_x;                 // 1: the iterate x is not formed (no field output asked)
     // > 0: an inner solve of the mixed-precision scheme: the recorded residual
     // is sqrt(<r, r>_C0 / <r(0), r(0)>_C0) and the stop is that ratio <= rr_stop
     double rr_stop;
