@@ -706,7 +706,8 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
             FastGeom fg4;
             const bool rr_ok = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, v, &fg4, s->phys);
             s->v_real = rr_ok ? v : 0;          // variant 4 exists for the real-space pass only
-            s->v_spec = v < 4 ? v : 0;
+            FastGeom fgs;
+            s->v_spec = (v < 4 || ahom_fast_geom(s->prec, FAST_SPEC, s->dim, P.ax[P.D - 1].len, v, &fgs, s->phys)) ? v : 0;
             for (int a = 0; a < AHOM_MAX_AXES; ++a) s->v_axis[a] = v < 4 ? v : 0;
             s->tuned = true;
         }
@@ -714,7 +715,7 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
         // kernels another run tuned); a variant a pass lacks falls back to 0
         const char* penv = getenv("AHOM_FAST_VARIANTS");
         int vr = -1, vs = -1, va = -1;
-        if (penv && std::sscanf(penv, "%d,%d,%d", &vr, &vs, &va) == 3 && vr >= 0 && vr <= 4 && vs >= 0 && vs <= 3 &&
+        if (penv && std::sscanf(penv, "%d,%d,%d", &vr, &vs, &va) == 3 && vr >= 0 && vr <= 4 && vs >= 0 && vs <= 4 &&
             va >= 0 && va <= 3) {
             FastGeom fgp;
             s->v_real = ahom_fast_geom(s->prec, FAST_REAL, s->dim, P.ax[0].len, vr, &fgp, s->phys) ? vr : 0;

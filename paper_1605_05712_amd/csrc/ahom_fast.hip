@@ -161,7 +161,8 @@ template <typename T, int L, int NF, int V = 0> struct Geo {
     static constexpr int by_lds = (50 * 1024) / (NF * CS * es);
     static constexpr int by_thr = 512 / (NF * N1);
     static constexpr int NCMAX = pow2floor((by_lds < by_thr ? by_lds : by_thr) < 1 ? 1 : (by_lds < by_thr ? by_lds : by_thr));
-    static constexpr int NC = (V & 1) && NCMAX > 1 ? NCMAX / 2 : NCMAX;
+    // V = 4 (spectral pass only): quarter-width tiles, one per workgroup
+    static constexpr int NC = V == 4 ? (NCMAX >= 4 ? NCMAX / 4 : 1) : ((V & 1) && NCMAX > 1 ? NCMAX / 2 : NCMAX);
     static constexpr bool PERSIST = (V & 2) != 0;
     static constexpr int THREADS = ((NF * NC * N1 + 63) / 64) * 64;
     static constexpr int TILE = NF * NC * CS;  // complex elements of LDS tile
@@ -1711,7 +1712,12 @@ int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream
 
 template <typename T>
 bool geom_T(int kind, int dim, int L, int v, FastGeom* g, int phys) {
-    if (v == kRRVariant) return kind == FAST_REAL && phys == PHYS_ELASTIC && rr_length(L) && geom_rr_T<T>(dim, L, g);
+    if (v == kRRVariant) {
+        // variant 4: the register-resident real-space pass, the quarter-width spectral pass
+        if (kind == FAST_REAL) return phys == PHYS_ELASTIC && rr_length(L) && geom_rr_T<T>(dim, L, g);
+        if (kind != FAST_SPEC) return false;
+        return tuned_length(L) ? geom_TV<T, 4>(kind, dim, L, g, phys) : geom_TV<T, 0>(kind, dim, L, g, phys);
+    }
     if (v > kRRVariant) return false;
     if (!tuned_length(L)) v = 0;
     switch (v) {
@@ -1744,17 +1750,20 @@ AHOM_INST_AXIS(float, 0) AHOM_INST_AXIS(float, 1) AHOM_INST_AXIS(float, 2) AHOM_
 #elif AHOM_FAST_PART == 4
 AHOM_INST_SPEC(double, 0, PHYS_ELASTIC) AHOM_INST_SPEC(double, 1, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 5
-AHOM_INST_SPEC(double, 2, PHYS_ELASTIC) AHOM_INST_SPEC(double, 3, PHYS_ELASTIC)
+AHOM_INST_SPEC(double, 2, PHYS_ELASTIC) AHOM_INST_SPEC(double, 3, PHYS_ELASTIC) AHOM_INST_SPEC(double, 4, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 6
 AHOM_INST_SPEC(float, 0, PHYS_ELASTIC) AHOM_INST_SPEC(float, 1, PHYS_ELASTIC) AHOM_INST_SPEC(float, 2, PHYS_ELASTIC) AHOM_INST_SPEC(float, 3, PHYS_ELASTIC)
+AHOM_INST_SPEC(float, 4, PHYS_ELASTIC)
 #elif AHOM_FAST_PART == 8
 AHOM_INST_REAL(double, 0, PHYS_THERMAL) AHOM_INST_REAL(double, 1, PHYS_THERMAL) AHOM_INST_REAL(double, 2, PHYS_THERMAL) AHOM_INST_REAL(double, 3, PHYS_THERMAL)
 #elif AHOM_FAST_PART == 9
 AHOM_INST_REAL(float, 0, PHYS_THERMAL) AHOM_INST_REAL(float, 1, PHYS_THERMAL) AHOM_INST_REAL(float, 2, PHYS_THERMAL) AHOM_INST_REAL(float, 3, PHYS_THERMAL)
 #elif AHOM_FAST_PART == 10
 AHOM_INST_SPEC(double, 0, PHYS_THERMAL) AHOM_INST_SPEC(double, 1, PHYS_THERMAL) AHOM_INST_SPEC(double, 2, PHYS_THERMAL) AHOM_INST_SPEC(double, 3, PHYS_THERMAL)
+AHOM_INST_SPEC(double, 4, PHYS_THERMAL)
 #elif AHOM_FAST_PART == 11
 AHOM_INST_SPEC(float, 0, PHYS_THERMAL) AHOM_INST_SPEC(float, 1, PHYS_THERMAL) AHOM_INST_SPEC(float, 2, PHYS_THERMAL) AHOM_INST_SPEC(float, 3, PHYS_THERMAL)
+AHOM_INST_SPEC(float, 4, PHYS_THERMAL)
 #elif AHOM_FAST_PART == 7
 template <typename T>
 int real_RR(int dim, int L, const RealArgs& a, int64_t total, int ncu, hipStream_t s) {
@@ -1775,6 +1784,10 @@ template int real_RR<float>(int, int, const RealArgs&, int64_t, int, hipStream_t
 #else
 AHOM_DECL_TV(double, 0) AHOM_DECL_TV(double, 1) AHOM_DECL_TV(double, 2) AHOM_DECL_TV(double, 3)
 AHOM_DECL_TV(float, 0) AHOM_DECL_TV(float, 1) AHOM_DECL_TV(float, 2) AHOM_DECL_TV(float, 3)
+extern template int spec_TV<double, 4, PHYS_ELASTIC>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+extern template int spec_TV<double, 4, PHYS_THERMAL>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+extern template int spec_TV<float, 4, PHYS_ELASTIC>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
+extern template int spec_TV<float, 4, PHYS_THERMAL>(int, int, const SpecArgs&, int64_t, int, hipStream_t);
 extern template int real_RR<double>(int, int, const RealArgs&, int64_t, int, hipStream_t);
 extern template int real_RR<float>(int, int, const RealArgs&, int64_t, int, hipStream_t);
 #endif
@@ -1848,6 +1861,15 @@ int ahom_launch_fast_axis(int prec, int dir, int L, int variant, const AxisArgs&
 
 int ahom_launch_fast_spec(int prec, int dim, int L, int variant, const SpecArgs& a, int64_t total, int ncu, hipStream_t s) {
     int rc;
+    if (variant == 4) {   // quarter-width tiles (tuned lengths only; shorter axes run variant 0)
+        if (prec == 0)
+            rc = a.phys == PHYS_THERMAL ? spec_TV<double, 4, PHYS_THERMAL>(dim, L, a, total, ncu, s)
+                                        : spec_TV<double, 4, PHYS_ELASTIC>(dim, L, a, total, ncu, s);
+        else
+            rc = a.phys == PHYS_THERMAL ? spec_TV<float, 4, PHYS_THERMAL>(dim, L, a, total, ncu, s)
+                                        : spec_TV<float, 4, PHYS_ELASTIC>(dim, L, a, total, ncu, s);
+        return rc == 0 && hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     auto run = [&]() -> int {
         if (a.phys == PHYS_THERMAL) AHOM_VPSWITCH(spec_TV, PHYS_THERMAL, dim, L, a, total, ncu, s);
         AHOM_VPSWITCH(spec_TV, PHYS_ELASTIC, dim, L, a, total, ncu, s);
