@@ -101,8 +101,11 @@ typedef struct ahom_config {
                            eps(n) = eps_bar + x_n; n = updates performed).  The residual
                            and <sigma> follow their own recurrences, so a FP64 solve with
                            no field output (strain_out NULL, ahom_effective_stiffness) does
-                           not form x at all.  Single-pattern solver, AHOM_STOP_RESIDUAL,
-                           no init.  In AHOM_FP32_MIXED: defect
+                           not form x at all.  An initial guess (ahom_solve init) starts CG
+                           from x_0 = P init, its projection Gamma0 C0 init onto compatible
+                           zero-mean fields (any field is accepted; one more operator sweep);
+                           guess_probe does not apply.  Single-pattern solver,
+                           AHOM_STOP_RESIDUAL.  In AHOM_FP32_MIXED: defect
                            correction — one FP64 sweep gives the exact residual field and
                            equilibrium residual of the FP64 iterate, an FP32 CG solve of the
                            correction runs until its residual has dropped by `refine` (C0

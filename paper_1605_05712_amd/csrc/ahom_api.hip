@@ -761,13 +761,88 @@ int ensure_ref64(ahom_solver* s, int nload) {
     return r->autotune(nload);
 }
 
-int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
-                   double* mean_out, int mem_flags);
+// The homogeneous reference medium of solver s (every point phase 0, table
+// entry C0 = (lambda0, mu0), or (k0, k0) for conductivity), in which a CG start
+// sweep is the projection: r = -Gamma0 C0 buf0 = -P buf0.
+int ensure_c0_medium(ahom_solver* s) {
+    if (!s->d_zero_phase) {
+        HIPCHK(hipMalloc((void**)&s->d_zero_phase, (size_t)s->pat->sf.m));
+        HIPCHK(hipMemset(s->d_zero_phase, 0, (size_t)s->pat->sf.m));
+        HIPCHK(hipMalloc((void**)&s->d_c0tab, 2 * sizeof(double)));
+    }
+    const double c0[2] = {s->lam0, s->mu0};
+    HIPCHK(hipMemcpy(s->d_c0tab, c0, sizeof c0, hipMemcpyHostToDevice));
+    return AHOM_OK;
+}
+
+// r->d_r = -P (r->d_buf0): one FP64 CG start sweep of r in the reference
+// medium of `owner` (r's own material pointers are restored afterwards).
+// Clobbers r's state, traction and buf1.
+int project_sweep(ahom_solver* owner, ahom_solver* r, int n_load) {
+    const Plan& P = r->pat->plan;
+    hipStream_t st = r->stream;
+    uint8_t* sv_ph = r->d_phase;
+    uint8_t* sv_pht = r->d_phase_t;
+    double* sv_tab = r->d_lame_tab;
+    double* sv_pts = r->d_lame_pts;
+    double* sv_ptst = r->d_lame_pts_t;
+    const int sv_np = r->n_phase;
+    const bool sv_nox = r->cg_no_x;
+    r->d_phase = r->d_phase_t = owner->d_zero_phase;
+    r->d_lame_tab = owner->d_c0tab;
+    r->d_lame_pts = r->d_lame_pts_t = nullptr;
+    r->n_phase = 1;
+    r->cg_no_x = true;
+    int rc = ahom_launch_reset(r->d_st, n_load, st) || ahom_launch_zero(AHOM_FP64, r->d_tbuf, (int64_t)n_load * r->nt * P.S, st)
+                 ? fail(AHOM_E_DEVICE, "reset")
+                 : cg_sweep(r, n_load, 1);
+    r->d_phase = sv_ph;
+    r->d_phase_t = sv_pht;
+    r->d_lame_tab = sv_tab;
+    r->d_lame_pts = sv_pts;
+    r->d_lame_pts_t = sv_ptst;
+    r->n_phase = sv_np;
+    r->cg_no_x = sv_nox;
+    return rc;
+}
+
+// CG start from a guess: the FP64 iterate r->d_x = eps_bar + P init (init:
+// the fluctuation, component-major per load, host or device doubles).  Only
+// the compatible zero-mean part of a guess is a CG iterate, so the guess is
+// projected first (any field is accepted).  stage: solver whose real-space
+// staging buffer takes a host init.
+int cg_start_from_init(ahom_solver* owner, ahom_solver* r, ahom_solver* stage, int n_load, const void* init,
+                       int mem_flags) {
+    const Plan& P = r->pat->plan;
+    const int nc = r->ncomp;
+    hipStream_t st = r->stream;
+    int rc;
+    if ((rc = ensure_c0_medium(owner))) return rc;
+    RealArgs fr = r->real_args(REAL_FROM_REAL);      // buf0 = state of eps_bar + init
+    fr.buf0 = fr.buf1 = r->d_buf0;
+    if (mem_flags == AHOM_MEM_DEVICE) {
+        fr.real_io = const_cast<double*>(static_cast<const double*>(init));
+    } else {
+        if ((rc = stage->ensure_real_staging())) return rc;
+        HIPCHK(hipMemcpyAsync(stage->d_real, init, (size_t)n_load * nc * P.m * sizeof(double), hipMemcpyHostToDevice, st));
+        fr.real_io = stage->d_real;
+    }
+    if (ahom_launch_real(AHOM_FP64, r->dim, REAL_FROM_REAL, fr, r->g_real.nwg, n_load, r->g_real.lds, st))
+        return fail(AHOM_E_DEVICE, "launch from_real");
+    if ((rc = project_sweep(owner, r, n_load))) return rc;
+    if (ahom_launch_cg_sub(static_cast<double2*>(r->d_x), static_cast<const double2*>(r->d_r), (int64_t)n_load * nc * P.S, st))
+        return fail(AHOM_E_DEVICE, "launch cg sub");
+    return AHOM_OK;
+}
+
+int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, const void* init, void* strain_out, int* iters,
+                   double* resid, double* mean_out, int mem_flags);
 
 // Conjugate gradients for n_load strains (cfg.scheme == AHOM_SCHEME_CG).
-int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
-             double* mean_out, int mem_flags) {
-    if (s->prec == AHOM_FP32_MIXED) return solve_cg_mixed(s, n_load, ebc, strain_out, iters, resid, mean_out, mem_flags);
+int solve_cg(ahom_solver* s, int n_load, const double* ebc, const void* init, void* strain_out, int* iters,
+             double* resid, double* mean_out, int mem_flags) {
+    if (s->prec == AHOM_FP32_MIXED)
+        return solve_cg_mixed(s, n_load, ebc, init, strain_out, iters, resid, mean_out, mem_flags);
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;
@@ -786,14 +861,19 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
     f.S = P.S;
     f.row = P.S / P.ax[0].slen;
     f.nfield = nc;
-    f.buf = s->d_buf0;                 // the start's operator input eps_bar
-    if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
     f.buf = s->d_x;                    // x(0) = 0: the iterate eps_bar
     if (ahom_launch_fill(s->prec, f, n_load, st)) return fail(AHOM_E_DEVICE, "fill");
+    HIPCHK(hipEventRecord(s->ev0, st));
+    if (init) {                        // x(0) = P init
+        if ((rc = cg_start_from_init(s, s, s, n_load, init, mem_flags))) return rc;
+        if (ahom_launch_reset(s->d_st, n_load, st)) return fail(AHOM_E_DEVICE, "reset");
+        if (ahom_launch_zero(s->prec, s->d_tbuf, (int64_t)n_load * s->nt * P.S, st)) return fail(AHOM_E_DEVICE, "zero");
+    }
+    // the start's operator input: the iterate
+    HIPCHK(hipMemcpyAsync(s->d_buf0, s->d_x, (size_t)n_load * nc * P.S * s->es(), hipMemcpyDeviceToDevice, st));
     // C_eff alone (no field asked) needs only the residual and mean-stress
     // recurrences: the iterate is then not formed
     s->cg_no_x = strain_out == nullptr;
-    HIPCHK(hipEventRecord(s->ev0, st));
     if ((rc = cg_sweep(s, n_load, 1))) { s->cg_no_x = false; return rc; }
     int enq = 1;
     const int limit = s->cfg.max_iter + 1;
@@ -855,8 +935,8 @@ int solve_cg(ahom_solver* s, int n_load, const double* ebc, void* strain_out, in
 // P the projection onto compatible zero-mean fields (one more FP64 sweep);
 // until the FP64 equilibrium residual of eps_b meets tol.  n counts the FP32
 // updates; the FP64 sweeps are the restarts.
-int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_out, int* iters, double* resid,
-                   double* mean_out, int mem_flags) {
+int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, const void* init, void* strain_out, int* iters,
+                   double* resid, double* mean_out, int mem_flags) {
     int rc = s->ensure_capacity(n_load);
     if (rc) return rc;
     s->spec_toff = nullptr;
@@ -869,15 +949,7 @@ int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_o
     const int nc = s->ncomp;
     const size_t per = (size_t)nc * P.S;
     // the reference medium C0 of this solve (stiffness or conductivity)
-    if (!s->d_zero_phase) {
-        HIPCHK(hipMalloc((void**)&s->d_zero_phase, (size_t)s->pat->sf.m));
-        HIPCHK(hipMemset(s->d_zero_phase, 0, (size_t)s->pat->sf.m));
-        HIPCHK(hipMalloc((void**)&s->d_c0tab, 2 * sizeof(double)));
-    }
-    {
-        const double c0[2] = {s->lam0, s->mu0};
-        HIPCHK(hipMemcpy(s->d_c0tab, c0, sizeof c0, hipMemcpyHostToDevice));
-    }
+    if ((rc = ensure_c0_medium(s))) return rc;
     hipStream_t st = s->stream;
     HIPCHK(hipMemcpyAsync(r->d_epsbar, ebc, (size_t)n_load * nc * sizeof(double), hipMemcpyHostToDevice, st));
     FillArgs f{};
@@ -892,6 +964,7 @@ int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_o
     std::vector<std::vector<std::pair<int, double>>> hrec(n_load);   // (updates so far, FP64 residual) per sweep
     int nrestart = 0, total = 0;
     HIPCHK(hipEventRecord(s->ev0, st));
+    if (init && (rc = cg_start_from_init(s, r, s, n_load, init, mem_flags))) return rc;   // eps_b = eps_bar + P init
     for (;;) {
         // FP64 sweep on eps_b: r_b, its traction, residual and mean stress
         HIPCHK(hipMemcpyAsync(r->d_buf0, r->d_x, (size_t)n_load * per * 16, hipMemcpyDeviceToDevice, st));
@@ -956,26 +1029,7 @@ int solve_cg_mixed(ahom_solver* s, int n_load, const double* ebc, void* strain_o
         ga.st = s->d_st;
         ga.per_load = (int64_t)per;
         if (ahom_launch_refine_gather(ga, n_load, st)) return fail(AHOM_E_DEVICE, "launch refine gather");
-        uint8_t* sv_ph = r->d_phase;
-        uint8_t* sv_pht = r->d_phase_t;
-        double* sv_tab = r->d_lame_tab;
-        double* sv_pts = r->d_lame_pts;
-        double* sv_ptst = r->d_lame_pts_t;
-        const int sv_np = r->n_phase;
-        r->d_phase = r->d_phase_t = s->d_zero_phase;
-        r->d_lame_tab = s->d_c0tab;
-        r->d_lame_pts = r->d_lame_pts_t = nullptr;
-        r->n_phase = 1;
-        rc = ahom_launch_reset(r->d_st, n_load, st) ||
-                     ahom_launch_zero(AHOM_FP64, r->d_tbuf, (int64_t)n_load * r->nt * P.S, st)
-                 ? fail(AHOM_E_DEVICE, "reset")
-                 : cg_sweep(r, n_load, 1);
-        r->d_phase = sv_ph;
-        r->d_phase_t = sv_pht;
-        r->d_lame_tab = sv_tab;
-        r->d_lame_pts = sv_pts;
-        r->d_lame_pts_t = sv_ptst;
-        r->n_phase = sv_np;
+        rc = project_sweep(s, r, n_load);
         if (rc) return rc;
         if (ahom_launch_cg_sub(static_cast<double2*>(r->d_x), static_cast<const double2*>(r->d_r), (int64_t)n_load * per, st))
             return fail(AHOM_E_DEVICE, "launch cg sub");
@@ -1387,8 +1441,8 @@ int solve_core(ahom_solver* s, int n_load, const double* ebc, const void* init, 
     if (init && s->cfg.stop_rule == AHOM_STOP_CAUCHY)
         return fail(AHOM_E_ARG, "the Cauchy stop rule measures against sqrt(m) |eps_bar|, not a guessed start: no init");
     if (s->cg) {
-        if (init) return fail(AHOM_E_ARG, "the conjugate-gradient scheme starts from eps_bar (no init)");
-        return solve_cg(s, n_load, ebc, strain_out, iters, resid, mean_out, mem_flags);
+        if (init && s->cfg.guess_probe > 0) return fail(AHOM_E_ARG, "guess_probe is a Basic Scheme option (the CG start is the projected guess)");
+        return solve_cg(s, n_load, ebc, init, strain_out, iters, resid, mean_out, mem_flags);
     }
     // guess probe: the plain start runs beside the guessed one as loads
     // n_load .. 2 n_load - 1 for the first guess_probe iterations

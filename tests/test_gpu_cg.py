@@ -14,7 +14,7 @@ from oracle import accelerated as A
 from oracle import closed_forms as CF
 from oracle import elasticity as E
 from oracle.dft import make_transform
-from tests.gpu_util import perm_between, tensors_to_fields, rel_err
+from tests.gpu_util import fields_to_tensors, perm_between, tensors_to_fields, rel_err
 
 pytestmark = pytest.mark.gpu
 ahom = pytest.importorskip("paper_1605_05712_amd.ahom")
@@ -131,11 +131,85 @@ def test_cg_homogeneous_and_argument_errors():
     with pytest.raises(ahom.AhomError) as ex:
         ahom.Solver(P, scheme=ahom.SCHEME_CG, stop_rule=ahom.STOP_CAUCHY)
     assert ex.value.code == ahom.AHOM_E_ARG
-    S2 = ahom.Solver(P, tol=1e-8, max_iter=10, scheme=ahom.SCHEME_CG)
+    S2 = ahom.Solver(P, tol=1e-8, max_iter=10, scheme=ahom.SCHEME_CG, guess_probe=4)
     S2.set_material(LAM3, rnd_phase(3, 3)(P.points(), P.m))
-    with pytest.raises(ahom.AhomError) as ex:
+    with pytest.raises(ahom.AhomError) as ex:       # the probe is a Basic Scheme option
         S2.solve(np.eye(3)[None] * 0.01, init=np.zeros((1, 6, P.m)))
     assert ex.value.code == ahom.AHOM_E_ARG
+
+
+INIT_CASES = [
+    ("3-D sheared", [[12, 0, 0], [0, 6, 0], [3, 0, 4]], ahom.FP64),
+    ("3-D 32x32x64 fast", [[32, 0, 0], [0, 32, 0], [0, 0, 64]], ahom.FP64),
+    ("2-D 64x64 fast", [[64, 0], [0, 64]], ahom.FP64),
+]
+
+
+@pytest.mark.parametrize("name,M,prec", INIT_CASES, ids=[c[0] for c in INIT_CASES])
+def test_cg_from_an_initial_guess_matches_oracle(name, M, prec):
+    """CG from a guess that is not compatible (random field): the start is the
+    guess's projection P g = Gamma0 C0 g onto compatible zero-mean fields; strain
+    after N updates, residual history and mean stress equal the CG oracle
+    started from the oracle's own projection of the same field (1e-10)."""
+    N = 4
+    d = len(M)
+    nc = 6 if d == 3 else 3
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((d, d))
+    eps_bar = 0.5 * (B + B.T)
+    lame = np.array([[1.0, 0.5], [30.0, 20.0], [5.0, 3.0]])
+    pf = rnd_phase(41, 3)
+    T = make_transform(M)
+    P = ahom.Pattern(M)
+    ip = perm_between(T.points, P.points())
+    g_gpu = 0.05 * rng.standard_normal((nc, P.m))                 # in the library's point order
+    inv = np.empty_like(ip)
+    inv[ip] = np.arange(len(ip))
+    g_or = fields_to_tensors(g_gpu[:, inv], d)                     # the same field in the oracle's order
+    op = A.LSOperator(M, pf(T.points, T.m), lame, E.default_reference(lame), transform=T)
+    r = A.conjugate_gradient(M, None, lame, None, eps_bar, init=op.project(g_or), fixed_iters=N, op=op)
+    say("cg init", name, M, "N", N)
+    S = ahom.Solver(P, precision=prec, tol=0.0, max_iter=N, check_period=3, scheme=ahom.SCHEME_CG)
+    S.set_material(lame, pf(P.points(), P.m))
+    eb = eps_bar[None] if d == 3 else np.pad(eps_bar, ((0, 1), (0, 1)))[None]
+    out = S.solve(eb, init=g_gpu[None], want_strain=True)
+    assert int(out["iters"][0]) == N
+    err = rel_err(out["strain"][0], tensors_to_fields(r.eps[:, :, ip]))
+    print(f"  field err {err:.2e}", flush=True)
+    assert err < 1e-10
+    assert np.allclose(S.history(0), r.history, rtol=1e-9, atol=1e-13 * r.history[0])
+    ms = out["mean_stress"][0][:d, :d]
+    assert np.allclose(ms, r.mean_stress, rtol=1e-10, atol=1e-12 * np.abs(r.mean_stress).max())
+
+
+@pytest.mark.parametrize("prec", [ahom.FP64, ahom.FP32_MIXED])
+def test_cg_restart_from_its_own_solution(prec):
+    """Restart: started from the converged field of a first solve, CG stops
+    after 0 updates with the same C_eff; from that field plus noise it needs
+    fewer updates than from eps_bar and reaches the same C_eff (contrast-100
+    spheres 32^3, tol 1e-9; noise of 1e-4 of the field amplitude)."""
+    n = 32
+    M = [[n, 0, 0], [0, n, 0], [0, 0, n]]
+    say("cg restart", M, "prec", prec)
+    c, rad = synth.spheres_rsa(seed=3)
+    P = ahom.Pattern(M)
+    ph = synth.spheres_phase(P.points(), P.m, c, rad)
+    lame = np.array([synth.lame(1.0, 0.25), synth.lame(100.0, 0.25)])
+    eb = np.diag([0.01, 0.0, 0.0])[None]
+    S = ahom.Solver(P, precision=prec, tol=1e-9, max_iter=3000, scheme=ahom.SCHEME_CG)
+    S.set_material(lame, ph)
+    a = S.solve(eb, want_strain=True, allow=(ahom.AHOM_OK,))
+    fl = a["strain"].copy()
+    fl[0, 0] -= 0.01
+    b = S.solve(eb, init=fl, want_strain=True, allow=(ahom.AHOM_OK,))
+    print("updates from eps_bar", list(a["iters"]), "from the solution", list(b["iters"]), flush=True)
+    assert int(b["iters"][0]) <= 1
+    assert np.abs(b["mean_stress"][0] - a["mean_stress"][0]).max() < 1e-8 * np.abs(a["mean_stress"][0]).max()
+    noisy = fl + 1e-6 * np.random.default_rng(2).standard_normal(fl.shape)   # 1e-4 of the field
+    c2 = S.solve(eb, init=noisy, allow=(ahom.AHOM_OK,))
+    print("from the noisy solution", list(c2["iters"]), flush=True)
+    assert int(c2["iters"][0]) < int(a["iters"][0])
+    assert np.abs(c2["mean_stress"][0] - a["mean_stress"][0]).max() < 1e-8 * np.abs(a["mean_stress"][0]).max()
 
 
 @pytest.mark.parametrize("variant", ["0", "2", "4"])
