@@ -81,7 +81,7 @@ typedef struct ahom_config {
                            correction to that iterate with the defect as a fixed traction
                            offset, so FP32 rounding scales with the correction rather than
                            with the whole field.  0 = default (1e-3; 1e-4 with the CG
-                           scheme); < 0 = no restarts (the
+                           scheme in elasticity); < 0 = no restarts (the
                            plain FP32 iteration, whose residual floor is set by FP32
                            rounding of the polarization). */
     int stop_rule;      /* AHOM_STOP_RESIDUAL (0, default): stop at r(n) <= tol.
@@ -113,7 +113,7 @@ typedef struct ahom_config {
                            compatible zero-mean fields (one more FP64 sweep); n counts the FP32
                            updates, ahom_solver_last_restarts the corrections, the history holds
                            the FP64 residual where a sweep evaluated it.  Needs refine >= 0
-                           (0 selects 1e-4 for CG). */
+                           (0 selects 1e-4 for elasticity, 1e-3 for conductivity). */
     int physics;        /* AHOM_ELASTICITY (0, default): quasi-static linear elasticity (Sec. 3.1).
                            AHOM_CONDUCTIVITY (1): the steady-state heat (conductivity) equation that
                            Sec. 3 names beside it: unknown the gradient e = grad theta of a
