@@ -90,40 +90,6 @@ def layer_shapes(ch=CH, n_in=3, n_out=36):
             (c2, c3), (c2, c2), (c1, c2), (c1, c1), (c0, c1), (c0, c0), (n_out, c0)]
 
 
-def unflatten(flat, ch=CH):
-    """The library's flat FP32 parameters -> list of (w (Co, Ci, 27), b (Co,)) with unpadded channels.
-
-    Library layout per layer: W[cout_pad][27][cin_pad], then b[cout_pad]; input
-    channels padded to 32, output channels of the last layer to 64.
-    """
-    flat = np.asarray(flat, dtype=np.float64)
-    out, off = [], 0
-    for k, (co, ci) in enumerate(layer_shapes(ch)):
-        cip = 32 if k == 0 else ci
-        cop = 64 if k == 14 else co
-        W = flat[off: off + cop * 27 * cip].reshape(cop, 27, cip)
-        off += cop * 27 * cip
-        b = flat[off: off + cop]
-        off += cop
-        out.append((W[:co, :, :ci].transpose(0, 2, 1).copy(), b[:co].copy()))
-    assert off == flat.size
-    return out
-
-
-def flatten(params, ch=CH):
-    """Inverse of unflatten (padding entries zero)."""
-    parts = []
-    for k, ((co, ci), (w, b)) in enumerate(zip(layer_shapes(ch), params)):
-        cip = 32 if k == 0 else ci
-        cop = 64 if k == 14 else co
-        W = np.zeros((cop, 27, cip))
-        W[:co, :, :ci] = w.transpose(0, 2, 1)
-        bb = np.zeros(cop)
-        bb[:co] = b
-        parts += [W.ravel(), bb]
-    return np.concatenate(parts)
-
-
 def net_input(phase, lame, lam0, mu0, n):
     """Three input channels on the grid from phase ids (canonical order) and the phase table."""
     phase = np.asarray(phase).reshape(n, n, n)

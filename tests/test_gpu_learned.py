@@ -13,6 +13,7 @@ import pytest
 
 import synth
 from oracle import learned as NN
+from tests import net_layout
 
 pytestmark = pytest.mark.gpu
 ahom = pytest.importorskip("paper_1605_05712_amd.ahom")
@@ -126,7 +127,7 @@ def test_network_loss_and_gradients_match_oracle():
     say("network gradients", n)
     g = ahom.Guess(n, batch=2, seed=5)
     flat = g.params()
-    params = NN.unflatten(flat)
+    params = net_layout.unflatten(flat)
     # the device multiplies BF16 weights
     params_b = [(to_bf16(w).astype(np.float64), b) for w, b in params]
     r = np.random.default_rng(11)
@@ -139,7 +140,7 @@ def test_network_loss_and_gradients_match_oracle():
         g.add_sample(ph, lame, lam0, mu0, unit_strain_from_fluct(fl))
         samples.append((ph, lame, lam0, mu0, fl))
     loss, grad = g.gradients([0, 1])
-    mine = NN.unflatten(grad)
+    mine = net_layout.unflatten(grad)
     worst = {}
     for store, lb in ((bf16_store, 1e-3), (None, 1e-2)):
         ref_loss = 0.0

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import learned as NN
+from tests import net_layout
 
 
 def rnd(shape, seed):
@@ -115,8 +116,8 @@ def test_network_gradient_matches_finite_differences(seed):
 
 def test_flat_layout_roundtrip():
     params = small_params(3, NN.CH, 1.0)
-    flat = NN.flatten(params)
-    back = NN.unflatten(flat)
+    flat = net_layout.flatten(params)
+    back = net_layout.unflatten(flat)
     assert all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) for a, b in zip(params, back))
 
 
