@@ -141,20 +141,30 @@ def test_conductivity_fp32_restarts_and_cg_on_a_contrast_100_cell():
     assert max(out["cg"][1]) * 3 < min(out["fp64"][1])
 
 
-def test_conductivity_fast_path_matches_generic(monkeypatch):
+@pytest.mark.parametrize("prec", [ahom.FP64, ahom.FP32_MIXED])
+def test_conductivity_fast_path_matches_generic(prec, monkeypatch):
+    """Every pinned tile variant of the power-of-two kernels (incl. the
+    quarter-width spectral tiles, variant 4) = the generic kernels."""
     M = [[64, 0, 0], [0, 64, 0], [0, 0, 128]]
-    say("conductivity fast-vs-generic", M)
+    say("conductivity fast-vs-generic", M, "prec", prec)
     P = ahom.Pattern(M)
     ph = rnd_phase(53, 3)(P.points(), P.m)
     gb = np.array([[1.0, 0.0, 0.0], [0.2, -0.5, 0.7]])
-    outs = []
-    for generic in ("1", "0"):
-        monkeypatch.setenv("AHOM_GENERIC_ONLY", generic)
-        S = solver(P, KV, ph, tol=0.0, max_iter=4)
-        outs.append(S.solve_conductivity(gb, want_field=True))
+    kw = dict(tol=0.0, max_iter=4, precision=prec, refine=-1.0 if prec == ahom.FP32_MIXED else 0.0)
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "1")
+    S = solver(P, KV, ph, **kw)
+    ref = S.solve_conductivity(gb, want_field=True)
+    del S
+    monkeypatch.setenv("AHOM_GENERIC_ONLY", "0")
+    tol = 1e-12 if prec == ahom.FP64 else 2e-5
+    for v in "01234":
+        monkeypatch.setenv("AHOM_FAST_VARIANT", v)
+        S = solver(P, KV, ph, **kw)
+        out = S.solve_conductivity(gb, want_field=True)
         del S
-    assert rel_err(outs[1]["field"], outs[0]["field"]) < 1e-12
-    assert np.allclose(outs[1]["resid"], outs[0]["resid"], rtol=1e-10)
+        assert rel_err(out["field"], ref["field"]) < tol, v
+        assert np.allclose(out["resid"], ref["resid"], rtol=tol * 10), v
+    monkeypatch.delenv("AHOM_FAST_VARIANT")
 
 
 def test_conductivity_argument_errors():
