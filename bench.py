@@ -141,7 +141,7 @@ print(json.dumps(dict(median=float(np.median(per)), min=float(per.min()), m=T.m,
 
 def batch_workload(ahom):
     """512 seeded 2-D members (uneven non-diagonal patterns, 1,024..65,536 points),
-    3 loads, FP32 with FP64 residual, tol 1e-6, one persistent launch from a graph."""
+    3 loads, FP32 with FP64 residual, tol 1e-6, persistent launches replayed from one graph."""
     import numpy as np
     import synth
     seeds = range(4000, 4512)
@@ -168,7 +168,7 @@ def batch_workload(ahom):
                 point_updates=upd, updates_per_s=round(upd / (ms * 1e-3), 1), restarts=int(restarts),
                 iters_min=int(out["iters"].min()), iters_max=int(out["iters"].max()),
                 converged=bool(np.all(out["item_status"] == 0)), setup_s=round(t_setup, 1),
-                precision="fp32 + fp64 residual, tol 1e-6", launch="one persistent kernel replayed from a HIP graph")
+                precision="fp32 + fp64 residual, tol 1e-6", launch="persistent FP32-stage and FP64-restart kernels replayed from one HIP graph")
 
 
 def sweep_workload(ahom):

@@ -371,13 +371,16 @@ int ahom_solver_cauchy_history(const ahom_solver* s, int load, double* hist, int
 
 /* ------------------------------------------------------------------------
  * Batched solves: Algorithm 1 on many patterns P(M_i) of uneven size (same
- * dimension) in one persistent device launch.  A workgroup takes one
+ * dimension) in persistent device launches.  A workgroup takes one
  * (member, load) item from a device queue and iterates it to its own stop,
- * so members of different sizes and iteration counts share the launch.  The
+ * so members of different sizes and iteration counts share a launch.  The
  * plan (largest radix) and tile widths of each distinct Smith shape are
  * chosen by timing the candidates on the device the first time the shape is
- * seen in the process.  AHOM_FP32_MIXED items use the defect-correction
- * restarts of ahom_config.refine inside the same launch.
+ * seen in the process.  AHOM_FP64 items are solved in one launch.
+ * AHOM_FP32_MIXED items use the defect-correction restarts of
+ * ahom_config.refine: a launch of first FP32 stages, then rounds of (FP64
+ * restart steps, FP32 correction stages) for the items that need them, all
+ * on the batch's stream (and replayed from one HIP graph when asked).
  * ------------------------------------------------------------------------ */
 typedef struct ahom_batch ahom_batch;
 
@@ -436,7 +439,8 @@ int ahom_batch_history(const ahom_batch* b, int member, int load, double* hist, 
  * is not evaluated and on the FP64 step of a restart). */
 int ahom_batch_cauchy_history(const ahom_batch* b, int member, int load, double* hist, int cap, int* count);
 
-/* Device time of the last batch launch (HIP events) and total restarts. */
+/* Device time of the last batch solve (HIP events around its launches) and
+ * total restarts. */
 int ahom_batch_last_timing(const ahom_batch* b, double* ms, int* restarts);
 
 /* Plan variant the autotuner chose for member i (index into the candidate list). */

@@ -117,6 +117,7 @@ struct ahom_batch {
     int* d_qslot = nullptr;
     int* d_gcount = nullptr;
     double* d_gpart = nullptr;
+    double* d_sbase = nullptr;
     int n_queue = 0;
     int* d_counter = nullptr;
     LoadState* d_st = nullptr;
@@ -128,8 +129,12 @@ struct ahom_batch {
     std::vector<BatchItem> h_items;
     std::vector<LoadState> h_st;
     std::vector<int> h_restarts;
-    size_t lds = 0;
-    int nwg = 1;
+    // the first kernel kind of a solve (BATCH_SOLVE for FP64, BATCH_FP32) and
+    // the FP64 restart step: dynamic LDS and workgroups of each
+    int kind = BATCH_SOLVE;
+    size_t lds = 0, lds64 = 0;
+    int nwg = 1, nwg64 = 1;
+    int graph_rounds = 2;             // restart rounds captured in the graph
     int hist_cap = 0;
     // graph of (queue reset, batch kernel) on a stream of its own
     hipStream_t gstream = nullptr;
@@ -146,7 +151,7 @@ struct ahom_batch {
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
-        dfree(arena); dfree(d_items); dfree(d_order); dfree(d_qslot); dfree(d_gcount); dfree(d_gpart);
+        dfree(arena); dfree(d_items); dfree(d_order); dfree(d_qslot); dfree(d_gcount); dfree(d_gpart); dfree(d_sbase);
         dfree(d_counter); dfree(d_st); dfree(d_st_base);
         dfree(d_restarts); dfree(d_hist); dfree(d_epsbar); dfree(d_zero);
         nload = 0;
@@ -229,6 +234,7 @@ int ahom_batch::build_items(int n_load) {
     BCHK(hipMalloc((void**)&d_counter, 256));
     BCHK(hipMalloc((void**)&d_gcount, n_items * sizeof(int)));
     BCHK(hipMalloc((void**)&d_gpart, (size_t)n_items * kGroupPart * sizeof(double)));
+    BCHK(hipMalloc((void**)&d_sbase, (size_t)n_items * 8 * sizeof(double)));
     BCHK(hipMalloc((void**)&d_st, n_items * sizeof(LoadState)));
     BCHK(hipMalloc((void**)&d_st_base, sizeof(LoadState)));
     BCHK(hipMalloc((void**)&d_restarts, n_items * sizeof(int)));
@@ -242,7 +248,7 @@ int ahom_batch::build_items(int n_load) {
         BCHK(hipMemcpy(d_zero, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     h_items.assign(n_items, BatchItem{});
-    size_t lds_max = 0;
+    size_t lds_main = 0, lds_r64 = 0;
     for (int q = 0; q < n_items; ++q) {
         const int i = q / n_load, l = q % n_load;
         const Member& mb = mem[i];
@@ -276,9 +282,10 @@ int ahom_batch::build_items(int n_load) {
         it.k = 1;
         it.gcount = d_gcount + q;
         it.gpart = d_gpart + (size_t)q * kGroupPart;
+        it.sbase = d_sbase + (size_t)q * 8;
         const double beta = (mb.lam0 + mb.mu0) / (mb.lam0 + 2.0 * mb.mu0);
         auto fill_args = [&](int pr, void* b0, void* b1, void* tb, RealArgs* ra, AxisArgs* ax, SpecArgs* sa,
-                             int64_t* t_real, int64_t* t_spec, int64_t* t_axis) {
+                             int64_t* t_real, int64_t* t_spec, int64_t* t_axis, size_t& lds_max) {
             const size_t esz = pr == AHOM_FP64 ? 16 : 8;
             PassGeo gr, gs, ga[AHOM_MAX_AXES];
             geometry(mb, esz, budget, &gr, &gs, ga);
@@ -307,28 +314,32 @@ int ahom_batch::build_items(int n_load) {
             *t_spec = gs.tiles;
             lds_max = std::max(lds_max, gs.lds);
         };
-        fill_args(prec, buf0, buf1, tbuf, &it.ra, it.ax, &it.sa, &it.t_real, &it.t_spec, it.t_axis);
+        fill_args(prec, buf0, buf1, tbuf, &it.ra, it.ax, &it.sa, &it.t_real, &it.t_spec, it.t_axis, lds_main);
         it.sa_corr = it.sa;
         if (ref) {
             it.sa_corr.eps_bar = d_zero;
             it.sa_corr.toff = toff;
-            fill_args(AHOM_FP64, b64_0, b64_1, tb64, &it.ra64, it.ax64, &it.sa64, &it.t_real64, &it.t_spec64, it.t_axis64);
+            fill_args(AHOM_FP64, b64_0, b64_1, tb64, &it.ra64, it.ax64, &it.sa64, &it.t_real64, &it.t_spec64, it.t_axis64,
+                      lds_r64);
             it.sa64.resid_period = 1;
             it.sa64.max_iter = 1;
             it.sa64.dout = toff;
             it.sa64.dneg = tbuf;
         }
     }
-    lds = lds_max;
-    const size_t lds_total = lds + ahom_batch_static_lds(d);
-    if (lds_total > 160 * 1024) return bfail(AHOM_E_UNSUPPORTED_SIZE, "batch tiles exceed the LDS");
+    kind = prec == AHOM_FP64 ? BATCH_SOLVE : BATCH_FP32;
+    lds = lds_main;
+    lds64 = lds_r64;
+    if (std::max(lds, lds64) + ahom_batch_static_lds(d) > 160 * 1024)
+        return bfail(AHOM_E_UNSUPPORTED_SIZE, "batch tiles exceed the LDS");
     int ncu = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {
         int n = 0;
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) ncu = n;
     }
-    const int occ = std::max(1, ahom_batch_occupancy(prec, d, lds));
+    const int occ = std::max(1, ahom_batch_occupancy(kind, d, lds));
     const int cap = std::max(1, occ * ncu);   // workgroups resident at once
+    const int cap64 = std::max(1, std::max(1, ahom_batch_occupancy(BATCH_RESTART64, d, lds64)) * ncu);
     // Items much larger than a workgroup's fair share are iterated by a group
     // of k workgroups (tiles of every pass dealt round-robin, a group barrier
     // between passes).  k <= nwg keeps the queue deadlock-free: a group's queue
@@ -337,7 +348,7 @@ int ahom_batch::build_items(int n_load) {
     {
         double total = 0.0;
         for (int q = 0; q < n_items; ++q) total += (double)Sv[q / n_load];
-        const int kmax = std::min(kGroupMax, cap);
+        const int kmax = std::min(kGroupMax, std::min(cap, cap64));
         for (int q = 0; q < n_items; ++q) {
             const double share = 3.0 * (double)Sv[q / n_load] * cap / std::max(total, 1.0);
             h_items[q].k = std::max(1, std::min(kmax, (int)std::ceil(share)));
@@ -354,6 +365,7 @@ int ahom_batch::build_items(int n_load) {
         for (int sl = 0; sl < h_items[q].k; ++sl) { qitem.push_back(q); qslot.push_back(sl); }
     n_queue = (int)qitem.size();
     nwg = std::min(n_queue, cap);   // >= every item's k
+    nwg64 = std::min(n_queue, cap64);
     BCHK(hipMalloc((void**)&d_order, n_queue * sizeof(int)));
     BCHK(hipMalloc((void**)&d_qslot, n_queue * sizeof(int)));
     BCHK(hipMemcpy(d_order, qitem.data(), n_queue * sizeof(int), hipMemcpyHostToDevice));
@@ -381,29 +393,68 @@ int ahom_batch::run(bool use_graph) {
     a.group_wait = 400000000LL;
     if (const char* w = getenv("AHOM_BATCH_GROUP_WAIT")) a.group_wait = std::max(0LL, atoll(w));
     hipStream_t s = use_graph ? gstream : stream;
+    const int n_items = (int)h_items.size();
+    // one launch of a kernel kind over the whole queue, after zeroing the
+    // queue head and the group barrier counters
+    auto launch = [&](hipStream_t st, int k, int phase) -> int {
+        a.phase = phase;
+        if (ahom_launch_batch_reset(d_counter, d_gcount, n_items, st)) return -1;
+        return k == BATCH_RESTART64 ? ahom_launch_batch(k, d, a, nwg64, lds64, st) : ahom_launch_batch(k, d, a, nwg, lds, st);
+    };
+    // FP32 with restarts: the first stage, then rounds of (FP64 restart step,
+    // correction stage); an item that needs no further restart skips a round
+    auto launch_solve = [&](hipStream_t st, int rounds) -> int {
+        if (launch(st, kind, 0)) return -1;
+        for (int r = 0; r < rounds; ++r)
+            if (launch(st, BATCH_RESTART64, 0) || launch(st, BATCH_FP32, 1)) return -1;
+        return 0;
+    };
+    const bool ref = refine_on();
+    auto pending = [&]() {
+        int n = 0;
+        for (const LoadState& x : h_st) n += ref && x.done && x.status == 0 && x.resid > cfg.tol;
+        return n;
+    };
+    const int rounds = ref ? graph_rounds : 0;
     if (use_graph && !gexec) {
         BCHK(hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal));
-        const int r1 = ahom_launch_batch_reset(d_counter, d_gcount, (int)h_items.size(), gstream);
-        const int r2 = ahom_launch_batch(prec, d, a, nwg, lds, gstream);
+        const int r1 = launch_solve(gstream, rounds);
         hipGraph_t g = nullptr;
         BCHK(hipStreamEndCapture(gstream, &g));
         graph = g;
-        if (r1 || r2) return bfail(AHOM_E_DEVICE, "batch graph capture failed");
+        if (r1) return bfail(AHOM_E_DEVICE, "batch graph capture failed");
         BCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
     }
     BCHK(hipEventRecord(ev0, s));
     if (use_graph) {
         BCHK(hipGraphLaunch(gexec, s));
     } else {
-        if (ahom_launch_batch_reset(d_counter, d_gcount, (int)h_items.size(), s)) return bfail(AHOM_E_DEVICE, "launch batch reset");
-        if (ahom_launch_batch(prec, d, a, nwg, lds, s)) return bfail(AHOM_E_DEVICE, "launch batch kernel");
+        if (launch_solve(s, rounds)) return bfail(AHOM_E_DEVICE, "launch batch kernels");
     }
     BCHK(hipEventRecord(ev1, s));
     BCHK(hipEventSynchronize(ev1));
+    BCHK(hipMemcpy(h_st.data(), d_st, h_st.size() * sizeof(LoadState), hipMemcpyDeviceToHost));
+    // items still short of tol after the planned rounds: more rounds, one at
+    // a time (each adds at least one update to every such item, so max_iter
+    // bounds them); the next graph capture plans for as many
+    int extra = 0;
+    while (pending() > 0) {
+        if (launch(s, BATCH_RESTART64, 0) || launch(s, BATCH_FP32, 1)) return bfail(AHOM_E_DEVICE, "launch batch kernels");
+        BCHK(hipEventRecord(ev1, s));
+        BCHK(hipEventSynchronize(ev1));
+        BCHK(hipMemcpy(h_st.data(), d_st, h_st.size() * sizeof(LoadState), hipMemcpyDeviceToHost));
+        ++extra;
+    }
+    if (extra > 0) {
+        graph_rounds += extra;
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    }
     float ms = 0.f;
     BCHK(hipEventElapsedTime(&ms, ev0, ev1));
     last_ms = ms;
-    BCHK(hipMemcpy(h_st.data(), d_st, h_st.size() * sizeof(LoadState), hipMemcpyDeviceToHost));
     BCHK(hipMemcpy(h_restarts.data(), d_restarts, h_restarts.size() * sizeof(int), hipMemcpyDeviceToHost));
     return AHOM_OK;
 }

@@ -256,6 +256,7 @@ struct BatchItem {
     int k;                             // workgroups that iterate the item together (>= 1)
     int* gcount;                       // group barrier arrivals (zeroed before each launch)
     double* gpart;                     // [2][k][8] partial sums of the group's workgroups
+    double* sbase;                     // [8] FP32 restarts: mean stress of the FP64 base iterate
 };
 
 struct BatchArgs {
@@ -267,16 +268,21 @@ struct BatchArgs {
     double tol, refine;
     int max_iter, resid_period;
     int refine_on;                     // FP32 items: defect-correction restarts
+    int phase;                         // BATCH_FP32 launches: 0 first stage, 1 correction stage
     long long group_wait;              // group barrier wait limit (100 MHz ticks)
 };
 
+// batch kernel kinds: the whole solve of FP64 items; the FP32 stages (first or
+// correction); the FP64 step of an FP32 item's restart
+enum { BATCH_SOLVE = 0, BATCH_FP32 = 1, BATCH_RESTART64 = 2 };
+
 // queue head and group barrier counters to zero (plain kernel: safe inside a captured graph)
 int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t s);
-int ahom_launch_batch(int prec, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s);
-// static LDS bytes of the batch kernel (reduction scratch and item state)
+int ahom_launch_batch(int kind, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s);
+// static LDS bytes of the batch kernels (reduction scratch and item state)
 size_t ahom_batch_static_lds(int dim);
-// resident workgroups per CU of the batch kernel with `lds` dynamic LDS bytes
-int ahom_batch_occupancy(int prec, int dim, size_t lds);
+// resident workgroups per CU of a batch kernel kind with `lds` dynamic LDS bytes
+int ahom_batch_occupancy(int kind, int dim, size_t lds);
 
 // ---- power-of-two fast path (ahom_fast.hip)
 enum { FAST_REAL = 0, FAST_AXIS = 1, FAST_SPEC = 2 };

@@ -1049,92 +1049,136 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
     }
 }
 
-// Algorithm 1 on one item, with the FP32 defect-correction restarts (the
-// same scheme as the single-pattern solver: FP64 iterate eps_b = F(eps_h),
-// traction step d, then FP32 iteration on eps - eps_b with offset d).
-template <typename T, int DIM>
-__device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, LoadState& st64,
-                           double* sbase, double* red) {
-    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
-    const int tid = threadIdx.x;
-    const int k = it.k;
-    const long long wait = b.group_wait;
-    int phase = 0, rround = 0;
-    wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_, slot, k);
-    wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S, slot, k);
-    if (tid == 0) st = LoadState{};
-    // |eps(0)| = sqrt(m) |eps_bar|_F of the item's load (the Cauchy denominator)
+// |eps(0)| = sqrt(m) |eps_bar|_F of an item's load (the Cauchy denominator)
+template <int DIM>
+__device__ double item_norm0(const BatchItem& it) {
+    constexpr int NC_ = Comp<DIM>::N;
     double nb = 0.0;
     for (int c = 0; c < NC_; ++c) {
         const bool diag = DIM == 3 ? c < 3 : c < 2;
         nb += (diag ? 1.0 : 2.0) * it.ra.eps_bar[c] * it.ra.eps_bar[c];
     }
-    const double norm0 = sqrt((double)it.m * nb);
-    group_sync(it, phase, wait);
-    double stage_tol = b.refine_on ? fmax(b.tol, b.refine) : b.tol;
-    batch_stage<T, DIM>(it, it.ra, it.ax, it.sa, it.t_real, it.t_spec, it.t_axis, st, nullptr, stage_tol, b.max_iter,
-                        b.resid_period, true, red, slot, phase, rround, b.group_wait, norm0);
-    int nres = 0;
-    if constexpr (sizeof(T) == 4) {
-        while (b.refine_on && st.status == 0 && st.resid > b.tol) {
-            // FP64 iterate eps_h = (FP64 base) + FP32 state
-            {
-                const float2* in = reinterpret_cast<const float2*>(st.final_buf ? it.ra.buf1 : it.ra.buf0);
-                double2* out = reinterpret_cast<double2*>(it.ra64.buf0);
-                const double2* base = nres ? reinterpret_cast<const double2*>(it.ra64.buf1) : nullptr;
-                const int64_t n = (int64_t)NC_ * it.S;
-                for (int64_t i = (int64_t)slot * blockDim.x + tid; i < n; i += (int64_t)k * blockDim.x) {
-                    const float2 x = in[i];
-                    double2 r = double2{(double)x.x, (double)x.y};
-                    if (base) { r.x += base[i].x; r.y += base[i].y; }
-                    out[i] = r;
-                }
-            }
-            wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S, slot, k);
-            if (tid == 0) st64 = LoadState{};
-            group_sync(it, phase, wait);
-            batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64,
-                                     nullptr, -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait, norm0);
-            ++nres;
-            // correction stage: e(0) = 0, t(e(-1)) = -d (written by the FP64 pass)
-            if (tid == 0) {
-                LoadState ns{};
-                ns.iter = st.iter + 1 < b.max_iter ? st.iter + 1 : b.max_iter;
-                ns.r0 = st.r0;
-                ns.resid = st64.resid;
-                for (int c = 0; c < NC_; ++c) ns.mean[c] = sbase[c] = st64.mean[c];
-                ns.final_buf = ns.iter & 1;
-                const double r = st64.resid;
-                if (!(r == r) || isinf(r)) { ns.done = 1; ns.status = 2; }
-                else if (r <= b.tol) { ns.done = 1; ns.status = 0; }
-                else if (ns.iter >= b.max_iter) { ns.done = 1; ns.status = 1; }
-                if (slot == 0 && ns.done && ns.iter < it.hist_cap) {
-                    it.hist[ns.iter] = r;
-                    it.chist[ns.iter] = -1.0;   // a restart's FP64 step: Cauchy measure not recorded
-                }
-                st = ns;
-            }
-            wg_zero<T>(it.ra.buf0, (int64_t)NC_ * it.S, slot, k);
-            wg_zero<T>(it.ra.buf1, (int64_t)NC_ * it.S, slot, k);
-            group_sync(it, phase, wait);
-            if (st.done) break;
-            stage_tol = fmax(b.tol, b.refine * st.resid);
-            batch_stage<T, DIM>(it, it.ra, it.ax, it.sa_corr, it.t_real, it.t_spec, it.t_axis, st, sbase, stage_tol,
-                                b.max_iter, b.resid_period, true, red, slot, phase, rround, b.group_wait, norm0);
-        }
+    return sqrt((double)it.m * nb);
+}
+
+// Algorithm 1 on one item, one stage: from eps(0) = eps_bar to the item's
+// stop (FP64 items; FP32 items without restarts) or to the first stage
+// tolerance max(tol, refine) of an FP32 item with restarts; or (corr) the
+// FP32 correction stage after a restart's FP64 step: e from 0 with the
+// traction offset, mean stress = sbase + mean of the correction, to
+// max(tol, refine x the restart's residual).  Then publish the state.  One
+// call site of batch_stage serves both, so the kernel holds one copy of it.
+template <typename T, int DIM>
+__device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, double* red, bool corr) {
+    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    const int tid = threadIdx.x;
+    const int k = it.k;
+    int phase = 0, rround = 0;
+    if (corr) {
+        if (tid == 0) st = *it.st;
+        __syncthreads();
+        if (st.done) return;   // the same decision in every workgroup of the group
+    } else {
+        wg_fill_state<T>(it.ra.buf0, it.ra.eps_bar, it.S, it.row, NC_, slot, k);
+        wg_zero<T>(it.sa.tbuf, (int64_t)NT * it.S, slot, k);
+        if (tid == 0) st = LoadState{};
+        group_sync(it, phase, b.group_wait);
     }
+    const double norm0 = item_norm0<DIM>(it);
+    const double stage_tol = corr ? fmax(b.tol, b.refine * st.resid) : b.refine_on ? fmax(b.tol, b.refine) : b.tol;
+    batch_stage<T, DIM>(it, it.ra, it.ax, corr ? it.sa_corr : it.sa, it.t_real, it.t_spec, it.t_axis, st,
+                        corr ? it.sbase : nullptr, stage_tol, b.max_iter, b.resid_period, true, red, slot, phase,
+                        rround, b.group_wait, norm0);
     if (tid == 0 && slot == 0) {
         *it.st = st;
-        *it.restarts = nres;
+        if (!corr) *it.restarts = 0;
     }
 }
 
-template <typename T, int DIM>
+// An FP32 item whose stage stopped at its stage tolerance above tol needs a
+// defect-correction restart (the single-pattern solver's scheme).
+__device__ __forceinline__ bool needs_restart(const BatchArgs& b, const LoadState& st) {
+    return b.refine_on && st.done && st.status == 0 && st.resid > b.tol;
+}
+
+// The FP64 step of a restart: eps_h = (FP64 base, from the second restart on)
+// + FP32 state, one FP64 update eps_b = F(eps_h) (its buffer is the next
+// base) whose traction step d becomes the offset of the correction stage
+// (written by the FP64 spectral pass), the FP32 state cleared for the
+// correction e = eps - eps_b, and the loop control of the correction stage.
+template <int DIM>
+__device__ void batch_restart64(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, LoadState& st64,
+                                double* red) {
+    constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
+    const int tid = threadIdx.x;
+    const int k = it.k;
+    __shared__ int nres_s;
+    if (tid == 0) {
+        st = *it.st;
+        nres_s = *it.restarts;
+    }
+    __syncthreads();
+    if (!needs_restart(b, st)) return;   // the same decision in every workgroup of the group
+    const int nres = nres_s;
+    int phase = 0, rround = 0;
+    {
+        const float2* in = reinterpret_cast<const float2*>(st.final_buf ? it.ra.buf1 : it.ra.buf0);
+        double2* out = reinterpret_cast<double2*>(it.ra64.buf0);
+        const double2* base = nres ? reinterpret_cast<const double2*>(it.ra64.buf1) : nullptr;
+        const int64_t n = (int64_t)NC_ * it.S;
+        for (int64_t i = (int64_t)slot * blockDim.x + tid; i < n; i += (int64_t)k * blockDim.x) {
+            const float2 x = in[i];
+            double2 r = double2{(double)x.x, (double)x.y};
+            if (base) { r.x += base[i].x; r.y += base[i].y; }
+            out[i] = r;
+        }
+    }
+    wg_zero<double>(it.sa64.tbuf, (int64_t)NT * it.S, slot, k);
+    if (tid == 0) st64 = LoadState{};
+    const double norm0 = item_norm0<DIM>(it);
+    group_sync(it, phase, b.group_wait);
+    batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64, nullptr,
+                             -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait, norm0);
+    // correction stage: e(0) = 0, t(e(-1)) = -d
+    if (tid == 0) {
+        LoadState ns{};
+        ns.iter = st.iter + 1 < b.max_iter ? st.iter + 1 : b.max_iter;
+        ns.r0 = st.r0;
+        ns.resid = st64.resid;
+        for (int c = 0; c < NC_; ++c) ns.mean[c] = st64.mean[c];
+        ns.final_buf = ns.iter & 1;
+        const double r = st64.resid;
+        if (!(r == r) || isinf(r)) { ns.done = 1; ns.status = 2; }
+        else if (r <= b.tol) { ns.done = 1; ns.status = 0; }
+        else if (ns.iter >= b.max_iter) { ns.done = 1; ns.status = 1; }
+        if (st64.status == 3) { ns.done = 1; ns.status = 3; }
+        if (slot == 0 && ns.done && ns.iter < it.hist_cap) {
+            it.hist[ns.iter] = r;
+            it.chist[ns.iter] = -1.0;   // a restart's FP64 step: Cauchy measure not recorded
+        }
+        st = ns;
+    }
+    wg_zero<float>(it.ra.buf0, (int64_t)NC_ * it.S, slot, k);
+    wg_zero<float>(it.ra.buf1, (int64_t)NC_ * it.S, slot, k);
+    // every workgroup of the group has read the state above before slot 0 publishes the new one
+    group_sync(it, phase, b.group_wait);
+    if (tid == 0 && slot == 0) {
+        for (int c = 0; c < NC_; ++c) it.sbase[c] = st.mean[c];
+        *it.st = st;
+        *it.restarts = nres + 1;
+    }
+}
+
+// Persistent workgroups over the item queue.  KIND selects the work per item:
+// BATCH_SOLVE (FP64 items, the whole solve), BATCH_FP32 (b.phase 0: the first
+// FP32 stage, 1: a correction stage) or BATCH_RESTART64 (a restart's FP64
+// step).  The FP32 solve is split over launches so that the FP32 kernel holds
+// no FP64 tile code: its registers then allow two workgroups per CU.
+template <int DIM, int KIND>
 __global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
     constexpr int NC_ = Comp<DIM>::N;
     __shared__ double red[(NC_ + 2) * AHOM_WG];
     __shared__ LoadState st, st64;
-    __shared__ double sbase[NC_];
     __shared__ int qi;
     for (;;) {
         if (threadIdx.x == 0) qi = atomicAdd(b.counter, 1);
@@ -1142,7 +1186,15 @@ __global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
         const int q = qi;
         __syncthreads();
         if (q >= b.n_queue) return;
-        batch_item<T, DIM>(b, b.items[b.order[q]], b.qslot[q], st, st64, sbase, red);
+        const BatchItem& it = b.items[b.order[q]];
+        const int slot = b.qslot[q];
+        if constexpr (KIND == BATCH_SOLVE) {
+            batch_item<double, DIM>(b, it, slot, st, red, false);
+        } else if constexpr (KIND == BATCH_FP32) {
+            batch_item<float, DIM>(b, it, slot, st, red, b.phase != 0);
+        } else {
+            batch_restart64<DIM>(b, it, slot, st, st64, red);
+        }
         __syncthreads();
     }
 }
@@ -1163,27 +1215,31 @@ int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t 
 
 size_t ahom_batch_static_lds(int dim) {
     const int nc = dim == 3 ? 6 : 3;
-    return (size_t)(nc + 2) * AHOM_WG * 8 + 2 * sizeof(LoadState) + nc * 8 + 16;
+    return (size_t)(nc + 2) * AHOM_WG * 8 + 2 * sizeof(LoadState) + 16;
 }
 
-int ahom_batch_occupancy(int prec, int dim, size_t lds) {
-    int n = 0;
-    hipError_t e;
-    if (prec == 0) e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 3>, AHOM_WG, lds)
-                                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<double, 2>, AHOM_WG, lds);
-    else e = dim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 3>, AHOM_WG, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch<float, 2>, AHOM_WG, lds);
-    return e == hipSuccess ? n : 0;
-}
-
-int ahom_launch_batch(int prec, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s) {
-    if (prec == 0) {
-        if (dim == 3) hipLaunchKernelGGL((k_batch<double, 3>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
-        else hipLaunchKernelGGL((k_batch<double, 2>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
-    } else {
-        if (dim == 3) hipLaunchKernelGGL((k_batch<float, 3>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
-        else hipLaunchKernelGGL((k_batch<float, 2>), dim3(nwg), dim3(AHOM_WG), lds, s, a);
+namespace {
+template <int DIM>
+const void* batch_fn(int kind) {
+    switch (kind) {
+    case BATCH_SOLVE: return (const void*)k_batch<DIM, BATCH_SOLVE>;
+    case BATCH_FP32: return (const void*)k_batch<DIM, BATCH_FP32>;
+    default: return (const void*)k_batch<DIM, BATCH_RESTART64>;
     }
+}
+}  // namespace
+
+int ahom_batch_occupancy(int kind, int dim, size_t lds) {
+    int n = 0;
+    const void* f = dim == 3 ? batch_fn<3>(kind) : batch_fn<2>(kind);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, AHOM_WG, lds) == hipSuccess ? n : 0;
+}
+
+int ahom_launch_batch(int kind, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s) {
+    const void* f = dim == 3 ? batch_fn<3>(kind) : batch_fn<2>(kind);
+    BatchArgs arg = a;
+    void* params[] = {&arg};
+    if (hipLaunchKernel(f, dim3(nwg), dim3(AHOM_WG), params, lds, s) != hipSuccess) return -1;
     return AHOM_CHECK_LAUNCH();
 }
 
