@@ -677,8 +677,8 @@ int create_solver(ahom_pattern* p, const ahom_config* cfg, ahom_solver** out) {
     const Plan& P = p->plan;
     const size_t es = s->es();
     auto bad = [&](int code) { delete s; return code; };
-    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, s->npack + 1, (size_t)(s->ncomp + 1) * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
-    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, s->ncomp + 1, (size_t)2 * AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
+    if ((rc = choose_geom(P.ax[0].len, P.S / P.ax[0].slen, 2 * s->npack, (size_t)(s->ncomp + 1) * AHOM_WG * 8, es, s->prec, &s->g_real))) return bad(rc);
+    if ((rc = choose_geom(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, 2 * s->ncomp, (size_t)2 * AHOM_WG * 8, es, s->prec, &s->g_spec))) return bad(rc);
     for (int a = 1; a <= P.D - 2; ++a) {
         int64_t O = 1, I = 1;
         for (int b = 0; b < a; ++b) O *= P.ax[b].slen;

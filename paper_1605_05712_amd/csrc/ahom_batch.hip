@@ -192,8 +192,9 @@ struct ahom_batch {
     // per-pass tiles of a member in element size es
     void geometry(const Member& mb, size_t esz, size_t budget, PassGeo* real, PassGeo* spec, PassGeo* axis) const {
         const Plan& P = mb.plan;
-        *real = pass_geo(P.ax[0].len, P.S / P.ax[0].slen, (d == 3 ? 3 : 2) + 1, esz, budget);
-        *spec = pass_geo(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, ncomp + 1, esz, budget);
+        // LDS buffers of a tile: the fields and a ping-pong buffer of the same size
+        *real = pass_geo(P.ax[0].len, P.S / P.ax[0].slen, 2 * (d == 3 ? 3 : 2), esz, budget);
+        *spec = pass_geo(P.ax[P.D - 1].len, P.S / P.ax[P.D - 1].len, 2 * ncomp, esz, budget);
         for (int a = 1; a <= P.D - 2; ++a) {
             int64_t O = 1, I = 1;
             for (int b = 0; b < a; ++b) O *= P.ax[b].slen;
@@ -720,7 +721,7 @@ int ahom_batch_strain(ahom_batch* b, int member, int load, double* out) {
         RealArgs rb = it.ra64;
         rb.real_io = d_out;
         rb.st = b->d_st_base;
-        if (ahom_launch_real(AHOM_FP64, b->d, REAL_TO_REAL, rb, (int)it.t_real64, 1, lds, b->stream)) rc = AHOM_E_DEVICE;
+        if (ahom_launch_real(AHOM_FP64, b->d, REAL_TO_REAL, rb, (int)it.t_real64, 1, b->lds64, b->stream)) rc = AHOM_E_DEVICE;
         ra.accumulate = 1;
     }
     if (!rc && ahom_launch_real(b->prec, b->d, REAL_TO_REAL, ra, (int)it.t_real, 1, lds, b->stream)) rc = AHOM_E_DEVICE;

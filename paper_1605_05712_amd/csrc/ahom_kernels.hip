@@ -269,9 +269,14 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
     const int tid = threadIdx.x;
     const UDiv by_nc(a.NC);
 
+    // LDS: the NP packed fields (a.NC columns each, field p's column j at
+    // (p a.NC + j) CS), the Stockham ping-pong buffer of the same size (all
+    // fields are transformed in one call: one barrier per stage for all of
+    // them), the twiddle table
     C* Z = lds_base<C>();
     C* tmp = Z + NP * a.NC * CS;
-    C* twl = stage_twiddles(tmp + a.NC * CS, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+    C* twl = stage_twiddles(tmp + NP * a.NC * CS, reinterpret_cast<const C*>(a.tw) + ax.tw_off, L);
+    const int ncol_all = (NP - 1) * a.NC + ncol;   // through the last valid column of the last field
 
     int src_buf = 0;
     if (MODE == REAL_TURN) src_buf = st.iter & 1;
@@ -334,7 +339,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
             }
         }
         __syncthreads();
-        for (int p = 0; p < NP; ++p) lds_fft<+1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, twl);
+        lds_fft<+1>(Z, tmp, ncol_all, CS, ax, twl);
     }
 
     if (MODE == REAL_TO_REAL) {
@@ -435,7 +440,7 @@ __device__ void real_tile(const RealArgs& a, const LoadState& st, int load, int6
         }
     }
     __syncthreads();
-    for (int p = 0; p < NP; ++p) lds_fft<-1>(Z + p * a.NC * CS, tmp, ncol, CS, ax, twl);
+    lds_fft<-1>(Z, tmp, ncol_all, CS, ax, twl);
 
     // ---- split the packed spectra and store the half spectra
     const T scale = MODE == REAL_FROM_REAL ? (T)(1.0 / L) : (T)1;
@@ -473,7 +478,7 @@ __global__ void __launch_bounds__(AHOM_WG) k_real(RealArgs a) {
     real_tile<T, DIM, MODE, PH>(a, a.st[load], load, blockIdx.x, sig);
     if (MODE == REAL_TURN) {
         __syncthreads();
-        double* red = reinterpret_cast<double*>(lds_base<C>() + (NP + 1) * a.NC * a.CS);
+        double* red = reinterpret_cast<double*>(lds_base<C>() + 2 * NP * a.NC * a.CS);
         block_sum<NC_ + 1>(sig, red);
         if (threadIdx.x == 0) {
             for (int c = 0; c < NC_; ++c) a.sig_part[((int64_t)load * gridDim.x + blockIdx.x) * NC_ + c] = sig[c];
@@ -564,9 +569,13 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     C* base = reinterpret_cast<C*>(par ? a.buf1 : a.buf0) + (int64_t)load * NC_ * P.S;
     C* tb = reinterpret_cast<C*>(a.tbuf) + (int64_t)load * NT * P.S;
     const C* tw = reinterpret_cast<const C*>(a.tw) + ax.tw_off;
+    // LDS: the NC_ fields (field f's column j at (f a.NC + j) CS), the
+    // Stockham ping-pong buffer of the same size (all fields in one
+    // transform call), the twiddle table
     C* F = lds_base<C>();
     C* tmp = F + NC_ * a.NC * CS;
-    C* twl = stage_twiddles(tmp + a.NC * CS, tw, L);
+    C* twl = stage_twiddles(tmp + NC_ * a.NC * CS, tw, L);
+    const int ncol_all = (NC_ - 1) * a.NC + ncol;
     const UDiv by_l(L);
 
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
@@ -578,7 +587,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
         for (int f = 0; f < NC_; ++f) F[f * a.NC * CS + j * CS + l] = base[(int64_t)f * P.S + addr];
     }
     __syncthreads();
-    for (int f = 0; f < NC_; ++f) lds_fft<-1>(F + f * a.NC * CS, tmp, ncol, CS, ax, twl);
+    lds_fft<-1>(F, tmp, ncol_all, CS, ax, twl);
 
     const double* eb = a.eps_bar + (int64_t)load * NC_;
     const T inv_m = (T)(1.0 / (double)P.m);
@@ -792,7 +801,7 @@ __device__ void spec_tile(const SpecArgs& a, const LoadState& st, int load, int6
     }
     if (MODE == SPEC_INIT) return;
     __syncthreads();
-    for (int f = 0; f < NC_; ++f) lds_fft<+1>(F + f * a.NC * CS, tmp, ncol, CS, ax, twl);
+    lds_fft<+1>(F, tmp, ncol_all, CS, ax, twl);
     for (int e = tid; e < L * a.NC; e += blockDim.x) {
         int j, l;
         by_l.divmod(e, j, l);
@@ -813,7 +822,7 @@ __global__ void __launch_bounds__(AHOM_WG) k_spec(SpecArgs a) {
     spec_tile<T, DIM, MODE, PH>(a, a.st[load], load, blockIdx.x, res, cau);
     if (MODE == SPEC_INIT) return;
     double rv[2] = {res, cau};
-    block_sum<2>(rv, reinterpret_cast<double*>(lds_base<C>() + (NC_ + 1) * a.NC * a.CS));
+    block_sum<2>(rv, reinterpret_cast<double*>(lds_base<C>() + 2 * NC_ * a.NC * a.CS));
     if (threadIdx.x == 0) {
         a.res_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[0];
         if (a.cau_part) a.cau_part[(int64_t)load * gridDim.x + blockIdx.x] = rv[1];

@@ -106,6 +106,30 @@ def test_batch_group_barrier_timeout_ends_cleanly(monkeypatch):
     assert np.allclose(out["mean_stress"][ok], ref["mean_stress"][ok], rtol=1e-12, atol=0.0)
 
 
+def test_batch_fp32_strain_fields_match_fp64():
+    """FP32 + restarts to 1e-6: each item's strain field (FP64 base + FP32
+    correction, read back by ahom_batch_strain) against an FP64 batch solved
+    to 1e-10 on the same members."""
+    seeds = list(range(4100, 4108))
+    say("batch fp32 strain vs fp64", seeds)
+    B32, _ = make_batch(seeds, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000)
+    o32 = B32.solve(loads3(), allow=(ahom.AHOM_OK,))
+    assert B32.last_timing()[1] >= len(seeds)
+    B64, _ = make_batch(seeds, precision=ahom.FP64, tol=1e-10, max_iter=5000)
+    B64.solve(loads3(), allow=(ahom.AHOM_OK,))
+    worst = 0.0
+    for i in range(len(seeds)):
+        for l in range(3):
+            a = B32.strain(i, l)
+            b = B64.strain(i, l)
+            e = np.abs(a - b).max() / np.abs(b).max()
+            worst = max(worst, e)
+            assert np.all(np.isfinite(a))
+    print(f"worst strain error {worst:.2e}, FP32 iterations {int(o32['iters'].min())}..{int(o32['iters'].max())}",
+          flush=True)
+    assert worst < 1e-4
+
+
 def test_batch_graph_replays_equal_eager():
     """FP32 + restarts: three graph replays reproduce the eager launch bit for bit."""
     seeds = list(range(4100, 4116))
