@@ -41,7 +41,11 @@ struct Variant {
 };
 const Variant kVariants[] = {{8, 1}, {4, 1}, {8, 2}, {4, 2}};
 constexpr int kNumVariants = 4;
-constexpr size_t kBudget = 48 * 1024;   // dynamic LDS per workgroup for the largest tiles
+// dynamic LDS per workgroup for the largest tiles: the FP32 stage kernel runs
+// two workgroups per CU (2 x (64 KB + its 10 KB of static LDS) fit in 160 KB
+// in 2-D), the FP64 kernels one (their registers allow no more)
+constexpr size_t kBudget32 = 64 * 1024;
+constexpr size_t kBudget64 = 128 * 1024;
 constexpr int kMaxNC = 512;
 constexpr int kGroupMax = 8;            // workgroups per item at most
 constexpr int kGroupPart = 2 * kGroupMax * 8;   // doubles of an item's group partial sums
@@ -144,6 +148,14 @@ struct ahom_batch {
     double last_ms = 0.0;
 
     size_t es() const { return prec == AHOM_FP64 ? 16 : 8; }
+    // dynamic LDS for the tiles of plan variant v in precision pr (FP32: at
+    // most half the CU's LDS less the kernel's static LDS, so that two
+    // workgroups stay resident)
+    size_t tile_budget(int pr, int v) const {
+        const size_t half = 80 * 1024 - ahom_batch_static_lds(d);
+        const size_t b = pr == AHOM_FP64 ? kBudget64 : std::min(kBudget32, half & ~(size_t)1023);
+        return b / (size_t)kVariants[v].budget_div;
+    }
     bool refine_on() const { return prec == AHOM_FP32_MIXED && cfg.refine > 0.0; }
 
     void free_items() {
@@ -255,7 +267,8 @@ int ahom_batch::build_items(int n_load) {
         const Member& mb = mem[i];
         const Plan& P = mb.plan;
         const int64_t S = P.S;
-        const size_t budget = kBudget / (size_t)kVariants[mb.variant].budget_div;
+        const size_t budget = tile_budget(AHOM_FP64, mb.variant);
+        const size_t budget_main = tile_budget(prec, mb.variant);
         char* p = arena + off[q];
         auto take = [&](size_t bytes) { char* r = p; p += align256(bytes); return (void*)r; };
         void* buf0 = take((size_t)ncomp * S * es());
@@ -286,10 +299,10 @@ int ahom_batch::build_items(int n_load) {
         it.sbase = d_sbase + (size_t)q * 8;
         const double beta = (mb.lam0 + mb.mu0) / (mb.lam0 + 2.0 * mb.mu0);
         auto fill_args = [&](int pr, void* b0, void* b1, void* tb, RealArgs* ra, AxisArgs* ax, SpecArgs* sa,
-                             int64_t* t_real, int64_t* t_spec, int64_t* t_axis, size_t& lds_max) {
+                             int64_t* t_real, int64_t* t_spec, int64_t* t_axis, size_t& lds_max, size_t bud) {
             const size_t esz = pr == AHOM_FP64 ? 16 : 8;
             PassGeo gr, gs, ga[AHOM_MAX_AXES];
-            geometry(mb, esz, budget, &gr, &gs, ga);
+            geometry(mb, esz, bud, &gr, &gs, ga);
             const void* tw = pr == AHOM_FP64 ? (const void*)mb.d_tw64 : (const void*)mb.d_tw32;
             *ra = RealArgs{};
             ra->plan = mb.d_plan; ra->buf0 = b0; ra->buf1 = b1; ra->tw = tw; ra->tw64 = mb.d_tw64;
@@ -315,13 +328,13 @@ int ahom_batch::build_items(int n_load) {
             *t_spec = gs.tiles;
             lds_max = std::max(lds_max, gs.lds);
         };
-        fill_args(prec, buf0, buf1, tbuf, &it.ra, it.ax, &it.sa, &it.t_real, &it.t_spec, it.t_axis, lds_main);
+        fill_args(prec, buf0, buf1, tbuf, &it.ra, it.ax, &it.sa, &it.t_real, &it.t_spec, it.t_axis, lds_main, budget_main);
         it.sa_corr = it.sa;
         if (ref) {
             it.sa_corr.eps_bar = d_zero;
             it.sa_corr.toff = toff;
             fill_args(AHOM_FP64, b64_0, b64_1, tb64, &it.ra64, it.ax64, &it.sa64, &it.t_real64, &it.t_spec64, it.t_axis64,
-                      lds_r64);
+                      lds_r64, budget);
             it.sa64.resid_period = 1;
             it.sa64.max_iter = 1;
             it.sa64.dout = toff;
@@ -488,7 +501,7 @@ int ahom_batch::autotune() {
                 std::string err;
                 if (ahom_build_plan_ex(probe.sf, 256, kVariants[v].max_radix, &probe.plan, &err)) continue;
                 PassGeo gr, gs, ga[AHOM_MAX_AXES];
-                geometry(probe, es(), kBudget / kVariants[v].budget_div, &gr, &gs, ga);
+                geometry(probe, es(), tile_budget(prec, v), &gr, &gs, ga);
                 std::vector<int> sig = {gr.NC, gs.NC};
                 for (int a = 0; a < probe.plan.D; ++a)
                     for (int s2 = 0; s2 < probe.plan.ax[a].nstage; ++s2) sig.push_back(probe.plan.ax[a].radix[s2]);
