@@ -41,11 +41,10 @@ struct Variant {
 };
 const Variant kVariants[] = {{8, 1}, {4, 1}, {8, 2}, {4, 2}};
 constexpr int kNumVariants = 4;
-// dynamic LDS per workgroup for the largest tiles: the FP32 stage kernel runs
-// two workgroups per CU (2 x (64 KB + its 10 KB of static LDS) fit in 160 KB
-// in 2-D), the FP64 kernels one (their registers allow no more)
-constexpr size_t kBudget32 = 64 * 1024;
-constexpr size_t kBudget64 = 128 * 1024;
+// dynamic LDS per workgroup for the largest tiles (every batch kernel runs one
+// workgroup per CU: 512 threads for the FP32 stages, 256 for the FP64
+// kernels), less where the kernel's static LDS leaves less of the 160 KB
+constexpr size_t kBudget = 128 * 1024;
 constexpr int kMaxNC = 512;
 constexpr int kGroupMax = 8;            // workgroups per item at most
 constexpr int kGroupPart = 2 * kGroupMax * 8;   // doubles of an item's group partial sums
@@ -148,13 +147,11 @@ struct ahom_batch {
     double last_ms = 0.0;
 
     size_t es() const { return prec == AHOM_FP64 ? 16 : 8; }
-    // dynamic LDS for the tiles of plan variant v in precision pr (FP32: at
-    // most half the CU's LDS less the kernel's static LDS, so that two
-    // workgroups stay resident)
+    // dynamic LDS for the tiles of plan variant v in precision pr (at most
+    // the CU's LDS less the kernel's static LDS)
     size_t tile_budget(int pr, int v) const {
-        const size_t half = 80 * 1024 - ahom_batch_static_lds(d);
-        const size_t b = pr == AHOM_FP64 ? kBudget64 : std::min(kBudget32, half & ~(size_t)1023);
-        return b / (size_t)kVariants[v].budget_div;
+        const size_t rest = 160 * 1024 - ahom_batch_static_lds(d, pr == AHOM_FP64 ? AHOM_WG : kBatchWg32);
+        return std::min(kBudget, rest & ~(size_t)1023) / (size_t)kVariants[v].budget_div;
     }
     bool refine_on() const { return prec == AHOM_FP32_MIXED && cfg.refine > 0.0; }
 
@@ -344,7 +341,8 @@ int ahom_batch::build_items(int n_load) {
     kind = prec == AHOM_FP64 ? BATCH_SOLVE : BATCH_FP32;
     lds = lds_main;
     lds64 = lds_r64;
-    if (std::max(lds, lds64) + ahom_batch_static_lds(d) > 160 * 1024)
+    if (std::max(lds + ahom_batch_static_lds(d, ahom_batch_wg_size(kind)), lds64 + ahom_batch_static_lds(d, AHOM_WG)) >
+        160 * 1024)
         return bfail(AHOM_E_UNSUPPORTED_SIZE, "batch tiles exceed the LDS");
     int ncu = 256, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {

@@ -278,9 +278,14 @@ enum { BATCH_SOLVE = 0, BATCH_FP32 = 1, BATCH_RESTART64 = 2 };
 
 // queue head and group barrier counters to zero (plain kernel: safe inside a captured graph)
 int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t s);
+// threads per workgroup of the FP32 stage kernel: its 235 VGPRs allow 8
+// waves per CU, held as one workgroup so that its tiles get all of the LDS
+constexpr int kBatchWg32 = 512;
+// threads per workgroup of a batch kernel kind
+int ahom_batch_wg_size(int kind);
 int ahom_launch_batch(int kind, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s);
-// static LDS bytes of the batch kernels (reduction scratch and item state)
-size_t ahom_batch_static_lds(int dim);
+// static LDS bytes of the batch kernels (reduction scratch and item state) with wgs threads
+size_t ahom_batch_static_lds(int dim, int wgs);
 // resident workgroups per CU of a batch kernel kind with `lds` dynamic LDS bytes
 int ahom_batch_occupancy(int kind, int dim, size_t lds);
 

@@ -229,19 +229,20 @@ __device__ __forceinline__ C* stage_twiddles(C* twl, const C* __restrict__ tw, i
     return twl;
 }
 
-// block-wide sum of NV doubles per thread (fixed order); result valid in thread 0
-template <int NV>
+// block-wide sum of NV doubles per thread (fixed order) over NT threads (the
+// workgroup size, a power of two); result valid in thread 0
+template <int NV, int NT = AHOM_WG>
 __device__ void block_sum(double* vals, double* scratch) {
     const int tid = threadIdx.x;
-    for (int c = 0; c < NV; ++c) scratch[c * AHOM_WG + tid] = vals[c];
+    for (int c = 0; c < NV; ++c) scratch[c * NT + tid] = vals[c];
     __syncthreads();
-    for (int off = AHOM_WG / 2; off > 0; off >>= 1) {
+    for (int off = NT / 2; off > 0; off >>= 1) {
         if (tid < off)
-            for (int c = 0; c < NV; ++c) scratch[c * AHOM_WG + tid] += scratch[c * AHOM_WG + tid + off];
+            for (int c = 0; c < NV; ++c) scratch[c * NT + tid] += scratch[c * NT + tid + off];
         __syncthreads();
     }
     if (tid == 0)
-        for (int c = 0; c < NV; ++c) vals[c] = scratch[c * AHOM_WG];
+        for (int c = 0; c < NV; ++c) vals[c] = scratch[c * NT];
 }
 
 template <int DIM, int PH = PHYS_ELASTIC> using Comp = Fields<DIM, PH>;
@@ -961,7 +962,7 @@ __device__ void wg_zero(void* p, int64_t n_complex, int slot, int k) {
 // Iterate one item (all passes, then the FP64 reduction and loop control of
 // k_reduce) until it stops at tol, max_iter or divergence.  st is the item's
 // state in LDS; sig_base (nullable) is added to the mean stress.
-template <typename T, int DIM>
+template <typename T, int DIM, int WGS>
 __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisArgs* ax, const SpecArgs& sa,
                             int64_t t_real, int64_t t_spec, const int64_t* t_axis, LoadState& st,
                             const double* sig_base, double tol, int max_iter, int resid_period, bool record,
@@ -1001,7 +1002,7 @@ __device__ void batch_stage(const BatchItem& it, const RealArgs& ra, const AxisA
             }
             group_sync(it, phase, wait);
         }
-        block_sum<NC_ + 2>(v, red);
+        block_sum<NC_ + 2, WGS>(v, red);
         if (k > 1) {
             // the group's partial sums, combined in slot order by every member
             double* gp = it.gpart + (rround & 1) * (k * 8);
@@ -1077,7 +1078,7 @@ __device__ double item_norm0(const BatchItem& it) {
 // traction offset, mean stress = sbase + mean of the correction, to
 // max(tol, refine x the restart's residual).  Then publish the state.  One
 // call site of batch_stage serves both, so the kernel holds one copy of it.
-template <typename T, int DIM>
+template <typename T, int DIM, int WGS>
 __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, double* red, bool corr) {
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
     const int tid = threadIdx.x;
@@ -1095,7 +1096,7 @@ __device__ void batch_item(const BatchArgs& b, const BatchItem& it, int slot, Lo
     }
     const double norm0 = item_norm0<DIM>(it);
     const double stage_tol = corr ? fmax(b.tol, b.refine * st.resid) : b.refine_on ? fmax(b.tol, b.refine) : b.tol;
-    batch_stage<T, DIM>(it, it.ra, it.ax, corr ? it.sa_corr : it.sa, it.t_real, it.t_spec, it.t_axis, st,
+    batch_stage<T, DIM, WGS>(it, it.ra, it.ax, corr ? it.sa_corr : it.sa, it.t_real, it.t_spec, it.t_axis, st,
                         corr ? it.sbase : nullptr, stage_tol, b.max_iter, b.resid_period, true, red, slot, phase,
                         rround, b.group_wait, norm0);
     if (tid == 0 && slot == 0) {
@@ -1115,7 +1116,7 @@ __device__ __forceinline__ bool needs_restart(const BatchArgs& b, const LoadStat
 // base) whose traction step d becomes the offset of the correction stage
 // (written by the FP64 spectral pass), the FP32 state cleared for the
 // correction e = eps - eps_b, and the loop control of the correction stage.
-template <int DIM>
+template <int DIM, int WGS>
 __device__ void batch_restart64(const BatchArgs& b, const BatchItem& it, int slot, LoadState& st, LoadState& st64,
                                 double* red) {
     constexpr int NC_ = Comp<DIM>::N, NT = Comp<DIM>::NT;
@@ -1146,7 +1147,7 @@ __device__ void batch_restart64(const BatchArgs& b, const BatchItem& it, int slo
     if (tid == 0) st64 = LoadState{};
     const double norm0 = item_norm0<DIM>(it);
     group_sync(it, phase, b.group_wait);
-    batch_stage<double, DIM>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64, nullptr,
+    batch_stage<double, DIM, WGS>(it, it.ra64, it.ax64, it.sa64, it.t_real64, it.t_spec64, it.t_axis64, st64, nullptr,
                              -1.0, 1, 1, false, red, slot, phase, rround, b.group_wait, norm0);
     // correction stage: e(0) = 0, t(e(-1)) = -d
     if (tid == 0) {
@@ -1183,10 +1184,10 @@ __device__ void batch_restart64(const BatchArgs& b, const BatchItem& it, int slo
 // FP32 stage, 1: a correction stage) or BATCH_RESTART64 (a restart's FP64
 // step).  The FP32 solve is split over launches so that the FP32 kernel holds
 // no FP64 tile code: its registers then allow two workgroups per CU.
-template <int DIM, int KIND>
-__global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
+template <int DIM, int KIND, int WGS>
+__global__ void __launch_bounds__(WGS) k_batch(BatchArgs b) {
     constexpr int NC_ = Comp<DIM>::N;
-    __shared__ double red[(NC_ + 2) * AHOM_WG];
+    __shared__ double red[(NC_ + 2) * WGS];
     __shared__ LoadState st, st64;
     __shared__ int qi;
     for (;;) {
@@ -1198,11 +1199,11 @@ __global__ void __launch_bounds__(AHOM_WG) k_batch(BatchArgs b) {
         const BatchItem& it = b.items[b.order[q]];
         const int slot = b.qslot[q];
         if constexpr (KIND == BATCH_SOLVE) {
-            batch_item<double, DIM>(b, it, slot, st, red, false);
+            batch_item<double, DIM, WGS>(b, it, slot, st, red, false);
         } else if constexpr (KIND == BATCH_FP32) {
-            batch_item<float, DIM>(b, it, slot, st, red, b.phase != 0);
+            batch_item<float, DIM, WGS>(b, it, slot, st, red, b.phase != 0);
         } else {
-            batch_restart64<DIM>(b, it, slot, st, st64, red);
+            batch_restart64<DIM, WGS>(b, it, slot, st, st64, red);
         }
         __syncthreads();
     }
@@ -1222,33 +1223,36 @@ int ahom_launch_batch_reset(int* counter, int* gcount, int n_items, hipStream_t 
     return AHOM_CHECK_LAUNCH();
 }
 
-size_t ahom_batch_static_lds(int dim) {
+size_t ahom_batch_static_lds(int dim, int wgs) {
     const int nc = dim == 3 ? 6 : 3;
-    return (size_t)(nc + 2) * AHOM_WG * 8 + 2 * sizeof(LoadState) + 16;
+    return (size_t)(nc + 2) * wgs * 8 + 2 * sizeof(LoadState) + 16;
 }
 
 namespace {
 template <int DIM>
 const void* batch_fn(int kind) {
     switch (kind) {
-    case BATCH_SOLVE: return (const void*)k_batch<DIM, BATCH_SOLVE>;
-    case BATCH_FP32: return (const void*)k_batch<DIM, BATCH_FP32>;
-    default: return (const void*)k_batch<DIM, BATCH_RESTART64>;
+    case BATCH_SOLVE: return (const void*)k_batch<DIM, BATCH_SOLVE, AHOM_WG>;
+    case BATCH_FP32: return (const void*)k_batch<DIM, BATCH_FP32, kBatchWg32>;
+    default: return (const void*)k_batch<DIM, BATCH_RESTART64, AHOM_WG>;
     }
 }
 }  // namespace
 
+int ahom_batch_wg_size(int kind) { return kind == BATCH_FP32 ? kBatchWg32 : AHOM_WG; }
+
 int ahom_batch_occupancy(int kind, int dim, size_t lds) {
     int n = 0;
     const void* f = dim == 3 ? batch_fn<3>(kind) : batch_fn<2>(kind);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, AHOM_WG, lds) == hipSuccess ? n : 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, ahom_batch_wg_size(kind), lds) == hipSuccess ? n : 0;
 }
 
 int ahom_launch_batch(int kind, int dim, const BatchArgs& a, int nwg, size_t lds, hipStream_t s) {
+    const int wgs = ahom_batch_wg_size(kind);
     const void* f = dim == 3 ? batch_fn<3>(kind) : batch_fn<2>(kind);
     BatchArgs arg = a;
     void* params[] = {&arg};
-    if (hipLaunchKernel(f, dim3(nwg), dim3(AHOM_WG), params, lds, s) != hipSuccess) return -1;
+    if (hipLaunchKernel(f, dim3(nwg), dim3(wgs), params, lds, s) != hipSuccess) return -1;
     return AHOM_CHECK_LAUNCH();
 }
 
