@@ -73,6 +73,70 @@ def test_batch_of_3d_members_matches_oracle_after_fixed_iterations():
         assert np.allclose(out["mean_stress"][i, 0], r.mean_stress, rtol=1e-10, atol=1e-13), M
 
 
+def test_batch_of_3d_members_fp32_after_fixed_iterations():
+    """The 3-D FP32 stage kernel: the members above in FP32 (no restarts),
+    3 updates, against the FP64 oracle at an FP32 bound."""
+    Ms = [[[16, 0, 0], [4, 8, 0], [0, 0, 1]],
+          [[8, 4, 0], [-8, 4, 0], [0, 0, 1]],
+          [[6, 0, 0], [1, 5, 0], [0, 2, 4]],
+          [[8, 0, 0], [0, 8, 0], [0, 0, 8]]]
+    lame = np.array([[1.0, 0.5], [4.0, 2.0], [2.0, 3.0]])
+    rng = np.random.default_rng(31)
+    A = rng.standard_normal((3, 3))
+    eb = 0.5 * (A + A.T)
+    say("3-D batch fp32 fixed iterations", Ms)
+    B = ahom.Batch(Ms, precision=ahom.FP32_MIXED, tol=0.0, max_iter=3, refine=-1.0)
+    for i in range(len(Ms)):
+        m, _ = B.info(i)
+        B.set_material(i, lame, rnd_phase(40 + i, 3)(B.points(i), m))
+    out = B.solve(eb[None])
+    assert np.all(out["iters"] == 3)
+    worst = 0.0
+    for i, M in enumerate(Ms):
+        T = make_transform(M)
+        ph = rnd_phase(40 + i, 3)(T.points, T.m)
+        r = E.basic_scheme(M, ph, lame, E.default_reference(lame), eb, transform=T, fixed_iters=3)
+        ip = perm_between(T.points, B.points(i))
+        e_f = rel_err(B.strain(i, 0), tensors_to_fields(r.eps[:, :, ip]))
+        e_s = rel_err(out["mean_stress"][i, 0], r.mean_stress)
+        worst = max(worst, e_f, e_s)
+        assert np.allclose(B.history(i, 0), r.history, rtol=1e-4), M
+    print(f"worst FP32 field / mean-stress error {worst:.2e}", flush=True)
+    assert worst < 2e-6   # measured 1.8e-7
+
+
+def test_batch_of_3d_members_fp32_with_restarts_matches_fp64():
+    """3-D FP32 batch with restarts to 1e-6 (one member large enough to be
+    iterated by a group of workgroups): strain fields against an FP64 batch
+    at 1e-10."""
+    Ms = [[[16, 0, 0], [4, 8, 0], [0, 0, 1]],
+          [[6, 0, 0], [1, 5, 0], [0, 2, 4]],
+          [[8, 0, 0], [0, 8, 0], [0, 0, 8]],
+          [[32, 0, 0], [0, 32, 0], [0, 0, 16]]]
+    lame = np.array([[1.0, 0.5], [4.0, 2.0], [2.0, 3.0]])
+    eb = np.zeros((2, 3, 3))
+    eb[0, 0, 0] = 1.0
+    eb[1, 0, 2] = eb[1, 2, 0] = 1.0 / math.sqrt(2.0)
+    say("3-D batch fp32 restarts vs fp64", Ms)
+    Bs = []
+    for prec, tol in ((ahom.FP32_MIXED, 1e-6), (ahom.FP64, 1e-10)):
+        B = ahom.Batch(Ms, precision=prec, tol=tol, max_iter=5000)
+        for i in range(len(Ms)):
+            m, _ = B.info(i)
+            B.set_material(i, lame, rnd_phase(60 + i, 3)(B.points(i), m))
+        Bs.append((B, B.solve(eb, allow=(ahom.AHOM_OK,))))
+    (B32, o32), (B64, o64) = Bs
+    assert np.all(o32["item_status"] == 0) and np.all(o32["resid"] <= 1e-6)
+    assert B32.last_timing()[1] >= 1
+    worst = 0.0
+    for i in range(len(Ms)):
+        for l in range(2):
+            a, b = B32.strain(i, l), B64.strain(i, l)
+            worst = max(worst, np.abs(a - b).max() / np.abs(b).max())
+    print(f"worst strain error {worst:.2e}, FP32 iterations {o32['iters'].tolist()}", flush=True)
+    assert worst < 1e-4
+
+
 def sweep_members():
     names, Ms = [], []
     for j in (7, 8, 9):
