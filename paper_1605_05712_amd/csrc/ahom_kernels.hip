@@ -1183,7 +1183,8 @@ __device__ void batch_restart64(const BatchArgs& b, const BatchItem& it, int slo
 // BATCH_SOLVE (FP64 items, the whole solve), BATCH_FP32 (b.phase 0: the first
 // FP32 stage, 1: a correction stage) or BATCH_RESTART64 (a restart's FP64
 // step).  The FP32 solve is split over launches so that the FP32 kernel holds
-// no FP64 tile code: its registers then allow two workgroups per CU.
+// no FP64 tile code: its registers then allow 8 waves per CU, run as one
+// workgroup of WGS = 512 threads whose tiles get the whole LDS budget.
 template <int DIM, int KIND, int WGS>
 __global__ void __launch_bounds__(WGS) k_batch(BatchArgs b) {
     constexpr int NC_ = Comp<DIM>::N;
