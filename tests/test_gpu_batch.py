@@ -130,6 +130,27 @@ def test_batch_fp32_strain_fields_match_fp64():
     assert worst < 1e-4
 
 
+def test_batch_restart_rounds_beyond_the_graph():
+    """FP32 with restart factor 0.5 (a restart per halving of the residual):
+    the first solve runs the rounds beyond the two a graph holds from the
+    host, the next capture plans for all of them; eager and graph results
+    agree bit for bit and every item converges."""
+    seeds = list(range(4100, 4106))
+    say("batch restart rounds beyond the graph", seeds)
+    B, _ = make_batch(seeds, precision=ahom.FP32_MIXED, tol=1e-6, max_iter=5000, refine=0.5)
+    ref = B.solve(loads3(), use_graph=False, allow=(ahom.AHOM_OK,))
+    n_restart = B.last_timing()[1]
+    print("restarts", n_restart, "iterations", ref["iters"].min(), "..", ref["iters"].max(), flush=True)
+    assert n_restart > 2 * len(seeds) * 3
+    assert np.all(ref["item_status"] == 0) and np.all(ref["resid"] <= 1e-6)
+    for k in range(2):
+        out = B.solve(loads3(), use_graph=True, allow=(ahom.AHOM_OK,))
+        assert B.last_timing()[1] == n_restart, k
+        assert np.array_equal(out["iters"], ref["iters"]), k
+        assert np.array_equal(out["mean_stress"], ref["mean_stress"]), k
+        assert np.array_equal(out["resid"], ref["resid"]), k
+
+
 def test_batch_graph_replays_equal_eager():
     """FP32 + restarts: three graph replays reproduce the eager launch bit for bit."""
     seeds = list(range(4100, 4116))
