@@ -611,7 +611,10 @@ int ahom_solver::autotune(int nload) {
             FastGeom fg;
             if (!ahom_fast_geom(prec, kind, dim, L, v, &fg, phys)) continue;
             bool dup = false;
-            for (auto& o : seen) dup = dup || (o.NC == fg.NC && o.persistent == fg.persistent);
+            // same launch shape = same kernel work (the register-resident
+            // real pass can report the column count of another variant)
+            for (auto& o : seen)
+                dup = dup || (o.NC == fg.NC && o.persistent == fg.persistent && o.threads == fg.threads && o.lds == fg.lds);
             if (dup) continue;
             seen.push_back(fg);
             // the register-resident variant has neither <p, C p> sums nor the conductivity law
