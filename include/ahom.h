@@ -296,8 +296,10 @@ int ahom_solver_set_conductivity(ahom_solver* s, int n_phase, const double* k, c
 int ahom_solver_set_reference_conductivity(ahom_solver* s, double k0);
 
 /*
- * The Basic Scheme (or CG, per ahom_config.scheme) for n_load mean gradients
- * grad_bar (n_load*3 doubles, host; in 2-D the first two entries are used).
+ * The Basic Scheme (Algorithm 1, Sec. 3.2, with the scalar Green operator of
+ * the heat equation of Sec. 3; or CG, per ahom_config.scheme) for n_load mean
+ * gradients grad_bar (n_load*3 doubles, host; in 2-D the first two entries
+ * are used).
  * field_out: NULL, or n_load*d*m doubles receiving the gradient field e(n_k)
  * per load, component-major, canonical point order (host, or device memory
  * with AHOM_MEM_DEVICE).  iters, resid: as ahom_solve, with the residual
@@ -309,7 +311,8 @@ int ahom_solve_conductivity(ahom_solver* s, int n_load, const double* grad_bar, 
                             double* resid, double* mean_flux, int mem_flags);
 
 /*
- * Effective conductivity K_eff (d x d row-major): column j is <q> for the
+ * Effective conductivity K_eff (d x d row-major; the heat-equation
+ * counterpart of the effective tensor of Sec. 3.1): column j is <q> for the
  * unit mean gradient e_j (the d loads solved together).  iters: NULL or d
  * ints.  Same return codes as ahom_solve.
  */
@@ -349,8 +352,10 @@ int ahom_solver_last_restarts(const ahom_solver* s, int* n);
 int ahom_solver_pass_times(ahom_solver* s, int n_iter, double* ms, double* bytes, int cap, int* n_pass);
 
 /*
- * Per-iteration residual history r(0..n) of load k of the last solve:
- * writes up to cap doubles, *count = number written.
+ * Per-iteration residual history r(0..n) of load k of the last solve (the
+ * equilibrium residual of the stop test that replaces the Cauchy criterion
+ * of Algorithm 1, Sec. 3.2): writes up to cap doubles, *count = number
+ * written.
  */
 int ahom_solver_history(const ahom_solver* s, int load, double* hist, int cap, int* count);
 
@@ -417,7 +422,8 @@ int ahom_batch_set_material(ahom_batch* b, int member, int n_phase, const double
 int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double mu0);
 
 /*
- * The same n_load macroscopic strains (n_load*9) for every member.  Outputs
+ * Algorithm 1 (Sec. 3.2) on every member for the same n_load macroscopic
+ * strains (n_load*9).  Outputs
  * are indexed [member * n_load + load]: iters, resid, status (0 converged,
  * 1 not converged, 2 diverged, 3 invalid: a large item iterated by a group of
  * workgroups lost a member at a pass barrier), mean_stress (9 doubles each);
@@ -428,7 +434,8 @@ int ahom_batch_set_reference(ahom_batch* b, int member, double lambda0, double m
 int ahom_batch_solve(ahom_batch* b, int n_load, const double* eps_bar, int* iters, double* resid, double* mean_stress,
                      int* status, int use_graph);
 
-/* Strain field of (member, load) after a solve: c*m doubles (host), component-major. */
+/* Strain field eps(n) of Algorithm 1 (Sec. 3.2) for (member, load) after a
+ * solve: c*m doubles (host), component-major. */
 int ahom_batch_strain(ahom_batch* b, int member, int load, double* out);
 
 /* Residual history of (member, load), as ahom_solver_history. */
